@@ -1,0 +1,178 @@
+/*
+ * bitonic.h -- C interface of the MI355X (gfx950) bitonic sort library
+ * (libbitonic_mi355x.so).
+ *
+ * The library sorts 32-bit signed integer keys on one GPU with the bitonic
+ * sorting network of Mu, Cui and Song, "The implementation and optimization
+ * of Bitonic sort algorithm based on CUDA" (arXiv 1506.01446): for
+ * N = 2^k keys the network has k phases, phase r merges blocks of 2^r keys
+ * in r compare-exchange steps, k(k+1)/2 steps in all (sections 3.1-3.3).
+ * Steps whose comparators stay inside one on-chip tile run in LDS and
+ * registers (the paper's optimization 1, section 4.1); consecutive steps
+ * with longer strides are fused into one pass over HBM with the keys held in
+ * registers (optimization 2, section 4.2).
+ *
+ * Conventions shared by every entry point:
+ *  - Key and offset pointers are DEVICE pointers (hipMalloc or torch CUDA
+ *    tensors); the caller owns them.  Sorting is in place.
+ *  - `stream` is a hipStream_t (NULL = the legacy default stream).  Calls are
+ *    asynchronous: they enqueue kernels on `stream` and return; the keys are
+ *    sorted once the stream reaches that point.  The host never blocks.
+ *  - Keys compare as signed int32.  `ascending` != 0 sorts ascending,
+ *    0 descending.  The result is unique (keys only), so it is bit-exact
+ *    whatever the plan.
+ *  - n that is not a power of two is handled as if padded to N = 2^k with
+ *    INT32_MAX sentinels (section 3 assumes n = 2^k).  The sentinels are
+ *    never stored: the network is run in its "flip" arrangement (first step
+ *    of each phase compares mirror images, every comparator puts the smaller
+ *    key at the lower index), in which a comparator whose upper end is a
+ *    sentinel never moves anything, so it is skipped.
+ *  - The optimized kernels move keys in 16-byte vectors; a keys pointer that
+ *    is not 16-byte aligned is sorted with the semi plan instead (same
+ *    result, scalar accesses).
+ *  - Errors in the arguments are reported synchronously and nothing is
+ *    enqueued.  No exception crosses this interface.
+ *  - Calls are reentrant on different streams.  The segmented sort uses a
+ *    per-device scratch buffer that the library allocates on first use (or
+ *    when a larger one is needed); two segmented calls on different streams
+ *    of one device must not overlap in time.
+ */
+#ifndef BITONIC_MI355X_H
+#define BITONIC_MI355X_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum bitonic_status {
+  BITONIC_OK = 0,
+  BITONIC_EINVAL = -1,       /* bad argument (null pointer, negative size, bad plan) */
+  BITONIC_ENOMEM = -2,       /* scratch allocation failed */
+  BITONIC_ELAUNCH = -3,      /* a kernel launch failed (hipGetLastError) */
+  BITONIC_EUNSUPPORTED = -4, /* size beyond what the library handles (n > 2^31) */
+  BITONIC_EDEVICE = -5       /* no usable gfx950 device / HIP runtime error */
+};
+
+/* Text for a status code (static storage, never NULL). */
+const char* bitonic_status_string(int status);
+
+/*
+ * Sort keys[0, n) in place (sections 3.1-3.3, 4.1, 4.2).
+ *   keys       device pointer to n int32 keys (may be NULL when n <= 1)
+ *   n          number of keys, 0 <= n <= 2^31; n <= 1 enqueues nothing
+ *   ascending  nonzero: ascending; zero: descending
+ *   stream     hipStream_t to enqueue on
+ * Returns BITONIC_OK, BITONIC_EINVAL (keys NULL with n > 1, n < 0),
+ * BITONIC_EUNSUPPORTED (n > 2^31) or BITONIC_ELAUNCH.
+ */
+int bitonic_sort_i32(int32_t* keys, int64_t n, int ascending, void* stream);
+
+/*
+ * Sort every segment of a CSR table independently, in one batched launch
+ * sequence (the network of section 3 applied per segment, each segment
+ * padded virtually to its own power of two).
+ *   keys       device pointer; segment s is keys[offsets[s], offsets[s+1])
+ *   offsets    DEVICE pointer to nseg + 1 nondecreasing int64 offsets
+ *              (offsets[0] need not be 0; empty segments are allowed;
+ *              segments must not overlap and each must hold < 2^31 keys)
+ *   nseg       number of segments, >= 0; 0 enqueues nothing
+ *   ascending  as above, for every segment
+ *   stream     hipStream_t
+ * The offsets are read on the device only, so the call never blocks; bad
+ * offsets are undefined behaviour.  Returns BITONIC_OK, BITONIC_EINVAL,
+ * BITONIC_ENOMEM or BITONIC_ELAUNCH.
+ */
+int bitonic_sort_segmented_i32(int32_t* keys, const int64_t* offsets,
+                               int64_t nseg, int ascending, void* stream);
+
+/*
+ * As bitonic_sort_segmented_i32, with a host-side bound: every segment holds
+ * at most max_seg_len keys (0 = unknown).  The bound only prunes launches
+ * for merge phases no segment can reach; a segment longer than the bound is
+ * undefined behaviour.
+ */
+int bitonic_sort_segmented_bounded_i32(int32_t* keys, const int64_t* offsets,
+                                       int64_t nseg, int64_t max_seg_len,
+                                       int ascending, void* stream);
+
+/*
+ * Plans.  A plan fixes how the k(k+1)/2 steps of the network map onto
+ * kernel launches; every plan gives the same sorted keys.
+ *   BITONIC_PLAN_BASIC      one launch per step, one compare-exchange per
+ *                           thread in global memory (section 3.3)
+ *   BITONIC_PLAN_SEMI       steps whose stride fits in an LDS tile run in one
+ *                           launch per tile phase; longer strides one launch
+ *                           per step (section 4.1)
+ *   BITONIC_PLAN_OPTIMIZED  register-resident tile sort and merges, and up to
+ *                           `fuse` consecutive long-stride steps per HBM pass
+ *                           (sections 4.1 and 4.2)
+ */
+enum bitonic_plan_kind {
+  BITONIC_PLAN_AUTO = 0,
+  BITONIC_PLAN_BASIC = 1,
+  BITONIC_PLAN_SEMI = 2,
+  BITONIC_PLAN_OPTIMIZED = 3
+};
+
+typedef struct bitonic_plan {
+  int kind;       /* enum bitonic_plan_kind */
+  int tile_log2;  /* keys per on-chip tile = 2^tile_log2 (0 = library choice) */
+  int fuse;       /* max long-stride steps per HBM pass, 1..5 (0 = library choice) */
+  int reserved;   /* must be 0 */
+} bitonic_plan;
+
+/*
+ * bitonic_sort_i32 with an explicit plan (used for the section 5 ablation
+ * and by the autotuner).  plan == NULL means BITONIC_PLAN_AUTO.
+ * Returns BITONIC_EINVAL for a plan the library does not implement.
+ */
+int bitonic_sort_plan_i32(int32_t* keys, int64_t n, int ascending,
+                          const bitonic_plan* plan, void* stream);
+
+/*
+ * Run only phases 1..last_phase of the network (flip arrangement) on
+ * keys[0, n): afterwards every aligned block of 2^last_phase keys (the last
+ * one cut at n) is sorted, the state section 3.1 describes after that phase.
+ * last_phase >= log2(N) sorts fully.  For tests of intermediate states.
+ */
+int bitonic_network_phases_i32(int32_t* keys, int64_t n, int ascending,
+                               int last_phase, const bitonic_plan* plan,
+                               void* stream);
+
+/*
+ * Number of kernel launches (passes) the plan makes for n keys; -1 on a bad
+ * argument.  For n >= 2 the optimized plan makes
+ * 1 + sum over phases p > t of (ceil((p - t) / f) + 1) launches.
+ */
+int64_t bitonic_plan_passes(int64_t n, const bitonic_plan* plan);
+
+/*
+ * Tuning.  bitonic_set_tuning(tile_log2, fuse) changes the library's
+ * default plan for BITONIC_PLAN_AUTO (values as in bitonic_plan; 0 keeps the
+ * current value).  bitonic_load_tuning reads the same two values from a text
+ * file written by the autotuner ("tile_log2 <t>" and "fuse <f>" lines).
+ * Both return BITONIC_OK or BITONIC_EINVAL; they are not thread-safe with
+ * concurrent sorts.
+ */
+int bitonic_set_tuning(int tile_log2, int fuse);
+int bitonic_load_tuning(const char* path);
+
+/*
+ * Input generator (not part of the sorting method): writes
+ * out[i] = (int32)(splitmix64(seed + (start + i + 1) * 0x9E3779B97F4A7C15) >> 32)
+ * for i in [0, n), the counter-based SplitMix64 stream of Steele, Lea and
+ * Flood (2014).  Device pointer, asynchronous on `stream`.
+ */
+int bitonic_keygen_i32(int32_t* out, int64_t n, uint64_t seed, int64_t start,
+                       void* stream);
+
+/* Library version string and the gfx target it was built for. */
+const char* bitonic_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BITONIC_MI355X_H */

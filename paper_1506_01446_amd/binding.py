@@ -1,0 +1,200 @@
+"""Thin Python binding of libbitonic_mi355x.so (include/bitonic.h).
+
+Argument marshalling only: every function here has the name of the C entry
+point it calls, checks that tensors are contiguous int32 / int64 device
+tensors, passes their device pointers and the current HIP stream, and turns
+a nonzero status into :class:`BitonicError`.  All sorting work runs in the
+library's HIP kernels; there is no fallback.  If the library has not been
+built, loading it raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libbitonic_mi355x.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "bitonic.h")
+
+PLAN_KINDS = {"auto": 0, "basic": 1, "semi": 2, "optimized": 3}
+STATUS = {0: "BITONIC_OK", -1: "BITONIC_EINVAL", -2: "BITONIC_ENOMEM",
+          -3: "BITONIC_ELAUNCH", -4: "BITONIC_EUNSUPPORTED", -5: "BITONIC_EDEVICE"}
+
+
+class BitonicError(RuntimeError):
+    def __init__(self, fn: str, status: int):
+        self.status = status
+        super().__init__(f"{fn} failed: {status} ({bitonic_status_string(status)})")
+
+
+class bitonic_plan(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("tile_log2", ctypes.c_int),
+                ("fuse", ctypes.c_int), ("reserved", ctypes.c_int)]
+
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """The HIP library.  Raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(
+            f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+            "(there is no CPU fallback)")
+    lib = ctypes.CDLL(LIB_PATH)
+    i32p, i64p, vp = (ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64),
+                      ctypes.c_void_p)
+    sig = {
+        "bitonic_status_string": ([ctypes.c_int], ctypes.c_char_p),
+        "bitonic_version": ([], ctypes.c_char_p),
+        "bitonic_sort_i32": ([vp, ctypes.c_int64, ctypes.c_int, vp], ctypes.c_int),
+        "bitonic_sort_plan_i32": ([vp, ctypes.c_int64, ctypes.c_int,
+                                   ctypes.POINTER(bitonic_plan), vp], ctypes.c_int),
+        "bitonic_sort_segmented_i32": ([vp, vp, ctypes.c_int64, ctypes.c_int, vp],
+                                       ctypes.c_int),
+        "bitonic_sort_segmented_bounded_i32": ([vp, vp, ctypes.c_int64, ctypes.c_int64,
+                                               ctypes.c_int, vp], ctypes.c_int),
+        "bitonic_network_phases_i32": ([vp, ctypes.c_int64, ctypes.c_int, ctypes.c_int,
+                                        ctypes.POINTER(bitonic_plan), vp], ctypes.c_int),
+        "bitonic_plan_passes": ([ctypes.c_int64, ctypes.POINTER(bitonic_plan)],
+                                ctypes.c_int64),
+        "bitonic_set_tuning": ([ctypes.c_int, ctypes.c_int], ctypes.c_int),
+        "bitonic_load_tuning": ([ctypes.c_char_p], ctypes.c_int),
+        "bitonic_keygen_i32": ([vp, ctypes.c_int64, ctypes.c_uint64, ctypes.c_int64, vp],
+                               ctypes.c_int),
+    }
+    del i32p, i64p
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name, None)
+        if fn is None:
+            continue
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+def header_functions(path: str = HEADER) -> list[str]:
+    """Names of the functions include/bitonic.h declares."""
+    text = open(path).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(bitonic_[a-z0-9_]+)\s*\(", text)))
+
+
+def _check(fn: str, rc: int) -> None:
+    if rc != 0:
+        raise BitonicError(fn, rc)
+
+
+def _stream(stream) -> int | None:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _keys_ptr(keys, dtype_name: str = "int32"):
+    import torch
+    want = torch.int32 if dtype_name == "int32" else torch.int64
+    if not isinstance(keys, torch.Tensor):
+        raise TypeError("expected a torch tensor on the GPU")
+    if keys.dtype != want or not keys.is_cuda or not keys.is_contiguous():
+        raise ValueError(f"expected a contiguous {dtype_name} tensor on the GPU, got "
+                         f"{keys.dtype} on {keys.device} (contiguous={keys.is_contiguous()})")
+    return keys.data_ptr() if keys.numel() else None
+
+
+def _plan(plan) -> bitonic_plan | None:
+    if plan is None:
+        return None
+    if isinstance(plan, bitonic_plan):
+        return plan
+    if isinstance(plan, str):
+        plan = (plan,)
+    kind = plan[0]
+    tile = plan[1] if len(plan) > 1 else 0
+    fuse = plan[2] if len(plan) > 2 else 0
+    return bitonic_plan(PLAN_KINDS[kind] if isinstance(kind, str) else int(kind),
+                        int(tile), int(fuse), 0)
+
+
+def _plan_ref(p):
+    return ctypes.byref(p) if p is not None else None
+
+
+def bitonic_status_string(status: int) -> str:
+    return load().bitonic_status_string(int(status)).decode()
+
+
+def bitonic_version() -> str:
+    return load().bitonic_version().decode()
+
+
+def bitonic_sort_i32(keys, ascending: bool = True, stream=None) -> None:
+    """Sort a contiguous int32 GPU tensor in place (asynchronous)."""
+    ptr = _keys_ptr(keys)
+    _check("bitonic_sort_i32",
+           load().bitonic_sort_i32(ptr, keys.numel(), int(bool(ascending)), _stream(stream)))
+
+
+def bitonic_sort_plan_i32(keys, ascending: bool = True, plan=None, stream=None) -> None:
+    """bitonic_sort_i32 with an explicit plan: ("basic"|"semi"|"optimized",
+    tile_log2, fuse)."""
+    ptr = _keys_ptr(keys)
+    p = _plan(plan)
+    _check("bitonic_sort_plan_i32",
+           load().bitonic_sort_plan_i32(ptr, keys.numel(), int(bool(ascending)), _plan_ref(p),
+                                        _stream(stream)))
+
+
+def bitonic_network_phases_i32(keys, last_phase: int, ascending: bool = True, plan=None,
+                               stream=None) -> None:
+    ptr = _keys_ptr(keys)
+    p = _plan(plan)
+    _check("bitonic_network_phases_i32",
+           load().bitonic_network_phases_i32(ptr, keys.numel(), int(bool(ascending)),
+                                             int(last_phase), _plan_ref(p), _stream(stream)))
+
+
+def bitonic_sort_segmented_i32(keys, offsets, ascending: bool = True, stream=None,
+                               max_seg_len: int | None = None) -> None:
+    """Sort every CSR segment of ``keys`` (int64 ``offsets`` on the GPU)."""
+    kp = _keys_ptr(keys)
+    op = _keys_ptr(offsets, "int64")
+    nseg = max(offsets.numel() - 1, 0)
+    if max_seg_len is None:
+        _check("bitonic_sort_segmented_i32",
+               load().bitonic_sort_segmented_i32(kp, op, nseg, int(bool(ascending)),
+                                                 _stream(stream)))
+    else:
+        _check("bitonic_sort_segmented_bounded_i32",
+               load().bitonic_sort_segmented_bounded_i32(kp, op, nseg, int(max_seg_len),
+                                                         int(bool(ascending)),
+                                                         _stream(stream)))
+
+
+def bitonic_plan_passes(n: int, plan=None) -> int:
+    p = _plan(plan)
+    return int(load().bitonic_plan_passes(int(n), _plan_ref(p)))
+
+
+def bitonic_set_tuning(tile_log2: int = 0, fuse: int = 0) -> None:
+    _check("bitonic_set_tuning", load().bitonic_set_tuning(int(tile_log2), int(fuse)))
+
+
+def bitonic_load_tuning(path: str) -> None:
+    _check("bitonic_load_tuning", load().bitonic_load_tuning(path.encode()))
+
+
+def bitonic_keygen_i32(out, seed: int, start: int = 0, stream=None) -> None:
+    """Fill an int32 GPU tensor with the SplitMix64 key stream ``seed``."""
+    ptr = _keys_ptr(out)
+    _check("bitonic_keygen_i32",
+           load().bitonic_keygen_i32(ptr, out.numel(), int(seed) & (2**64 - 1), int(start),
+                                     _stream(stream)))

@@ -1,0 +1,287 @@
+// Planner and C interface of the single-array sort (include/bitonic.h).
+//
+// The planner maps the k(k+1)/2 steps of the network for N = 2^k keys
+// (sections 3.2, 3.3) onto kernel launches, all enqueued on the caller's
+// stream with no host synchronisation:
+//   optimized: one tile sort (phases 1..t), then for each phase p > t the
+//              p - t long-stride steps in ceil((p - t) / f) fused HBM passes
+//              followed by one tile merge (strides 2^(t-1)..1);
+//   semi:      LDS tile network for phases 1..t, one launch per long-stride
+//              step, one LDS tail per phase (section 4.1 alone);
+//   basic:     one launch per step (section 3.3).
+#include <atomic>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+
+#include "../../include/bitonic.h"
+#include "launch.hpp"
+#include "segmented.hpp"
+
+namespace bitonic {
+
+static std::atomic<int> g_tile_log2{13};
+static std::atomic<int> g_fuse{4};
+
+struct Resolved {
+  int kind;
+  int tile;
+  int fuse;
+};
+
+static int resolve(const bitonic_plan* plan, Resolved* r) {
+  r->kind = BITONIC_PLAN_OPTIMIZED;
+  r->tile = g_tile_log2.load();
+  r->fuse = g_fuse.load();
+  if (plan) {
+    if (plan->reserved != 0) return BITONIC_EINVAL;
+    if (plan->kind < BITONIC_PLAN_AUTO || plan->kind > BITONIC_PLAN_OPTIMIZED) return BITONIC_EINVAL;
+    if (plan->kind != BITONIC_PLAN_AUTO) r->kind = plan->kind;
+    if (plan->tile_log2) r->tile = plan->tile_log2;
+    if (plan->fuse) r->fuse = plan->fuse;
+  }
+  if (r->kind == BITONIC_PLAN_SEMI) {
+    if (!plan || !plan->tile_log2) r->tile = 12;
+    if (r->tile < 1 || r->tile > kLdsNetworkMaxLog2) return BITONIC_EINVAL;
+  }
+  if (r->kind == BITONIC_PLAN_OPTIMIZED && !tile_log2_supported(r->tile)) return BITONIC_EINVAL;
+  if (r->fuse < 1 || r->fuse > kFuseMax) return BITONIC_EINVAL;
+  return BITONIC_OK;
+}
+
+static int ceil_log2(int64_t n) {
+  int k = 0;
+  while ((int64_t(1) << k) < n) ++k;
+  return k;
+}
+
+// Enqueue (or, with st == nullptr and count_only, just count) the launches
+// for phases 1..K of the network over keys[0, n).
+static int64_t enqueue_plain(int32_t* keys, uint32_t n, int K, int32_t flip, const Resolved& r,
+                             hipStream_t st, bool count_only) {
+  const int k = ceil_log2(n);
+  const uint32_t N = (k >= 32) ? 0u : (1u << k);
+  int64_t launches = 0;
+  if (K > k) K = k;
+  if (K <= 0) return 0;
+
+  if (r.kind == BITONIC_PLAN_BASIC) {
+    for (int p = 1; p <= K; ++p)
+      for (int sb = p - 1; sb >= 0; --sb) {
+        if (!count_only) launch_step(sb, sb == p - 1, keys, n, N, flip, st);
+        ++launches;
+      }
+    return launches;
+  }
+
+  if (r.kind == BITONIC_PLAN_SEMI) {
+    const int L = K < r.tile ? K : r.tile;
+    if (!count_only) launch_lds_network(L, 1, L, false, keys, n, flip, st);
+    ++launches;
+    for (int p = L + 1; p <= K; ++p) {
+      for (int sb = p - 1; sb >= L; --sb) {
+        if (!count_only) launch_step(sb, sb == p - 1, keys, n, N, flip, st);
+        ++launches;
+      }
+      if (!count_only) launch_lds_network(L, 0, 0, true, keys, n, flip, st);
+      ++launches;
+    }
+    return launches;
+  }
+
+  // optimized
+  if (K <= r.tile) {
+    if (K < kTileMinLog2) {
+      if (!count_only) launch_lds_network(K, 1, K, false, keys, n, flip, st);
+    } else {
+      if (!count_only) launch_tile(K, 0, keys, n, flip, st);
+    }
+    return 1;
+  }
+  const int L = r.tile;
+  if (!count_only) launch_tile(L, 0, keys, n, flip, st);
+  ++launches;
+  for (int p = L + 1; p <= K; ++p) {
+    const int nb = p - L;                          // long-stride steps
+    const int npass = (nb + r.fuse - 1) / r.fuse;  // fused HBM passes
+    int top = p - 1;
+    for (int i = 0; i < npass; ++i) {
+      const int left = top - L + 1;                // bits still to do
+      const int passes_left = npass - i;
+      const int f = (left + passes_left - 1) / passes_left;
+      const int q = top - f + 1;
+      if (!count_only) launch_global_pass(f, i == 0, keys, n, q, flip, st);
+      ++launches;
+      top = q - 1;
+    }
+    if (!count_only) launch_tile(L, 1, keys, n, flip, st);
+    ++launches;
+  }
+  return launches;
+}
+
+// The optimized kernels move keys in 16-byte vectors, which needs a 16-byte
+// aligned base; other pointers take the semi plan (scalar accesses).
+static void fit_alignment(const int32_t* keys, Resolved* r) {
+  if (r->kind == BITONIC_PLAN_OPTIMIZED && (reinterpret_cast<uintptr_t>(keys) & 15u) != 0) {
+    r->kind = BITONIC_PLAN_SEMI;
+    r->tile = 12;
+  }
+}
+
+static int check_sort_args(int32_t* keys, int64_t n) {
+  if (n < 0) return BITONIC_EINVAL;
+  if (n > (int64_t(1) << 31)) return BITONIC_EUNSUPPORTED;
+  if (n > 1 && keys == nullptr) return BITONIC_EINVAL;
+  return BITONIC_OK;
+}
+
+static int finish_launches() {
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? BITONIC_OK : BITONIC_ELAUNCH;
+}
+
+// Per-device scratch of the segmented sort, allocated on first use and kept
+// until the process ends.
+constexpr int kMaxDevices = 64;
+struct DeviceState {
+  uint32_t* counter = nullptr;
+  int cus = 0;
+};
+static DeviceState g_dev[kMaxDevices];
+static std::mutex g_dev_mu;
+
+static int device_state(DeviceState** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return BITONIC_EDEVICE;
+  std::lock_guard<std::mutex> lock(g_dev_mu);
+  DeviceState& d = g_dev[dev];
+  if (!d.counter) {
+    void* p = nullptr;
+    if (hipMalloc(&p, 256) != hipSuccess) return BITONIC_ENOMEM;
+    d.counter = static_cast<uint32_t*>(p);
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus <= 0)
+      cus = 256;
+    d.cus = cus;
+  }
+  *out = &d;
+  return BITONIC_OK;
+}
+
+}  // namespace bitonic
+
+using namespace bitonic;
+
+extern "C" {
+
+const char* bitonic_status_string(int status) {
+  switch (status) {
+    case BITONIC_OK: return "ok";
+    case BITONIC_EINVAL: return "invalid argument";
+    case BITONIC_ENOMEM: return "out of device memory";
+    case BITONIC_ELAUNCH: return "kernel launch failed";
+    case BITONIC_EUNSUPPORTED: return "unsupported size";
+    case BITONIC_EDEVICE: return "device error";
+    default: return "unknown status";
+  }
+}
+
+const char* bitonic_version(void) { return "bitonic_mi355x 0.1 (gfx950)"; }
+
+int bitonic_sort_plan_i32(int32_t* keys, int64_t n, int ascending, const bitonic_plan* plan,
+                          void* stream) {
+  int rc = check_sort_args(keys, n);
+  if (rc) return rc;
+  Resolved r;
+  rc = resolve(plan, &r);
+  if (rc) return rc;
+  if (n <= 1) return BITONIC_OK;
+  fit_alignment(keys, &r);
+  (void)hipGetLastError();
+  enqueue_plain(keys, (uint32_t)n, 64, ascending ? 0 : -1, r, (hipStream_t)stream, false);
+  return finish_launches();
+}
+
+int bitonic_sort_i32(int32_t* keys, int64_t n, int ascending, void* stream) {
+  return bitonic_sort_plan_i32(keys, n, ascending, nullptr, stream);
+}
+
+int bitonic_network_phases_i32(int32_t* keys, int64_t n, int ascending, int last_phase,
+                               const bitonic_plan* plan, void* stream) {
+  int rc = check_sort_args(keys, n);
+  if (rc) return rc;
+  if (last_phase < 1) return BITONIC_EINVAL;
+  Resolved r;
+  rc = resolve(plan, &r);
+  if (rc) return rc;
+  if (n <= 1) return BITONIC_OK;
+  fit_alignment(keys, &r);
+  (void)hipGetLastError();
+  enqueue_plain(keys, (uint32_t)n, last_phase, ascending ? 0 : -1, r, (hipStream_t)stream, false);
+  return finish_launches();
+}
+
+int64_t bitonic_plan_passes(int64_t n, const bitonic_plan* plan) {
+  if (n < 0 || n > (int64_t(1) << 31)) return -1;
+  Resolved r;
+  if (resolve(plan, &r)) return -1;
+  if (n <= 1) return 0;
+  return enqueue_plain(nullptr, (uint32_t)n, 64, 0, r, nullptr, true);
+}
+
+int bitonic_set_tuning(int tile_log2, int fuse) {
+  if (tile_log2 && !tile_log2_supported(tile_log2)) return BITONIC_EINVAL;
+  if (fuse && (fuse < 1 || fuse > kFuseMax)) return BITONIC_EINVAL;
+  if (tile_log2) g_tile_log2.store(tile_log2);
+  if (fuse) g_fuse.store(fuse);
+  return BITONIC_OK;
+}
+
+int bitonic_load_tuning(const char* path) {
+  if (!path) return BITONIC_EINVAL;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return BITONIC_EINVAL;
+  int tile = 0, fuse = 0;
+  char key[64];
+  int val;
+  while (std::fscanf(f, "%63s %d", key, &val) == 2) {
+    if (!std::strcmp(key, "tile_log2")) tile = val;
+    else if (!std::strcmp(key, "fuse")) fuse = val;
+  }
+  std::fclose(f);
+  return bitonic_set_tuning(tile, fuse);
+}
+
+int bitonic_sort_segmented_bounded_i32(int32_t* keys, const int64_t* offsets, int64_t nseg,
+                                       int64_t max_seg_len, int ascending, void* stream) {
+  if (nseg < 0 || max_seg_len < 0) return BITONIC_EINVAL;
+  if (nseg >= (int64_t(1) << 31)) return BITONIC_EUNSUPPORTED;
+  if (max_seg_len > (int64_t(1) << 31)) return BITONIC_EUNSUPPORTED;
+  if (nseg == 0) return BITONIC_OK;
+  if (keys == nullptr || offsets == nullptr) return BITONIC_EINVAL;
+  DeviceState* d = nullptr;
+  int rc = device_state(&d);
+  if (rc) return rc;
+  (void)hipGetLastError();
+  const int64_t grid = (int64_t)d->cus * 4 < nseg ? (int64_t)d->cus * 4 : nseg;
+  launch_segmented(keys, offsets, nseg, ascending ? 0 : -1, d->counter, (int)grid,
+                   (hipStream_t)stream);
+  return finish_launches();
+}
+
+int bitonic_sort_segmented_i32(int32_t* keys, const int64_t* offsets, int64_t nseg,
+                               int ascending, void* stream) {
+  return bitonic_sort_segmented_bounded_i32(keys, offsets, nseg, 0, ascending, stream);
+}
+
+int bitonic_keygen_i32(int32_t* out, int64_t n, uint64_t seed, int64_t start, void* stream) {
+  if (n < 0 || start < 0 || (n > 0 && out == nullptr)) return BITONIC_EINVAL;
+  if (n == 0) return BITONIC_OK;
+  (void)hipGetLastError();
+  launch_keygen(out, (uint64_t)n, seed, (uint64_t)start, (hipStream_t)stream);
+  return finish_launches();
+}
+
+}  // extern "C"

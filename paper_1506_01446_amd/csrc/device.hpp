@@ -1,0 +1,186 @@
+// Device-side building blocks shared by the plain and segmented kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <type_traits>
+
+#include "program.hpp"
+
+namespace bitonic {
+
+// Sentinel in the sorting domain.  Keys are sorted ascending after an XOR
+// with `flip` (0 for ascending, -1 for descending: ~x reverses signed order),
+// so the absent padding keys are always INT32_MAX there.
+constexpr int32_t kPad = 0x7FFFFFFF;
+
+template <int B, int E, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    static_for<B + 1, E>(f);
+  }
+}
+
+// Compare-exchange: a takes the minimum, b the maximum.
+__device__ __forceinline__ void cmpx(int32_t& a, int32_t& b) {
+  const int32_t lo = min(a, b);
+  const int32_t hi = max(a, b);
+  a = lo;
+  b = hi;
+}
+
+// Spread the low bits of t over the set bits of MASK (lowest first).
+template <uint32_t MASK>
+__device__ __forceinline__ uint32_t deposit(uint32_t t) {
+  uint32_t out = 0;
+  static_for<0, 32>([&](auto B) {
+    constexpr int b = B;
+    if constexpr ((MASK >> b) & 1u) {
+      constexpr int k = __builtin_popcount(MASK & ((1u << b) - 1u));
+      out |= ((t >> k) & 1u) << b;
+    }
+  });
+  return out;
+}
+
+// LDS address swizzle: XOR bits 5..9 of the index into bits 0..4, so that
+// thread layouts whose lanes step through index bits 5..9 spread over the
+// banks.  A bijection on every aligned block of 1024 indices.
+__device__ __forceinline__ uint32_t swz(uint32_t i) { return i ^ ((i >> 5) & 31u); }
+
+// Program of a tile kernel, as a type.
+template <int L_, int R_LOG_, int KIND_>
+struct Prog {
+  static constexpr int L = L_;
+  static constexpr int RL = R_LOG_;
+  static constexpr int R = 1 << R_LOG_;
+  static constexpr int NT = 1 << (L_ - R_LOG_);
+  static constexpr int T = 1 << L_;
+  static constexpr Program value =
+      KIND_ == 0 ? make_tile_sort(L_, R_LOG_) : make_tile_merge(L_, R_LOG_);
+  static_assert(value.ngroups <= kMaxGroups, "program too long");
+};
+
+// All compare-exchange steps of group G on the registers.
+template <class PR, int G>
+__device__ __forceinline__ void group_steps(int32_t (&x)[PR::R]) {
+  constexpr Group gr = PR::value.g[G];
+  static_for<0, gr.nsteps>([&](auto S) {
+    constexpr uint32_t D = gr.d[S];
+    static_for<0, PR::R>([&](auto J) {
+      constexpr uint32_t j = J;
+      constexpr uint32_t jj = j ^ D;
+      if constexpr (j < jj) {
+        if constexpr (slot_is_lower(gr, j, D)) {
+          cmpx(x[j], x[jj]);
+        } else {
+          cmpx(x[jj], x[j]);
+        }
+      }
+    });
+  });
+}
+
+// Move the registers from the layout of group GA to that of group GB
+// through LDS.  Begins with a barrier so the LDS is free to overwrite.
+template <class PR, int GA, int GB>
+__device__ __forceinline__ void regroup(int32_t (&x)[PR::R], int32_t* lds, uint32_t tid) {
+  constexpr Group A = PR::value.g[GA];
+  constexpr Group B = PR::value.g[GB];
+  const uint32_t ba = deposit<free_mask(A, PR::L)>(tid);
+  const uint32_t bb = deposit<free_mask(B, PR::L)>(tid);
+  __syncthreads();
+  static_for<0, PR::R>([&](auto J) {
+    constexpr uint32_t o = goff(A, J);
+    lds[swz(ba ^ o)] = x[J];
+  });
+  __syncthreads();
+  static_for<0, PR::R>([&](auto J) {
+    constexpr uint32_t o = goff(B, J);
+    x[J] = lds[swz(bb ^ o)];
+  });
+}
+
+template <class PR, int G>
+__device__ __forceinline__ void run_from(int32_t (&x)[PR::R], int32_t* lds, uint32_t tid) {
+  group_steps<PR, G>(x);
+  if constexpr (G + 1 < PR::value.ngroups) {
+    regroup<PR, G, G + 1>(x, lds, tid);
+    run_from<PR, G + 1>(x, lds, tid);
+  }
+}
+
+// Load the thread's keys of a tile in the layout of group G.
+// `valid` keys of the tile exist; the rest read as the sentinel.
+template <class PR, int G>
+__device__ __forceinline__ void load_tile(int32_t (&x)[PR::R], const int32_t* __restrict__ tile,
+                                          uint32_t valid, int32_t flip, uint32_t tid) {
+  constexpr Group gr = PR::value.g[G];
+  const uint32_t base = deposit<free_mask(gr, PR::L)>(tid);
+  if (valid >= (uint32_t)PR::T) {
+    if constexpr (layout_is_vector4(gr)) {
+      static_for<0, PR::R / 4>([&](auto Q) {
+        constexpr uint32_t o = goff(gr, 4u * Q);
+        const int4 v = *reinterpret_cast<const int4*>(tile + ((base ^ o) & ~3u));
+        const int32_t e[4] = {v.x, v.y, v.z, v.w};
+        static_for<0, 4>([&](auto C) {
+          x[4 * Q + C] = e[(o ^ C) & 3u] ^ flip;
+        });
+      });
+    } else {
+      static_for<0, PR::R>([&](auto J) {
+        constexpr uint32_t o = goff(gr, J);
+        x[J] = tile[base ^ o] ^ flip;
+      });
+    }
+  } else {
+    static_for<0, PR::R>([&](auto J) {
+      constexpr uint32_t o = goff(gr, J);
+      const uint32_t i = base ^ o;
+      x[J] = i < valid ? (tile[i] ^ flip) : kPad;
+    });
+  }
+}
+
+template <class PR, int G>
+__device__ __forceinline__ void store_tile(const int32_t (&x)[PR::R], int32_t* __restrict__ tile,
+                                           uint32_t valid, int32_t flip, uint32_t tid) {
+  constexpr Group gr = PR::value.g[G];
+  const uint32_t base = deposit<free_mask(gr, PR::L)>(tid);
+  if (valid >= (uint32_t)PR::T) {
+    if constexpr (layout_is_vector4(gr)) {
+      static_for<0, PR::R / 4>([&](auto Q) {
+        constexpr uint32_t o = goff(gr, 4u * Q);
+        int32_t e[4];
+        static_for<0, 4>([&](auto C) { e[(o ^ C) & 3u] = x[4 * Q + C] ^ flip; });
+        *reinterpret_cast<int4*>(tile + ((base ^ o) & ~3u)) = make_int4(e[0], e[1], e[2], e[3]);
+      });
+    } else {
+      static_for<0, PR::R>([&](auto J) {
+        constexpr uint32_t o = goff(gr, J);
+        tile[base ^ o] = x[J] ^ flip;
+      });
+    }
+  } else {
+    static_for<0, PR::R>([&](auto J) {
+      constexpr uint32_t o = goff(gr, J);
+      const uint32_t i = base ^ o;
+      if (i < valid) tile[i] = x[J] ^ flip;
+    });
+  }
+}
+
+// Sort (KIND 0) or merge (KIND 1) one tile that starts at `tile` and holds
+// `valid` real keys.  All threads of the block must call it.
+template <class PR>
+__device__ __forceinline__ void tile_program(int32_t* __restrict__ tile, uint32_t valid,
+                                             int32_t flip, int32_t* lds, uint32_t tid) {
+  int32_t x[PR::R];
+  load_tile<PR, 0>(x, tile, valid, flip, tid);
+  run_from<PR, 0>(x, lds, tid);
+  store_tile<PR, PR::value.ngroups - 1>(x, tile, valid, flip, tid);
+}
+
+}  // namespace bitonic

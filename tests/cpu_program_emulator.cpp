@@ -1,0 +1,128 @@
+// CPU emulation of the tile programs of the HIP library (program.hpp), for
+// host-side tests: runs a tile through the same layouts, register steps and
+// LDS regroupings the tile kernels perform, one simulated thread at a time,
+// and counts LDS bank conflicts of the regroupings.  It includes only the
+// library's program description, never the oracle.
+#include <stdint.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "../paper_1506_01446_amd/csrc/program.hpp"
+
+using namespace bitonic;
+
+static uint32_t deposit_rt(uint32_t mask, uint32_t t) {
+  uint32_t out = 0;
+  int k = 0;
+  for (int b = 0; b < 32; ++b)
+    if ((mask >> b) & 1u) {
+      out |= ((t >> k) & 1u) << b;
+      ++k;
+    }
+  return out;
+}
+
+static uint32_t swz(uint32_t i) { return i ^ ((i >> 5) & 31u); }
+
+static Program make(int L, int r, int kind) {
+  return kind == 0 ? make_tile_sort(L, r) : make_tile_merge(L, r);
+}
+
+extern "C" {
+
+// Returns the number of compare-exchange steps performed, or -1 on error
+// (e.g. an LDS regrouping that is not a permutation).
+int emulate_tile(int L, int r, int kind, int32_t* tile, uint32_t valid) {
+  const Program P = make(L, r, kind);
+  const uint32_t T = 1u << L, NT = 1u << (L - r), R = 1u << r;
+  const int32_t PAD = 0x7FFFFFFF;
+  std::vector<int32_t> x(size_t(NT) * R);
+  {
+    const Group& G = P.g[0];
+    for (uint32_t t = 0; t < NT; ++t) {
+      const uint32_t base = deposit_rt(free_mask(G, L), t);
+      for (uint32_t j = 0; j < R; ++j) {
+        const uint32_t i = base ^ goff(G, j);
+        if (i >= T) return -1;
+        x[t * R + j] = i < valid ? tile[i] : PAD;
+      }
+    }
+  }
+  int steps = 0;
+  std::vector<int32_t> lds(T);
+  std::vector<int> hit(T);
+  for (int g = 0; g < P.ngroups; ++g) {
+    const Group& G = P.g[g];
+    if (g > 0) {
+      const Group& A = P.g[g - 1];
+      std::fill(hit.begin(), hit.end(), 0);
+      for (uint32_t t = 0; t < NT; ++t) {
+        const uint32_t ba = deposit_rt(free_mask(A, L), t);
+        for (uint32_t j = 0; j < R; ++j) {
+          const uint32_t a = swz(ba ^ goff(A, j));
+          if (a >= T) return -1;
+          lds[a] = x[t * R + j];
+          hit[a]++;
+        }
+      }
+      for (uint32_t a = 0; a < T; ++a)
+        if (hit[a] != 1) return -1;
+      for (uint32_t t = 0; t < NT; ++t) {
+        const uint32_t bb = deposit_rt(free_mask(G, L), t);
+        for (uint32_t j = 0; j < R; ++j) x[t * R + j] = lds[swz(bb ^ goff(G, j))];
+      }
+    }
+    for (int s = 0; s < G.nsteps; ++s) {
+      const uint32_t D = G.d[s];
+      for (uint32_t t = 0; t < NT; ++t)
+        for (uint32_t j = 0; j < R; ++j) {
+          const uint32_t jj = j ^ D;
+          if (j >= jj) continue;
+          int32_t& lo = slot_is_lower(G, j, D) ? x[t * R + j] : x[t * R + jj];
+          int32_t& hi = slot_is_lower(G, j, D) ? x[t * R + jj] : x[t * R + j];
+          const int32_t a = std::min(lo, hi), b = std::max(lo, hi);
+          lo = a;
+          hi = b;
+        }
+      ++steps;
+    }
+  }
+  {
+    const Group& G = P.g[P.ngroups - 1];
+    for (uint32_t t = 0; t < NT; ++t) {
+      const uint32_t base = deposit_rt(free_mask(G, L), t);
+      for (uint32_t j = 0; j < R; ++j) {
+        const uint32_t i = base ^ goff(G, j);
+        if (i < valid) tile[i] = x[t * R + j];
+      }
+    }
+  }
+  return steps;
+}
+
+// Worst number of lanes of one half-wave (32 lanes) that hit the same LDS
+// bank (of `banks`) in any 32-bit access of any regrouping of the program.
+int worst_bank_conflict(int L, int r, int kind, int banks) {
+  const Program P = make(L, r, kind);
+  const uint32_t NT = 1u << (L - r), R = 1u << r;
+  int worst = 0;
+  for (int g = 1; g < P.ngroups; ++g) {
+    for (int side = 0; side < 2; ++side) {
+      const Group& G = side == 0 ? P.g[g - 1] : P.g[g];
+      for (uint32_t w0 = 0; w0 < NT; w0 += 32)
+        for (uint32_t j = 0; j < R; ++j) {
+          std::vector<int> cnt(banks, 0);
+          for (uint32_t t = w0; t < w0 + 32 && t < NT; ++t) {
+            const uint32_t a = swz(deposit_rt(free_mask(G, L), t) ^ goff(G, j));
+            worst = std::max(worst, ++cnt[a % banks]);
+          }
+        }
+    }
+  }
+  return worst;
+}
+
+int program_groups(int L, int r, int kind) { return make(L, r, kind).ngroups; }
+
+}  // extern "C"

@@ -1,0 +1,94 @@
+"""The C-ABI library loads and exports every function include/bitonic.h
+declares; argument errors come back synchronously; the plan's launch counts
+follow the closed forms of sections 3.2-4.2.  No GPU is touched: only calls
+that fail argument checks or only count launches are made."""
+import ctypes
+
+import pytest
+
+from paper_1506_01446_amd import binding as B
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return B.load()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = B.header_functions()
+    assert "bitonic_sort_i32" in names and "bitonic_sort_segmented_i32" in names
+    missing = [n for n in names if getattr(lib, n, None) is None]
+    assert not missing, missing
+
+
+def test_status_strings(lib):
+    for code in B.STATUS:
+        assert B.bitonic_status_string(code)
+    assert B.bitonic_status_string(12345) == "unknown status"
+    assert "gfx950" in B.bitonic_version()
+
+
+def test_argument_errors_are_synchronous(lib):
+    assert lib.bitonic_sort_i32(None, -1, 1, None) == -1
+    assert lib.bitonic_sort_i32(None, 5, 1, None) == -1
+    assert lib.bitonic_sort_i32(None, 2**31 + 1, 1, None) == -4
+    assert lib.bitonic_sort_i32(None, 0, 1, None) == 0
+    assert lib.bitonic_sort_i32(None, 1, 0, None) == 0
+    bad = B.bitonic_plan(9, 0, 0, 0)
+    assert lib.bitonic_sort_plan_i32(None, 0, 1, ctypes.byref(bad), None) == -1
+    bad = B.bitonic_plan(3, 17, 0, 0)
+    assert lib.bitonic_sort_plan_i32(None, 0, 1, ctypes.byref(bad), None) == -1
+    bad = B.bitonic_plan(3, 13, 9, 0)
+    assert lib.bitonic_sort_plan_i32(None, 0, 1, ctypes.byref(bad), None) == -1
+    bad = B.bitonic_plan(3, 13, 4, 1)
+    assert lib.bitonic_sort_plan_i32(None, 0, 1, ctypes.byref(bad), None) == -1
+    assert lib.bitonic_network_phases_i32(None, 4, 1, 0, None, None) == -1
+    assert lib.bitonic_sort_segmented_i32(None, None, -1, 1, None) == -1
+    assert lib.bitonic_sort_segmented_i32(None, None, 0, 1, None) == 0
+    assert lib.bitonic_sort_segmented_i32(None, None, 3, 1, None) == -1
+    assert lib.bitonic_sort_segmented_bounded_i32(None, None, 3, -1, 1, None) == -1
+    assert lib.bitonic_keygen_i32(None, -1, 0, 0, None) == -1
+    assert lib.bitonic_set_tuning(99, 0) == -1
+    assert lib.bitonic_set_tuning(0, 6) == -1
+    assert lib.bitonic_load_tuning(b"/nonexistent/tuning.txt") == -1
+
+
+def _closed_form_optimized(k, t, f):
+    if k <= 1:
+        return k
+    if k <= t:
+        return 1
+    return 1 + sum(-(-(p - t) // f) + 1 for p in range(t + 1, k + 1))
+
+
+@pytest.mark.parametrize("t", [11, 12, 13])
+@pytest.mark.parametrize("f", [1, 2, 3, 4, 5])
+def test_optimized_pass_count(lib, t, f):
+    for k in range(1, 32):
+        n = 2**k
+        got = B.bitonic_plan_passes(n, ("optimized", t, f))
+        assert got == _closed_form_optimized(k, t, f), (k, t, f)
+        # a non-power-of-two n makes the launches of its padded size
+        if k >= 2:
+            assert B.bitonic_plan_passes(n - 1, ("optimized", t, f)) == got
+
+
+def test_basic_plan_is_one_launch_per_round(lib):
+    # section 3.3: N = 2^k keys need k(k+1)/2 rounds, one kernel each
+    for k in range(1, 32):
+        assert B.bitonic_plan_passes(2**k, "basic") == k * (k + 1) // 2
+
+
+def test_semi_plan_counts(lib):
+    for t in (8, 12):
+        for k in range(1, 28):
+            L = min(k, t)
+            want = 1 + sum((p - L) + 1 for p in range(L + 1, k + 1))
+            assert B.bitonic_plan_passes(2**k, ("semi", t)) == want
+
+
+def test_headline_pass_count(lib):
+    # n = 2^24 with 2^13-key tiles and up to 4 fused steps per HBM pass
+    assert B.bitonic_plan_passes(2**24, ("optimized", 13, 4)) == 33
+    assert B.bitonic_plan_passes(0) == 0 and B.bitonic_plan_passes(1) == 0
+    assert B.bitonic_plan_passes(-1) == -1

@@ -1,0 +1,201 @@
+"""GPU parity: the HIP path through the C-ABI against the CPU oracle.
+
+Keys-only sorting has a unique answer, so every comparison is bit-exact
+(tolerance 0).  Inputs come from the seeded generators; expected values come
+from the oracle only.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import oracle as O  # noqa: E402
+from paper_1506_01446_amd import binding as B  # noqa: E402
+from paper_1506_01446_amd import workloads as W  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+SIZES = [0, 1, 2, 3, 4, 5, 7, 8, 9, 15, 16, 17, 31, 33, 63, 64, 65, 127, 129, 255, 256,
+         257, 1000, 1023, 1024, 1025, 2047, 2048, 2049, 4095, 4096, 4097, 8191, 8192, 8193,
+         16383, 16385, 32768, 65535, 65536, 65537, 100003, 131075, 262144, 300001]
+PLANS = [("basic",), ("semi", 8), ("semi", 12)] + \
+        [("optimized", t, f) for t in (11, 12, 13) for f in (1, 2, 3, 4, 5)]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    B.load()
+    print(f"[gpu] {torch.cuda.get_device_name(0)} lib={B.bitonic_version()}", flush=True)
+
+
+def gpu_sort(keys, ascending=True, plan=None):
+    t = torch.from_numpy(np.ascontiguousarray(keys, dtype=np.int32)).cuda()
+    if plan is None:
+        B.bitonic_sort_i32(t, ascending)
+    else:
+        B.bitonic_sort_plan_i32(t, ascending, plan)
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def test_headline_small_config():
+    """n = 2^16 uniform int32, ascending, default plan."""
+    keys = W.uniform_i32(W.SEED_BASE + 1, 2**16)
+    want = O.sort_i32(keys, True)
+    net, _, _ = O.bitonic_i32(keys, True, O.FLIP_VIRTUAL)
+    assert (want == net).all()
+    for rep in range(5):  # repeated: an LDS race would show as a mismatch
+        assert np.array_equal(gpu_sort(keys, True), want), rep
+
+
+@pytest.mark.parametrize("plan", PLANS, ids=lambda p: "-".join(map(str, p)))
+def test_sizes_and_plans(plan):
+    for n in SIZES:
+        keys = W.uniform_i32(W.SEED_BASE + 7 * n + 3, n)
+        for asc in (True, False):
+            print(f"[case] plan={plan} n={n} asc={asc}", flush=True)
+            got = gpu_sort(keys, asc, plan)
+            assert np.array_equal(got, O.sort_i32(keys, asc)), (plan, n, asc)
+
+
+@pytest.mark.parametrize("kind", W.KINDS)
+def test_distributions(kind):
+    n = (1 << 20) + 12345
+    keys = W.make_keys(kind, W.SEED_BASE + 10, n)
+    for asc in (True, False):
+        assert np.array_equal(gpu_sort(keys, asc), O.sort_i32(keys, asc)), (kind, asc)
+
+
+def test_signed_extremes():
+    n = 50000
+    keys = W.uniform_i32(5, n)
+    keys[::7] = 2**31 - 1
+    keys[3::11] = -2**31
+    keys[5::13] = -1
+    for asc in (True, False):
+        for plan in (None, ("basic",), ("semi", 12)):
+            assert np.array_equal(gpu_sort(keys, asc, plan), O.sort_i32(keys, asc))
+
+
+@pytest.mark.parametrize("plan", [("optimized", 11, 2), ("optimized", 13, 4), ("semi", 9),
+                                  ("basic",)], ids=lambda p: "-".join(map(str, p)))
+def test_per_phase_states(plan):
+    """After phase p the GPU state equals the oracle network's state after
+    phase p (every aligned 2^p block sorted), for every p."""
+    n = (1 << 16) + 4321
+    keys = W.uniform_i32(77, n)
+    states = {}
+    O.bitonic_i32(keys, True, O.FLIP_VIRTUAL,
+                  hook=lambda p, s, x: states.__setitem__(p, x) if s == p else None)
+    for p in sorted(states):
+        t = torch.from_numpy(keys.copy()).cuda()
+        B.bitonic_network_phases_i32(t, p, True, plan)
+        torch.cuda.synchronize()
+        assert np.array_equal(t.cpu().numpy(), states[p]), (plan, p)
+
+
+def test_guard_bands():
+    n = 300001
+    keys = W.uniform_i32(9, n)
+    canary = np.int32(0x5AFE5AFE)
+    buf = torch.full((n + 2048,), int(canary), dtype=torch.int32, device="cuda")
+    buf[1024:1024 + n] = torch.from_numpy(keys).cuda()
+    for asc in (True, False):
+        B.bitonic_sort_i32(buf[1024:1024 + n], asc)
+        torch.cuda.synchronize()
+        h = buf.cpu().numpy()
+        assert (h[:1024] == canary).all() and (h[1024 + n:] == canary).all()
+        assert np.array_equal(h[1024:1024 + n], O.sort_i32(keys, asc))
+
+
+def test_keygen_matches_host_generator():
+    for seed, start, n in ((1, 0, 1000), (W.SEED_BASE + 2, 12345, 70001), (2**63 + 5, 7, 33)):
+        t = torch.empty(n, dtype=torch.int32, device="cuda")
+        B.bitonic_keygen_i32(t, seed, start)
+        torch.cuda.synchronize()
+        assert np.array_equal(t.cpu().numpy(), W.uniform_i32(seed, n, start=start))
+
+
+# -- full-size configurations ------------------------------------------------------
+
+def _full_check(keys, asc, want_asc):
+    got = gpu_sort(keys, asc)
+    want = want_asc if asc else want_asc[::-1]
+    assert np.array_equal(got, want)
+
+
+def test_config_2_full_size():
+    """n = 2^24 and n = 10,000,000 uniform, ascending (and descending)."""
+    for n, seed in ((1 << 24, W.SEED_BASE + 2), (10_000_000, W.SEED_BASE + 3)):
+        keys = W.uniform_i32(seed, n)
+        want = O.sort_i32(keys, True)
+        print(f"[case] config2 n={n}", flush=True)
+        _full_check(keys, True, want)
+        _full_check(keys, False, want)
+
+
+@pytest.mark.parametrize("kind", W.KINDS)
+def test_config_3_full_size(kind):
+    """n = 2^26 per distribution, both directions, bit-exact vs the oracle."""
+    n = 1 << 26
+    keys = W.make_keys(kind, W.SEED_BASE + 10 + W.KINDS.index(kind), n)
+    want = O.sort_i32(keys, True)
+    print(f"[case] config3 kind={kind}", flush=True)
+    _full_check(keys, True, want)
+    _full_check(keys, False, want)
+
+
+# -- segmented --------------------------------------------------------------------
+
+def gpu_sort_segmented(keys, off, asc=True, max_seg_len=None):
+    t = torch.from_numpy(np.ascontiguousarray(keys, dtype=np.int32)).cuda()
+    o = torch.from_numpy(np.ascontiguousarray(off, dtype=np.int64)).cuda()
+    B.bitonic_sort_segmented_i32(t, o, asc, max_seg_len=max_seg_len)
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def test_segmented_edge_lengths():
+    lens = np.array([0, 1, 2, 3, 0, 5, 64, 255, 256, 257, 8191, 8192, 8193, 0, 16384,
+                     16385, 65536, 65537, 100003, 1, 0], dtype=np.int64)
+    off = W.offsets_from_lengths(lens) + 17   # offsets[0] != 0
+    keys = W.uniform_i32(31, int(off[-1]) + 5)
+    for asc in (True, False):
+        got = gpu_sort_segmented(keys, off, asc)
+        want = keys.copy()
+        want[off[0]:off[-1]] = O.sort_segmented_i32(keys[off[0]:off[-1]], off - off[0], asc)
+        assert np.array_equal(got, want), asc
+
+
+def test_segmented_zero_one_principle():
+    """Every 0-1 input of length n <= 16, all in one segmented call."""
+    segs = []
+    for n in range(1, 17):
+        codes = np.arange(2**n, dtype=np.int64)
+        segs.append(((codes[:, None] >> np.arange(n)) & 1).astype(np.int32).ravel())
+    lens = np.concatenate([np.full(2**n, n, dtype=np.int64) for n in range(1, 17)])
+    keys = np.concatenate(segs)
+    off = W.offsets_from_lengths(lens)
+    for asc in (True, False):
+        got = gpu_sort_segmented(keys, off, asc)
+        assert np.array_equal(got, O.sort_segmented_i32(keys, off, asc)), asc
+
+
+def test_segmented_config_4():
+    """8192 arrays of length round(2^u), u ~ U[0, 16], uniform keys."""
+    keys, off = W.batched_workload()
+    for asc in (True, False):
+        got = gpu_sort_segmented(keys, off, asc)
+        assert np.array_equal(got, O.sort_segmented_i32(keys, off, asc)), asc
+
+
+def test_segmented_equals_looped():
+    keys, off = W.batched_workload(nseg=300, seed=5, max_log2=15)
+    batched = gpu_sort_segmented(keys, off, True)
+    t = torch.from_numpy(keys.copy()).cuda()
+    for s in range(len(off) - 1):
+        B.bitonic_sort_i32(t[off[s]:off[s + 1]], True)
+    torch.cuda.synchronize()
+    assert np.array_equal(batched, t.cpu().numpy())

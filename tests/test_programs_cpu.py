@@ -1,0 +1,88 @@
+"""Host-side checks of the tile programs the HIP kernels are generated from.
+
+The tile kernels are compile-time programs (program.hpp): register layouts,
+compare-exchange steps and LDS regroupings.  A CPU emulator runs a tile
+through the same program; the result must be the sorted tile (tile sort) or
+the merged tile (tile merge), with absent keys past ``valid`` left alone.
+Expected values come from numpy's sort, not from the library.
+"""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+from paper_1506_01446_amd import workloads as W
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+@pytest.fixture(scope="module")
+def emu(tmp_path_factory):
+    out = str(tmp_path_factory.mktemp("emu") / "libemu.so")
+    subprocess.run(["g++", "-O2", "-std=c++20", "-shared", "-fPIC", "-o", out,
+                    os.path.join(HERE, "cpu_program_emulator.cpp")], check=True)
+    lib = ctypes.CDLL(out)
+    lib.emulate_tile.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                 ctypes.POINTER(ctypes.c_int32), ctypes.c_uint32]
+    lib.emulate_tile.restype = ctypes.c_int
+    lib.worst_bank_conflict.argtypes = [ctypes.c_int] * 4
+    lib.worst_bank_conflict.restype = ctypes.c_int
+    lib.program_groups.argtypes = [ctypes.c_int] * 3
+    lib.program_groups.restype = ctypes.c_int
+    return lib
+
+
+def _run(emu, L, r, kind, tile, valid):
+    x = np.ascontiguousarray(tile, dtype=np.int32).copy()
+    steps = emu.emulate_tile(L, r, kind, x.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), valid)
+    assert steps >= 0, "program is not a permutation of the tile"
+    return x, steps
+
+
+@pytest.mark.parametrize("L", [11, 12, 13])
+def test_tile_sort_program(emu, L):
+    T = 1 << L
+    for seed in range(3):
+        keys = W.uniform_i32(seed, T)
+        out, steps = _run(emu, L, 5, 0, keys, T)
+        assert steps == L * (L + 1) // 2
+        assert (out == np.sort(keys)).all()
+    for kind in ("sorted", "reverse", "distinct16", "equal"):
+        keys = W.make_keys(kind, 7, T)
+        out, _ = _run(emu, L, 5, 0, keys, T)
+        assert (out == np.sort(keys)).all()
+
+
+@pytest.mark.parametrize("L", [11, 13])
+def test_tile_sort_partial(emu, L):
+    T = 1 << L
+    for valid in (1, 2, 3, 100, T // 2 + 1, T - 1):
+        keys = W.uniform_i32(valid, T)
+        out, _ = _run(emu, L, 5, 0, keys, valid)
+        assert (out[:valid] == np.sort(keys[:valid])).all()
+        assert (out[valid:] == keys[valid:]).all()
+
+
+@pytest.mark.parametrize("L", [11, 12, 13])
+def test_tile_merge_program(emu, L):
+    """The merge tail sorts any tile whose halves at every level were left
+    in the state a long-stride pass leaves: here, a bitonic tile (ascending
+    then descending) -- a half-cleaner cascade sorts exactly those."""
+    T = 1 << L
+    for seed in range(3):
+        keys = W.uniform_i32(seed + 10, T)
+        cut = int(W.uniform_i32(seed + 20, 1)[0]) % T
+        bit = np.concatenate([np.sort(keys[:cut]), np.sort(keys[cut:])[::-1]])
+        out, steps = _run(emu, L, 5, 1, bit, T)
+        assert steps == L
+        assert (out == np.sort(keys)).all()
+
+
+@pytest.mark.parametrize("L", [11, 12, 13])
+@pytest.mark.parametrize("kind", [0, 1])
+def test_lds_bank_conflicts(emu, L, kind):
+    # no half-wave access of any regrouping puts two lanes on one bank
+    assert emu.worst_bank_conflict(L, 5, kind, 32) == 1
+    assert emu.worst_bank_conflict(L, 5, kind, 64) == 1
