@@ -117,10 +117,16 @@ enum bitonic_plan_kind {
 };
 
 typedef struct bitonic_plan {
-  int kind;       /* enum bitonic_plan_kind */
-  int tile_log2;  /* keys per on-chip tile = 2^tile_log2 (0 = library choice) */
-  int fuse;       /* max long-stride steps per HBM pass, 1..5 (0 = library choice) */
-  int reserved;   /* must be 0 */
+  int kind;                /* enum bitonic_plan_kind */
+  int tile_log2;           /* keys per on-chip tile = 2^tile_log2, 11..13 for
+                              the optimized plan, 1..13 for semi (0 = library
+                              choice) */
+  int fuse;                /* max long-stride steps per HBM pass, 1..5
+                              (0 = library choice, 5) */
+  int merge_blocks_per_cu; /* tile-merge workgroups per compute unit, 1..16,
+                              each looping over its tiles with the next
+                              tile's loads in flight; -1 = one tile per
+                              workgroup (0 = library choice) */
 } bitonic_plan;
 
 /*
@@ -142,21 +148,61 @@ int bitonic_network_phases_i32(int32_t* keys, int64_t n, int ascending,
                                void* stream);
 
 /*
- * Number of kernel launches (passes) the plan makes for n keys; -1 on a bad
- * argument.  For n >= 2 the optimized plan makes
- * 1 + sum over phases p > t of (ceil((p - t) / f) + 1) launches.
+ * Number of passes the plan makes over the keys for n keys (each pass reads
+ * and writes every key once); -1 on a bad argument.  For n >= 2 the
+ * optimized plan makes 1 + sum over phases p > t of (ceil((p - t) / f) + 1)
+ * passes.  A long-stride pass over a non-power-of-two n may run as two
+ * kernels: one over the 2^(q+f)-key blocks wholly below n, one over the
+ * block that straddles n.
  */
 int64_t bitonic_plan_passes(int64_t n, const bitonic_plan* plan);
 
 /*
- * Tuning.  bitonic_set_tuning(tile_log2, fuse) changes the library's
- * default plan for BITONIC_PLAN_AUTO (values as in bitonic_plan; 0 keeps the
- * current value).  bitonic_load_tuning reads the same two values from a text
- * file written by the autotuner ("tile_log2 <t>" and "fuse <f>" lines).
- * Both return BITONIC_OK or BITONIC_EINVAL; they are not thread-safe with
- * concurrent sorts.
+ * Launch description, for measurement.  For each launch i of the plan for n
+ * keys (i < cap) writes kinds[i] (enum bitonic_launch_kind) and fuse[i] (the
+ * number of network steps a global pass fuses, 1 for a step launch, else
+ * 0); either array may be NULL.  Returns the number of launches, -1 on a bad
+ * argument.
  */
-int bitonic_set_tuning(int tile_log2, int fuse);
+enum bitonic_launch_kind {
+  BITONIC_LAUNCH_TILE_SORT = 1,   /* phases 1..t on every tile (one HBM pass) */
+  BITONIC_LAUNCH_GLOBAL_PASS = 2, /* fused long-stride steps (one HBM pass) */
+  BITONIC_LAUNCH_TILE_MERGE = 3,  /* strides 2^(t-1)..1 on every tile (one HBM pass) */
+  BITONIC_LAUNCH_LDS_NETWORK = 4, /* LDS network on tiles (one HBM pass) */
+  BITONIC_LAUNCH_STEP = 5         /* one step in global memory (one HBM pass) */
+};
+
+int64_t bitonic_plan_describe(int64_t n, const bitonic_plan* plan, int32_t* kinds,
+                              int32_t* fuse, int64_t cap);
+
+/*
+ * bitonic_sort_plan_i32 that also records HIP events on `stream`:
+ * events[0] before the first launch and events[i + 1] right after launch i
+ * (for i + 1 < nevents).  `events` is an array of hipEvent_t created by the
+ * caller.  Used to time every kernel of a sort on the device.
+ */
+int bitonic_sort_plan_events_i32(int32_t* keys, int64_t n, int ascending,
+                                 const bitonic_plan* plan, void** events,
+                                 int64_t nevents, void* stream);
+
+/*
+ * Enqueue only launches [first, first + count) of the plan for n keys (the
+ * order of bitonic_plan_describe).  Running a subset leaves the keys in an
+ * intermediate state; it exists to time single kernels on the device.
+ */
+int bitonic_sort_plan_launches_i32(int32_t* keys, int64_t n, int ascending,
+                                   const bitonic_plan* plan, int64_t first,
+                                   int64_t count, void* stream);
+
+/*
+ * Tuning.  bitonic_set_tuning(tile_log2, fuse, merge_blocks_per_cu) changes
+ * the library's default plan for BITONIC_PLAN_AUTO (values as in
+ * bitonic_plan; 0 keeps the current value).  bitonic_load_tuning reads the
+ * same values from a text file written by the autotuner ("tile_log2 <t>",
+ * "fuse <f>", "merge_blocks_per_cu <b>" lines).  Both return BITONIC_OK or
+ * BITONIC_EINVAL; they are not thread-safe with concurrent sorts.
+ */
+int bitonic_set_tuning(int tile_log2, int fuse, int merge_blocks_per_cu);
 int bitonic_load_tuning(const char* path);
 
 /*

@@ -30,7 +30,7 @@ class BitonicError(RuntimeError):
 
 class bitonic_plan(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int), ("tile_log2", ctypes.c_int),
-                ("fuse", ctypes.c_int), ("reserved", ctypes.c_int)]
+                ("fuse", ctypes.c_int), ("merge_blocks_per_cu", ctypes.c_int)]
 
 
 _lib = None
@@ -46,8 +46,7 @@ def load() -> ctypes.CDLL:
             f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
             "(there is no CPU fallback)")
     lib = ctypes.CDLL(LIB_PATH)
-    i32p, i64p, vp = (ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64),
-                      ctypes.c_void_p)
+    vp = ctypes.c_void_p
     sig = {
         "bitonic_status_string": ([ctypes.c_int], ctypes.c_char_p),
         "bitonic_version": ([], ctypes.c_char_p),
@@ -62,12 +61,19 @@ def load() -> ctypes.CDLL:
                                         ctypes.POINTER(bitonic_plan), vp], ctypes.c_int),
         "bitonic_plan_passes": ([ctypes.c_int64, ctypes.POINTER(bitonic_plan)],
                                 ctypes.c_int64),
-        "bitonic_set_tuning": ([ctypes.c_int, ctypes.c_int], ctypes.c_int),
+        "bitonic_set_tuning": ([ctypes.c_int, ctypes.c_int, ctypes.c_int], ctypes.c_int),
         "bitonic_load_tuning": ([ctypes.c_char_p], ctypes.c_int),
         "bitonic_keygen_i32": ([vp, ctypes.c_int64, ctypes.c_uint64, ctypes.c_int64, vp],
                                ctypes.c_int),
+        "bitonic_plan_describe": ([ctypes.c_int64, ctypes.POINTER(bitonic_plan), vp, vp,
+                                   ctypes.c_int64], ctypes.c_int64),
+        "bitonic_sort_plan_launches_i32": ([vp, ctypes.c_int64, ctypes.c_int,
+                                            ctypes.POINTER(bitonic_plan), ctypes.c_int64,
+                                            ctypes.c_int64, vp], ctypes.c_int),
+        "bitonic_sort_plan_events_i32": ([vp, ctypes.c_int64, ctypes.c_int,
+                                          ctypes.POINTER(bitonic_plan), vp, ctypes.c_int64,
+                                          vp], ctypes.c_int),
     }
-    del i32p, i64p
     for name, (args, res) in sig.items():
         fn = getattr(lib, name, None)
         if fn is None:
@@ -120,8 +126,9 @@ def _plan(plan) -> bitonic_plan | None:
     kind = plan[0]
     tile = plan[1] if len(plan) > 1 else 0
     fuse = plan[2] if len(plan) > 2 else 0
+    bpc = plan[3] if len(plan) > 3 else 0
     return bitonic_plan(PLAN_KINDS[kind] if isinstance(kind, str) else int(kind),
-                        int(tile), int(fuse), 0)
+                        int(tile), int(fuse), int(bpc))
 
 
 def _plan_ref(p):
@@ -184,8 +191,79 @@ def bitonic_plan_passes(n: int, plan=None) -> int:
     return int(load().bitonic_plan_passes(int(n), _plan_ref(p)))
 
 
-def bitonic_set_tuning(tile_log2: int = 0, fuse: int = 0) -> None:
-    _check("bitonic_set_tuning", load().bitonic_set_tuning(int(tile_log2), int(fuse)))
+LAUNCH_KINDS = {1: "tile_sort", 2: "global_pass", 3: "tile_merge", 4: "lds_network",
+                5: "step"}
+
+
+def bitonic_plan_describe(n: int, plan=None) -> list[tuple[str, int]]:
+    """[(launch kind, fused steps)] for every launch of the plan for n keys."""
+    import numpy as np
+    p = _plan(plan)
+    m = int(load().bitonic_plan_describe(int(n), _plan_ref(p), None, None, 0))
+    if m < 0:
+        raise BitonicError("bitonic_plan_describe", m)
+    kinds = np.zeros(max(m, 1), np.int32)
+    fuse = np.zeros(max(m, 1), np.int32)
+    load().bitonic_plan_describe(int(n), _plan_ref(p), kinds.ctypes.data, fuse.ctypes.data, m)
+    return [(LAUNCH_KINDS[int(k)], int(f)) for k, f in zip(kinds[:m], fuse[:m])]
+
+
+class HipEvents:
+    """A set of HIP events (created through the HIP runtime) for timing."""
+
+    def __init__(self, count: int):
+        self.rt = ctypes.CDLL("libamdhip64.so")
+        self.rt.hipEventCreate.argtypes = [ctypes.POINTER(ctypes.c_void_p)]
+        self.rt.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float),
+                                                ctypes.c_void_p, ctypes.c_void_p]
+        self.rt.hipEventSynchronize.argtypes = [ctypes.c_void_p]
+        self.rt.hipEventDestroy.argtypes = [ctypes.c_void_p]
+        self.ev = (ctypes.c_void_p * count)()
+        for i in range(count):
+            e = ctypes.c_void_p()
+            if self.rt.hipEventCreate(ctypes.byref(e)) != 0:
+                raise RuntimeError("hipEventCreate failed")
+            self.ev[i] = e
+        self.count = count
+
+    def elapsed_ms(self, a: int, b: int) -> float:
+        self.rt.hipEventSynchronize(self.ev[b])
+        ms = ctypes.c_float()
+        if self.rt.hipEventElapsedTime(ctypes.byref(ms), self.ev[a], self.ev[b]) != 0:
+            raise RuntimeError("hipEventElapsedTime failed")
+        return float(ms.value)
+
+    def close(self):
+        for i in range(self.count):
+            self.rt.hipEventDestroy(self.ev[i])
+        self.count = 0
+
+
+def bitonic_sort_plan_events_i32(keys, events: HipEvents, ascending: bool = True, plan=None,
+                                 stream=None) -> None:
+    """Sort recording events[0] before and events[i + 1] after launch i."""
+    ptr = _keys_ptr(keys)
+    p = _plan(plan)
+    _check("bitonic_sort_plan_events_i32",
+           load().bitonic_sort_plan_events_i32(ptr, keys.numel(), int(bool(ascending)),
+                                               _plan_ref(p), ctypes.cast(events.ev, ctypes.c_void_p),
+                                               events.count, _stream(stream)))
+
+
+def bitonic_sort_plan_launches_i32(keys, first: int, count: int, ascending: bool = True,
+                                   plan=None, stream=None) -> None:
+    """Enqueue launches [first, first + count) of the plan only (timing)."""
+    ptr = _keys_ptr(keys)
+    p = _plan(plan)
+    _check("bitonic_sort_plan_launches_i32",
+           load().bitonic_sort_plan_launches_i32(ptr, keys.numel(), int(bool(ascending)),
+                                                 _plan_ref(p), int(first), int(count),
+                                                 _stream(stream)))
+
+
+def bitonic_set_tuning(tile_log2: int = 0, fuse: int = 0, merge_blocks_per_cu: int = 0) -> None:
+    _check("bitonic_set_tuning", load().bitonic_set_tuning(int(tile_log2), int(fuse),
+                                                           int(merge_blocks_per_cu)))
 
 
 def bitonic_load_tuning(path: str) -> None:

@@ -10,35 +10,43 @@
 //              step, one LDS tail per phase (section 4.1 alone);
 //   basic:     one launch per step (section 3.3).
 #include <atomic>
+#include <climits>
 #include <cstdio>
 #include <cstring>
 #include <mutex>
 
-#include "../../include/bitonic.h"
+#include "bitonic.h"
 #include "launch.hpp"
 #include "segmented.hpp"
 
 namespace bitonic {
 
 static std::atomic<int> g_tile_log2{13};
-static std::atomic<int> g_fuse{4};
+static std::atomic<int> g_fuse{5};
+static std::atomic<int> g_merge_bpc{0};  // 0: one tile per workgroup
 
 struct Resolved {
   int kind;
   int tile;
   int fuse;
+  int merge_bpc;          // tile-merge workgroups per compute unit
+  uint32_t merge_blocks;  // merge_bpc x compute units (set when enqueueing)
 };
 
 static int resolve(const bitonic_plan* plan, Resolved* r) {
   r->kind = BITONIC_PLAN_OPTIMIZED;
   r->tile = g_tile_log2.load();
   r->fuse = g_fuse.load();
+  r->merge_bpc = g_merge_bpc.load();
+  r->merge_blocks = 0;
   if (plan) {
-    if (plan->reserved != 0) return BITONIC_EINVAL;
     if (plan->kind < BITONIC_PLAN_AUTO || plan->kind > BITONIC_PLAN_OPTIMIZED) return BITONIC_EINVAL;
+    if (plan->merge_blocks_per_cu < -1 || plan->merge_blocks_per_cu > 16) return BITONIC_EINVAL;
     if (plan->kind != BITONIC_PLAN_AUTO) r->kind = plan->kind;
     if (plan->tile_log2) r->tile = plan->tile_log2;
     if (plan->fuse) r->fuse = plan->fuse;
+    if (plan->merge_blocks_per_cu > 0) r->merge_bpc = plan->merge_blocks_per_cu;
+    if (plan->merge_blocks_per_cu < 0) r->merge_bpc = 0;
   }
   if (r->kind == BITONIC_PLAN_SEMI) {
     if (!plan || !plan->tile_log2) r->tile = 12;
@@ -55,52 +63,74 @@ static int ceil_log2(int64_t n) {
   return k;
 }
 
-// Enqueue (or, with st == nullptr and count_only, just count) the launches
-// for phases 1..K of the network over keys[0, n).
+// Receives every launch of a plan as it is enqueued (or counted).
+struct Observer {
+  int32_t* kinds = nullptr;   // launch kind per launch (bitonic_launch_kind)
+  int32_t* fuse = nullptr;    // fused steps per launch (global passes), else 0
+  int64_t cap = 0;
+  hipEvent_t* events = nullptr;  // events[i + 1] recorded after launch i
+  int64_t nevents = 0;
+  int64_t first = 0;             // only launches [first, first + count) run
+  int64_t count = INT64_MAX;
+};
+
+// Enqueue (or, with count_only, just count) the launches for phases 1..K of
+// the network over keys[0, n).
 static int64_t enqueue_plain(int32_t* keys, uint32_t n, int K, int32_t flip, const Resolved& r,
-                             hipStream_t st, bool count_only) {
+                             hipStream_t st, bool count_only, Observer* obs = nullptr) {
   const int k = ceil_log2(n);
   const uint32_t N = (k >= 32) ? 0u : (1u << k);
   int64_t launches = 0;
   if (K > k) K = k;
   if (K <= 0) return 0;
+  auto emit = [&](int kind, int f, auto&& launch) {
+    const bool selected =
+        !obs || (launches >= obs->first && launches - obs->first < obs->count);
+    if (!count_only && selected) launch();
+    if (obs) {
+      if (launches < obs->cap) {
+        if (obs->kinds) obs->kinds[launches] = kind;
+        if (obs->fuse) obs->fuse[launches] = f;
+      }
+      if (!count_only && obs->events && launches + 1 < obs->nevents)
+        (void)hipEventRecord(obs->events[launches + 1], st);
+    }
+    ++launches;
+  };
+  if (obs && !count_only && obs->events && obs->nevents > 0)
+    (void)hipEventRecord(obs->events[0], st);
 
   if (r.kind == BITONIC_PLAN_BASIC) {
     for (int p = 1; p <= K; ++p)
-      for (int sb = p - 1; sb >= 0; --sb) {
-        if (!count_only) launch_step(sb, sb == p - 1, keys, n, N, flip, st);
-        ++launches;
-      }
+      for (int sb = p - 1; sb >= 0; --sb)
+        emit(BITONIC_LAUNCH_STEP, 1, [&] { launch_step(sb, sb == p - 1, keys, n, N, flip, st); });
     return launches;
   }
 
   if (r.kind == BITONIC_PLAN_SEMI) {
     const int L = K < r.tile ? K : r.tile;
-    if (!count_only) launch_lds_network(L, 1, L, false, keys, n, flip, st);
-    ++launches;
+    emit(BITONIC_LAUNCH_LDS_NETWORK, 0,
+         [&] { launch_lds_network(L, 1, L, false, keys, n, flip, st); });
     for (int p = L + 1; p <= K; ++p) {
-      for (int sb = p - 1; sb >= L; --sb) {
-        if (!count_only) launch_step(sb, sb == p - 1, keys, n, N, flip, st);
-        ++launches;
-      }
-      if (!count_only) launch_lds_network(L, 0, 0, true, keys, n, flip, st);
-      ++launches;
+      for (int sb = p - 1; sb >= L; --sb)
+        emit(BITONIC_LAUNCH_STEP, 1, [&] { launch_step(sb, sb == p - 1, keys, n, N, flip, st); });
+      emit(BITONIC_LAUNCH_LDS_NETWORK, 0,
+           [&] { launch_lds_network(L, 0, 0, true, keys, n, flip, st); });
     }
     return launches;
   }
 
   // optimized
   if (K <= r.tile) {
-    if (K < kTileMinLog2) {
-      if (!count_only) launch_lds_network(K, 1, K, false, keys, n, flip, st);
-    } else {
-      if (!count_only) launch_tile(K, 0, keys, n, flip, st);
-    }
-    return 1;
+    if (K < kTileMinLog2)
+      emit(BITONIC_LAUNCH_LDS_NETWORK, 0,
+           [&] { launch_lds_network(K, 1, K, false, keys, n, flip, st); });
+    else
+      emit(BITONIC_LAUNCH_TILE_SORT, 0, [&] { launch_tile(K, 0, keys, n, flip, 0, st); });
+    return launches;
   }
   const int L = r.tile;
-  if (!count_only) launch_tile(L, 0, keys, n, flip, st);
-  ++launches;
+  emit(BITONIC_LAUNCH_TILE_SORT, 0, [&] { launch_tile(L, 0, keys, n, flip, 0, st); });
   for (int p = L + 1; p <= K; ++p) {
     const int nb = p - L;                          // long-stride steps
     const int npass = (nb + r.fuse - 1) / r.fuse;  // fused HBM passes
@@ -110,12 +140,11 @@ static int64_t enqueue_plain(int32_t* keys, uint32_t n, int K, int32_t flip, con
       const int passes_left = npass - i;
       const int f = (left + passes_left - 1) / passes_left;
       const int q = top - f + 1;
-      if (!count_only) launch_global_pass(f, i == 0, keys, n, q, flip, st);
-      ++launches;
+      emit(BITONIC_LAUNCH_GLOBAL_PASS, f,
+           [&] { launch_global_pass(f, i == 0, keys, n, q, flip, st); });
       top = q - 1;
     }
-    if (!count_only) launch_tile(L, 1, keys, n, flip, st);
-    ++launches;
+    emit(BITONIC_LAUNCH_TILE_MERGE, 0, [&] { launch_tile(L, 1, keys, n, flip, r.merge_blocks, st); });
   }
   return launches;
 }
@@ -141,32 +170,48 @@ static int finish_launches() {
   return e == hipSuccess ? BITONIC_OK : BITONIC_ELAUNCH;
 }
 
-// Per-device scratch of the segmented sort, allocated on first use and kept
-// until the process ends.
+// Per-device state: compute-unit count and the segmented sort's scratch,
+// created on first use and kept until the process ends.
 constexpr int kMaxDevices = 64;
 struct DeviceState {
+  std::atomic<int> cus{0};
   uint32_t* counter = nullptr;
-  int cus = 0;
 };
 static DeviceState g_dev[kMaxDevices];
 static std::mutex g_dev_mu;
 
-static int device_state(DeviceState** out) {
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return BITONIC_EDEVICE;
+static int current_device(int* dev) {
+  if (hipGetDevice(dev) != hipSuccess || *dev < 0 || *dev >= kMaxDevices) return BITONIC_EDEVICE;
+  return BITONIC_OK;
+}
+
+static int device_cus(int dev) {
+  int c = g_dev[dev].cus.load(std::memory_order_relaxed);
+  if (c > 0) return c;
+  if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || c <= 0)
+    c = 256;
+  g_dev[dev].cus.store(c, std::memory_order_relaxed);
+  return c;
+}
+
+static int device_counter(int dev, uint32_t** out) {
   std::lock_guard<std::mutex> lock(g_dev_mu);
   DeviceState& d = g_dev[dev];
   if (!d.counter) {
     void* p = nullptr;
     if (hipMalloc(&p, 256) != hipSuccess) return BITONIC_ENOMEM;
     d.counter = static_cast<uint32_t*>(p);
-    int cus = 0;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        cus <= 0)
-      cus = 256;
-    d.cus = cus;
   }
-  *out = &d;
+  *out = d.counter;
+  return BITONIC_OK;
+}
+
+// Fill in the device-dependent parts of a plan.
+static int bind_device(Resolved* r) {
+  int dev = 0;
+  int rc = current_device(&dev);
+  if (rc) return rc;
+  r->merge_blocks = r->merge_bpc > 0 ? (uint32_t)(device_cus(dev) * r->merge_bpc) : 0u;
   return BITONIC_OK;
 }
 
@@ -199,6 +244,8 @@ int bitonic_sort_plan_i32(int32_t* keys, int64_t n, int ascending, const bitonic
   if (rc) return rc;
   if (n <= 1) return BITONIC_OK;
   fit_alignment(keys, &r);
+  rc = bind_device(&r);
+  if (rc) return rc;
   (void)hipGetLastError();
   enqueue_plain(keys, (uint32_t)n, 64, ascending ? 0 : -1, r, (hipStream_t)stream, false);
   return finish_launches();
@@ -218,6 +265,8 @@ int bitonic_network_phases_i32(int32_t* keys, int64_t n, int ascending, int last
   if (rc) return rc;
   if (n <= 1) return BITONIC_OK;
   fit_alignment(keys, &r);
+  rc = bind_device(&r);
+  if (rc) return rc;
   (void)hipGetLastError();
   enqueue_plain(keys, (uint32_t)n, last_phase, ascending ? 0 : -1, r, (hipStream_t)stream, false);
   return finish_launches();
@@ -231,11 +280,69 @@ int64_t bitonic_plan_passes(int64_t n, const bitonic_plan* plan) {
   return enqueue_plain(nullptr, (uint32_t)n, 64, 0, r, nullptr, true);
 }
 
-int bitonic_set_tuning(int tile_log2, int fuse) {
+int64_t bitonic_plan_describe(int64_t n, const bitonic_plan* plan, int32_t* kinds,
+                              int32_t* fuse, int64_t cap) {
+  if (n < 0 || n > (int64_t(1) << 31) || cap < 0) return -1;
+  Resolved r;
+  if (resolve(plan, &r)) return -1;
+  if (n <= 1) return 0;
+  Observer obs;
+  obs.kinds = kinds;
+  obs.fuse = fuse;
+  obs.cap = cap;
+  return enqueue_plain(nullptr, (uint32_t)n, 64, 0, r, nullptr, true, &obs);
+}
+
+int bitonic_sort_plan_events_i32(int32_t* keys, int64_t n, int ascending,
+                                 const bitonic_plan* plan, void** events, int64_t nevents,
+                                 void* stream) {
+  int rc = check_sort_args(keys, n);
+  if (rc) return rc;
+  if (nevents < 0 || (nevents > 0 && events == nullptr)) return BITONIC_EINVAL;
+  Resolved r;
+  rc = resolve(plan, &r);
+  if (rc) return rc;
+  if (n <= 1) return BITONIC_OK;
+  fit_alignment(keys, &r);
+  rc = bind_device(&r);
+  if (rc) return rc;
+  Observer obs;
+  obs.events = reinterpret_cast<hipEvent_t*>(events);
+  obs.nevents = nevents;
+  (void)hipGetLastError();
+  enqueue_plain(keys, (uint32_t)n, 64, ascending ? 0 : -1, r, (hipStream_t)stream, false, &obs);
+  return finish_launches();
+}
+
+int bitonic_sort_plan_launches_i32(int32_t* keys, int64_t n, int ascending,
+                                   const bitonic_plan* plan, int64_t first, int64_t count,
+                                   void* stream) {
+  int rc = check_sort_args(keys, n);
+  if (rc) return rc;
+  if (first < 0 || count < 0) return BITONIC_EINVAL;
+  Resolved r;
+  rc = resolve(plan, &r);
+  if (rc) return rc;
+  if (n <= 1 || count == 0) return BITONIC_OK;
+  fit_alignment(keys, &r);
+  rc = bind_device(&r);
+  if (rc) return rc;
+  Observer obs;
+  obs.first = first;
+  obs.count = count;
+  (void)hipGetLastError();
+  enqueue_plain(keys, (uint32_t)n, 64, ascending ? 0 : -1, r, (hipStream_t)stream, false, &obs);
+  return finish_launches();
+}
+
+int bitonic_set_tuning(int tile_log2, int fuse, int merge_blocks_per_cu) {
   if (tile_log2 && !tile_log2_supported(tile_log2)) return BITONIC_EINVAL;
   if (fuse && (fuse < 1 || fuse > kFuseMax)) return BITONIC_EINVAL;
+  if (merge_blocks_per_cu < -1 || merge_blocks_per_cu > 16) return BITONIC_EINVAL;
   if (tile_log2) g_tile_log2.store(tile_log2);
   if (fuse) g_fuse.store(fuse);
+  if (merge_blocks_per_cu > 0) g_merge_bpc.store(merge_blocks_per_cu);
+  if (merge_blocks_per_cu < 0) g_merge_bpc.store(0);
   return BITONIC_OK;
 }
 
@@ -243,15 +350,16 @@ int bitonic_load_tuning(const char* path) {
   if (!path) return BITONIC_EINVAL;
   FILE* f = std::fopen(path, "r");
   if (!f) return BITONIC_EINVAL;
-  int tile = 0, fuse = 0;
+  int tile = 0, fuse = 0, bpc = 0;
   char key[64];
   int val;
   while (std::fscanf(f, "%63s %d", key, &val) == 2) {
     if (!std::strcmp(key, "tile_log2")) tile = val;
     else if (!std::strcmp(key, "fuse")) fuse = val;
+    else if (!std::strcmp(key, "merge_blocks_per_cu")) bpc = val;
   }
   std::fclose(f);
-  return bitonic_set_tuning(tile, fuse);
+  return bitonic_set_tuning(tile, fuse, bpc);
 }
 
 int bitonic_sort_segmented_bounded_i32(int32_t* keys, const int64_t* offsets, int64_t nseg,
@@ -261,12 +369,16 @@ int bitonic_sort_segmented_bounded_i32(int32_t* keys, const int64_t* offsets, in
   if (max_seg_len > (int64_t(1) << 31)) return BITONIC_EUNSUPPORTED;
   if (nseg == 0) return BITONIC_OK;
   if (keys == nullptr || offsets == nullptr) return BITONIC_EINVAL;
-  DeviceState* d = nullptr;
-  int rc = device_state(&d);
+  int dev = 0;
+  int rc = current_device(&dev);
+  if (rc) return rc;
+  uint32_t* counter = nullptr;
+  rc = device_counter(dev, &counter);
   if (rc) return rc;
   (void)hipGetLastError();
-  const int64_t grid = (int64_t)d->cus * 4 < nseg ? (int64_t)d->cus * 4 : nseg;
-  launch_segmented(keys, offsets, nseg, ascending ? 0 : -1, d->counter, (int)grid,
+  const int64_t slots = (int64_t)device_cus(dev) * 4;
+  const int64_t grid = slots < nseg ? slots : nseg;
+  launch_segmented(keys, offsets, nseg, ascending ? 0 : -1, counter, (int)grid,
                    (hipStream_t)stream);
   return finish_launches();
 }

@@ -84,22 +84,26 @@ __device__ __forceinline__ void group_steps(int32_t (&x)[PR::R]) {
 }
 
 // Move the registers from the layout of group GA to that of group GB
-// through LDS.  Begins with a barrier so the LDS is free to overwrite.
+// through LDS.  Begins with a barrier so the LDS is free to overwrite.  The
+// swizzle is linear over XOR, so each address is the swizzled thread base
+// XOR a compile-time constant.  (The compiler computes the bases of all
+// layouts early and keeps them live; recomputing them per regroup would save
+// registers but costs more ALU time than it gains, measured.)
 template <class PR, int GA, int GB>
 __device__ __forceinline__ void regroup(int32_t (&x)[PR::R], int32_t* lds, uint32_t tid) {
   constexpr Group A = PR::value.g[GA];
   constexpr Group B = PR::value.g[GB];
-  const uint32_t ba = deposit<free_mask(A, PR::L)>(tid);
-  const uint32_t bb = deposit<free_mask(B, PR::L)>(tid);
+  const uint32_t sa = swz(deposit<free_mask(A, PR::L)>(tid));
+  const uint32_t sb = swz(deposit<free_mask(B, PR::L)>(tid));
   __syncthreads();
   static_for<0, PR::R>([&](auto J) {
-    constexpr uint32_t o = goff(A, J);
-    lds[swz(ba ^ o)] = x[J];
+    constexpr uint32_t c = swz_const(goff(A, J));
+    lds[sa ^ c] = x[J];
   });
   __syncthreads();
   static_for<0, PR::R>([&](auto J) {
-    constexpr uint32_t o = goff(B, J);
-    x[J] = lds[swz(bb ^ o)];
+    constexpr uint32_t c = swz_const(goff(B, J));
+    x[J] = lds[sb ^ c];
   });
 }
 
@@ -110,6 +114,15 @@ __device__ __forceinline__ void run_from(int32_t (&x)[PR::R], int32_t* lds, uint
     regroup<PR, G, G + 1>(x, lds, tid);
     run_from<PR, G + 1>(x, lds, tid);
   }
+}
+
+// Index of register slot J of a thread whose base index is `base`.
+template <class PR, int G, uint32_t J>
+__device__ __forceinline__ uint32_t slot_index(uint32_t base) {
+  constexpr Group gr = PR::value.g[G];
+  constexpr uint32_t o = goff(gr, J);
+  if constexpr (layout_is_unit(gr)) return base + o;  // disjoint bits
+  else return base ^ o;
 }
 
 // Load the thread's keys of a tile in the layout of group G.
@@ -123,22 +136,19 @@ __device__ __forceinline__ void load_tile(int32_t (&x)[PR::R], const int32_t* __
     if constexpr (layout_is_vector4(gr)) {
       static_for<0, PR::R / 4>([&](auto Q) {
         constexpr uint32_t o = goff(gr, 4u * Q);
-        const int4 v = *reinterpret_cast<const int4*>(tile + ((base ^ o) & ~3u));
+        const uint32_t i = slot_index<PR, G, 4u * Q>(base);
+        const int4 v = *reinterpret_cast<const int4*>(tile + (i & ~3u));
         const int32_t e[4] = {v.x, v.y, v.z, v.w};
         static_for<0, 4>([&](auto C) {
           x[4 * Q + C] = e[(o ^ C) & 3u] ^ flip;
         });
       });
     } else {
-      static_for<0, PR::R>([&](auto J) {
-        constexpr uint32_t o = goff(gr, J);
-        x[J] = tile[base ^ o] ^ flip;
-      });
+      static_for<0, PR::R>([&](auto J) { x[J] = tile[slot_index<PR, G, J>(base)] ^ flip; });
     }
   } else {
     static_for<0, PR::R>([&](auto J) {
-      constexpr uint32_t o = goff(gr, J);
-      const uint32_t i = base ^ o;
+      const uint32_t i = slot_index<PR, G, J>(base);
       x[J] = i < valid ? (tile[i] ^ flip) : kPad;
     });
   }
@@ -153,20 +163,17 @@ __device__ __forceinline__ void store_tile(const int32_t (&x)[PR::R], int32_t* _
     if constexpr (layout_is_vector4(gr)) {
       static_for<0, PR::R / 4>([&](auto Q) {
         constexpr uint32_t o = goff(gr, 4u * Q);
+        const uint32_t i = slot_index<PR, G, 4u * Q>(base);
         int32_t e[4];
         static_for<0, 4>([&](auto C) { e[(o ^ C) & 3u] = x[4 * Q + C] ^ flip; });
-        *reinterpret_cast<int4*>(tile + ((base ^ o) & ~3u)) = make_int4(e[0], e[1], e[2], e[3]);
+        *reinterpret_cast<int4*>(tile + (i & ~3u)) = make_int4(e[0], e[1], e[2], e[3]);
       });
     } else {
-      static_for<0, PR::R>([&](auto J) {
-        constexpr uint32_t o = goff(gr, J);
-        tile[base ^ o] = x[J] ^ flip;
-      });
+      static_for<0, PR::R>([&](auto J) { tile[slot_index<PR, G, J>(base)] = x[J] ^ flip; });
     }
   } else {
     static_for<0, PR::R>([&](auto J) {
-      constexpr uint32_t o = goff(gr, J);
-      const uint32_t i = base ^ o;
+      const uint32_t i = slot_index<PR, G, J>(base);
       if (i < valid) tile[i] = x[J] ^ flip;
     });
   }

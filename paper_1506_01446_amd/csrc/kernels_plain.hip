@@ -22,6 +22,7 @@
 
 namespace bitonic {
 
+// One tile per workgroup.
 template <int L, int RL, int KIND>
 __global__ __launch_bounds__(1 << (L - RL)) void tile_kernel(int32_t* __restrict__ keys,
                                                              uint32_t n, int32_t flip) {
@@ -33,63 +34,106 @@ __global__ __launch_bounds__(1 << (L - RL)) void tile_kernel(int32_t* __restrict
   tile_program<PR>(keys + t0, valid, flip, lds, threadIdx.x);
 }
 
+// Tiles blockIdx.x, blockIdx.x + gridDim.x, ... of keys[0, n).  The keys of a
+// block's next tile are loaded into a second register set before the current
+// tile's steps run, so the loads overlap the compute (a workgroup barrier
+// waits for LDS traffic only, not for those loads).  The thread id is passed
+// through an empty asm statement every iteration so that the compiler
+// recomputes the loop-invariant LDS and global offsets instead of keeping
+// all of them live in registers.
+template <int L, int RL, int KIND>
+__global__ __launch_bounds__(1 << (L - RL)) void tile_loop_kernel(int32_t* __restrict__ keys,
+                                                                  uint32_t n, int32_t flip) {
+  using PR = Prog<L, RL, KIND>;
+  __shared__ int32_t lds[PR::T];
+  const uint32_t ntiles = (uint32_t)(((uint64_t)n + PR::T - 1) >> L);
+  auto valid_of = [&](uint32_t tile) {
+    const uint32_t left = n - (tile << L);
+    return left < (uint32_t)PR::T ? left : (uint32_t)PR::T;
+  };
+  uint32_t tile = blockIdx.x;
+  int32_t x[PR::R];
+  load_tile<PR, 0>(x, keys + ((size_t)tile << L), valid_of(tile), flip, threadIdx.x);
+  for (;;) {
+    uint32_t tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    const uint32_t next = tile + gridDim.x;
+    const bool more = next < ntiles;
+    int32_t y[PR::R];
+    if (more) load_tile<PR, 0>(y, keys + ((size_t)next << L), valid_of(next), flip, tid);
+    run_from<PR, 0>(x, lds, tid);
+    store_tile<PR, PR::value.ngroups - 1>(x, keys + ((size_t)tile << L), valid_of(tile), flip,
+                                           tid);
+    if (!more) break;
+    static_for<0, PR::R>([&](auto J) { x[J] = y[J]; });
+    tile = next;
+  }
+}
+
 // Keys of thread g: 4 consecutive columns x 2^F rows.  Row rho sits at
 // index base | rho << q; with MIRROR the upper half of the rows are the
 // mirror images (index XOR (2^(q+F) - 1)), so the first step pairs each key
 // with its mirror in the 2^(q+F) block.
+template <int F, bool MIRROR, int RHO>
+__device__ __forceinline__ uint32_t pass_row_index(uint32_t base, uint32_t span, int q) {
+  constexpr int TOP = (1 << F) >> 1;
+  if constexpr (MIRROR && (RHO & TOP))
+    return base ^ span ^ ((uint32_t)(RHO & (TOP - 1)) << q);
+  else
+    return base | ((uint32_t)RHO << q);
+}
+
+// Row RHO into registers x[4 RHO .. 4 RHO + 3]: one 16-byte load if VEC, else
+// key by key with indices >= n read as the sentinel.  Mirrored rows are
+// stored in reverse order, so their registers are reversed.
+template <int F, bool MIRROR, int RHO, bool VEC>
+__device__ __forceinline__ void pass_load_row(int32_t* x, const int32_t* __restrict__ keys,
+                                              uint32_t ri, uint32_t n, int32_t flip) {
+  constexpr bool rev = MIRROR && (RHO & ((1 << F) >> 1));
+  if constexpr (VEC) {
+    const int4 v = *reinterpret_cast<const int4*>(keys + (ri & ~3u));
+    x[4 * RHO + (rev ? 3 : 0)] = v.x ^ flip;
+    x[4 * RHO + (rev ? 2 : 1)] = v.y ^ flip;
+    x[4 * RHO + (rev ? 1 : 2)] = v.z ^ flip;
+    x[4 * RHO + (rev ? 0 : 3)] = v.w ^ flip;
+  } else {
+#pragma unroll
+    for (uint32_t c = 0; c < 4; ++c) {
+      const uint32_t i = ri ^ c;
+      x[4 * RHO + c] = i < n ? (keys[i] ^ flip) : kPad;
+    }
+  }
+}
+
+template <int F, bool MIRROR, int RHO, bool VEC>
+__device__ __forceinline__ void pass_store_row(const int32_t* x, int32_t* __restrict__ keys,
+                                               uint32_t ri, uint32_t n, int32_t flip) {
+  constexpr bool rev = MIRROR && (RHO & ((1 << F) >> 1));
+  if constexpr (VEC) {
+    *reinterpret_cast<int4*>(keys + (ri & ~3u)) =
+        make_int4(x[4 * RHO + (rev ? 3 : 0)] ^ flip, x[4 * RHO + (rev ? 2 : 1)] ^ flip,
+                  x[4 * RHO + (rev ? 1 : 2)] ^ flip, x[4 * RHO + (rev ? 0 : 3)] ^ flip);
+  } else {
+#pragma unroll
+    for (uint32_t c = 0; c < 4; ++c) {
+      const uint32_t i = ri ^ c;
+      if (i < n) keys[i] = x[4 * RHO + c] ^ flip;
+    }
+  }
+}
+
+// The F steps on the registers: the mirror step (if MIRROR) on the top row
+// bit, then half-cleaners on the remaining row bits, highest first.
 template <int F, bool MIRROR>
-__global__ __launch_bounds__(256) void global_pass_kernel(int32_t* __restrict__ keys, uint32_t n,
-                                                          int q, int32_t flip) {
+__device__ __forceinline__ void pass_steps(int32_t (&x)[4 << F]) {
   constexpr int ROWS = 1 << F;
   constexpr int TOP = ROWS >> 1;
-  const uint32_t g = blockIdx.x * 256u + threadIdx.x;
-  const uint32_t lowmask = (1u << (q - 2)) - 1u;
-  const uint32_t base = ((g & lowmask) << 2) | ((g >> (q - 2)) << (q + F));
-  if (base >= n) return;
-  const uint32_t span = (q + F >= 32) ? 0xFFFFFFFFu : ((1u << (q + F)) - 1u);
-
-  int32_t x[4 * ROWS];
-  auto row_index = [&](int rho) -> uint32_t {
-    if (MIRROR && (rho & TOP)) return base ^ span ^ ((uint32_t)(rho & (TOP - 1)) << q);
-    return base | ((uint32_t)rho << q);
-  };
-  const bool inside = (base | span) < n;
-
-  if (inside) {
-    static_for<0, ROWS>([&](auto RHO) {
-      constexpr int rho = RHO;
-      constexpr bool rev = MIRROR && (rho & TOP);
-      const uint32_t ri = row_index(rho);
-      const int4 v = *reinterpret_cast<const int4*>(keys + (ri & ~3u));
-      if constexpr (rev) {
-        x[4 * rho + 0] = v.w ^ flip;
-        x[4 * rho + 1] = v.z ^ flip;
-        x[4 * rho + 2] = v.y ^ flip;
-        x[4 * rho + 3] = v.x ^ flip;
-      } else {
-        x[4 * rho + 0] = v.x ^ flip;
-        x[4 * rho + 1] = v.y ^ flip;
-        x[4 * rho + 2] = v.z ^ flip;
-        x[4 * rho + 3] = v.w ^ flip;
-      }
-    });
-  } else {
-    static_for<0, ROWS>([&](auto RHO) {
-      constexpr int rho = RHO;
-      const uint32_t ri = row_index(rho);
-      static_for<0, 4>([&](auto C) {
-        const uint32_t i = ri ^ (uint32_t)C;
-        x[4 * rho + C] = i < n ? (keys[i] ^ flip) : kPad;
-      });
-    });
-  }
-
   if constexpr (MIRROR) {
     static_for<0, TOP>([&](auto RHO) {
       static_for<0, 4>([&](auto C) { cmpx(x[4 * RHO + C], x[4 * (RHO + TOP) + C]); });
     });
   }
-  constexpr int NB = MIRROR ? F - 1 : F;  // remaining row bits, highest first
+  constexpr int NB = MIRROR ? F - 1 : F;
   static_for<0, NB>([&](auto I) {
     constexpr int b = NB - 1 - I;
     static_for<0, ROWS>([&](auto RHO) {
@@ -108,30 +152,75 @@ __global__ __launch_bounds__(256) void global_pass_kernel(int32_t* __restrict__ 
       }
     });
   });
+}
 
-  if (inside) {
+// Thread g0 + blockIdx.x * 256 + threadIdx.x.  BOUNDED == false: the
+// thread's whole 2^(q+F) block lies below n, every row moves as a 16-byte
+// vector and nothing is checked.  Because 256 divides 2^(q-2), a workgroup
+// stays inside one block, so a row's address is a workgroup-uniform part
+// (block start + row offset, kept in scalar registers) plus one of two
+// per-lane 32-bit byte offsets (the column, or its mirror image), which keeps
+// the kernel to few vector registers.
+// BOUNDED == true: rows wholly below n move as vectors, a row that straddles
+// n goes key by key, rows at or past n are sentinels.
+template <int F, bool MIRROR, bool BOUNDED>
+__global__ __launch_bounds__(256) void global_pass_kernel(int32_t* __restrict__ keys, uint32_t n,
+                                                          int q, int32_t flip, uint32_t g0) {
+  constexpr int ROWS = 1 << F;
+  constexpr int TOP = ROWS >> 1;
+  int32_t x[4 * ROWS];
+  if constexpr (!BOUNDED) {
+    const uint32_t gw = g0 + blockIdx.x * 256u;            // uniform
+    const uint32_t blk = gw >> (q - 2);                    // uniform block index
+    int32_t* bp = keys + ((size_t)blk << (q + F));         // uniform block start
+    const uint32_t col = ((gw + threadIdx.x) & ((1u << (q - 2)) - 1u)) << 2;
+    const uint32_t off = col * 4u;                          // byte offset, < 2^(q+2)
+    const uint32_t moff = ((1u << q) - 4u - col) * 4u;      // mirrored column
+    auto row_ptr = [&](int rho) -> int4* {
+      const bool mir = MIRROR && (rho & TOP);
+      const uint32_t r = mir ? ((uint32_t)(ROWS - 1) ^ (uint32_t)(rho & (TOP - 1))) : (uint32_t)rho;
+      char* rb = reinterpret_cast<char*>(bp + ((size_t)r << q));
+      return reinterpret_cast<int4*>(rb + (mir ? moff : off));
+    };
     static_for<0, ROWS>([&](auto RHO) {
-      constexpr int rho = RHO;
-      constexpr bool rev = MIRROR && (rho & TOP);
-      const uint32_t ri = row_index(rho);
-      int4 v;
-      if constexpr (rev) {
-        v = make_int4(x[4 * rho + 3] ^ flip, x[4 * rho + 2] ^ flip, x[4 * rho + 1] ^ flip,
-                      x[4 * rho + 0] ^ flip);
-      } else {
-        v = make_int4(x[4 * rho + 0] ^ flip, x[4 * rho + 1] ^ flip, x[4 * rho + 2] ^ flip,
-                      x[4 * rho + 3] ^ flip);
-      }
-      *reinterpret_cast<int4*>(keys + (ri & ~3u)) = v;
+      constexpr bool rev = MIRROR && (RHO & TOP);
+      const int4 v = *row_ptr(RHO);
+      x[4 * RHO + (rev ? 3 : 0)] = v.x ^ flip;
+      x[4 * RHO + (rev ? 2 : 1)] = v.y ^ flip;
+      x[4 * RHO + (rev ? 1 : 2)] = v.z ^ flip;
+      x[4 * RHO + (rev ? 0 : 3)] = v.w ^ flip;
+    });
+    // Scheduling fences keep the compiler from interleaving the steps with
+    // the loads and stores, which would hold many more registers live.
+    __builtin_amdgcn_sched_barrier(0);
+    pass_steps<F, MIRROR>(x);
+    __builtin_amdgcn_sched_barrier(0);
+    static_for<0, ROWS>([&](auto RHO) {
+      constexpr bool rev = MIRROR && (RHO & TOP);
+      *row_ptr(RHO) = make_int4(x[4 * RHO + (rev ? 3 : 0)] ^ flip, x[4 * RHO + (rev ? 2 : 1)] ^ flip,
+                                x[4 * RHO + (rev ? 1 : 2)] ^ flip, x[4 * RHO + (rev ? 0 : 3)] ^ flip);
+      __builtin_amdgcn_sched_barrier(0);
     });
   } else {
+    const uint32_t g = g0 + blockIdx.x * 256u + threadIdx.x;
+    const uint32_t lowmask = (1u << (q - 2)) - 1u;
+    const uint32_t base = ((g & lowmask) << 2) | ((g >> (q - 2)) << (q + F));
+    if (base >= n) return;
+    const uint32_t span = (q + F >= 32) ? 0xFFFFFFFFu : ((1u << (q + F)) - 1u);
     static_for<0, ROWS>([&](auto RHO) {
-      constexpr int rho = RHO;
-      const uint32_t ri = row_index(rho);
-      static_for<0, 4>([&](auto C) {
-        const uint32_t i = ri ^ (uint32_t)C;
-        if (i < n) keys[i] = x[4 * rho + C] ^ flip;
-      });
+      const uint32_t ri = pass_row_index<F, MIRROR, RHO>(base, span, q);
+      if ((ri | 3u) < n)
+        pass_load_row<F, MIRROR, RHO, true>(x, keys, ri, n, flip);
+      else
+        pass_load_row<F, MIRROR, RHO, false>(x, keys, ri, n, flip);
+    });
+    pass_steps<F, MIRROR>(x);
+    static_for<0, ROWS>([&](auto RHO) {
+      const uint32_t ri = pass_row_index<F, MIRROR, RHO>(base, span, q);
+      if ((ri | 3u) < n)
+        pass_store_row<F, MIRROR, RHO, true>(x, keys, ri, n, flip);
+      else
+        pass_store_row<F, MIRROR, RHO, false>(x, keys, ri, n, flip);
     });
   }
 }
@@ -195,46 +284,61 @@ __global__ __launch_bounds__(256) void step_kernel(int32_t* __restrict__ keys, u
 constexpr int kTileRegLog = 5;  // 32 keys per thread in the tile kernels
 
 template <int L>
-static void launch_tile_L(int kind, int32_t* keys, uint32_t n, int32_t flip, hipStream_t st) {
-  const uint32_t blocks = (uint32_t)(((uint64_t)n + (1u << L) - 1) >> L);
+static void launch_tile_L(int kind, int32_t* keys, uint32_t n, int32_t flip, uint32_t max_blocks,
+                          hipStream_t st) {
+  const uint32_t ntiles = (uint32_t)(((uint64_t)n + (1u << L) - 1) >> L);
   constexpr int NT = 1 << (L - kTileRegLog);
-  if (kind == 0)
-    tile_kernel<L, kTileRegLog, 0><<<blocks, NT, 0, st>>>(keys, n, flip);
-  else
-    tile_kernel<L, kTileRegLog, 1><<<blocks, NT, 0, st>>>(keys, n, flip);
+  if (kind == 0) {
+    tile_kernel<L, kTileRegLog, 0><<<ntiles, NT, 0, st>>>(keys, n, flip);
+  } else if (max_blocks == 0 || max_blocks >= ntiles) {
+    tile_kernel<L, kTileRegLog, 1><<<ntiles, NT, 0, st>>>(keys, n, flip);
+  } else {
+    tile_loop_kernel<L, kTileRegLog, 1><<<max_blocks, NT, 0, st>>>(keys, n, flip);
+  }
 }
 
 bool tile_log2_supported(int L) { return L >= kTileMinLog2 && L <= kTileMaxLog2; }
 
-void launch_tile(int L, int kind, int32_t* keys, uint32_t n, int32_t flip, hipStream_t st) {
+void launch_tile(int L, int kind, int32_t* keys, uint32_t n, int32_t flip, uint32_t max_blocks,
+                 hipStream_t st) {
   switch (L) {
-    case 11: launch_tile_L<11>(kind, keys, n, flip, st); break;
-    case 12: launch_tile_L<12>(kind, keys, n, flip, st); break;
-    case 13: launch_tile_L<13>(kind, keys, n, flip, st); break;
+    case 11: launch_tile_L<11>(kind, keys, n, flip, max_blocks, st); break;
+    case 12: launch_tile_L<12>(kind, keys, n, flip, max_blocks, st); break;
+    case 13: launch_tile_L<13>(kind, keys, n, flip, max_blocks, st); break;
     default: break;
   }
 }
 
-// Threads whose base index is below n (see global_pass_kernel's mapping).
-static uint32_t global_pass_threads(uint32_t n, int q, int f) {
+// Thread counts of a pass (see global_pass_kernel's mapping): `full` threads
+// own keys in 2^(q+f) blocks wholly below n, `total` own any key below n.
+static void global_pass_threads(uint32_t n, int q, int f, uint32_t* full, uint32_t* total) {
   const uint64_t per_block = 1ull << (q - 2);
-  const uint64_t full = (uint64_t)n >> (q + f);
+  const uint64_t nfull = (uint64_t)n >> (q + f);
   const uint64_t rem = (uint64_t)n & ((1ull << (q + f)) - 1);
   uint64_t part = (rem + 3) >> 2;
   if (part > per_block) part = per_block;
-  return (uint32_t)(full * per_block + part);
+  *full = (uint32_t)(nfull * per_block);
+  *total = (uint32_t)(nfull * per_block + part);
+}
+
+template <int F, bool MIRROR>
+static void launch_global_FM(int32_t* keys, uint32_t n, int q, int32_t flip, hipStream_t st) {
+  uint32_t full = 0, total = 0;
+  global_pass_threads(n, q, F, &full, &total);
+  if (full > 0)  // full is a multiple of 2^(q-2) >= 256
+    global_pass_kernel<F, MIRROR, false><<<full / 256, 256, 0, st>>>(keys, n, q, flip, 0u);
+  if (total > full)
+    global_pass_kernel<F, MIRROR, true><<<(total - full + 255) / 256, 256, 0, st>>>(keys, n, q,
+                                                                                  flip, full);
 }
 
 template <int F>
 static void launch_global_F(bool mirror, int32_t* keys, uint32_t n, int q, int32_t flip,
                             hipStream_t st) {
-  const uint32_t threads = global_pass_threads(n, q, F);
-  const uint32_t blocks = (threads + 255) / 256;
-  if (blocks == 0) return;
   if (mirror)
-    global_pass_kernel<F, true><<<blocks, 256, 0, st>>>(keys, n, q, flip);
+    launch_global_FM<F, true>(keys, n, q, flip, st);
   else
-    global_pass_kernel<F, false><<<blocks, 256, 0, st>>>(keys, n, q, flip);
+    launch_global_FM<F, false>(keys, n, q, flip, st);
 }
 
 void launch_global_pass(int f, bool mirror, int32_t* keys, uint32_t n, int q, int32_t flip,

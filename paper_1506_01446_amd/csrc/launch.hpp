@@ -14,8 +14,10 @@ constexpr int kLdsNetworkMaxLog2 = 13;
 bool tile_log2_supported(int L);
 
 // Tile sort (kind 0: phases 1..L) or tile merge (kind 1: strides
-// 2^(L-1)..1) over every 2^L tile of keys[0, n).
-void launch_tile(int L, int kind, int32_t* keys, uint32_t n, int32_t flip, hipStream_t st);
+// 2^(L-1)..1) over every 2^L tile of keys[0, n).  The merge runs at most
+// max_blocks workgroups (0 = one per tile), each looping over its tiles.
+void launch_tile(int L, int kind, int32_t* keys, uint32_t n, int32_t flip, uint32_t max_blocks,
+                 hipStream_t st);
 
 // f fused steps on bits q+f-1 .. q (the first one the mirror step if
 // `mirror`).  Requires q >= 8, q + f <= 31, 1 <= f <= kFuseMax.

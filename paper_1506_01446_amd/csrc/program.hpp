@@ -73,6 +73,18 @@ constexpr bool slot_is_lower(const Group& G, uint32_t j, uint32_t D) {
   return ((goff(G, j) >> h) & 1u) == 0;
 }
 
+// Layout for global loads and stores: each thread holds 4 consecutive keys
+// (index bits 0, 1) of r - 2 rows (the top tile bits), so a wave moves 64
+// consecutive 16-byte pieces per instruction.
+constexpr Group io_group(int L, int r) {
+  Group G{};
+  G.r = r;
+  G.v[0] = 1u;
+  G.v[1] = 2u;
+  for (int m = 2; m < r; ++m) G.v[m] = 1u << (L - 1 - (m - 2));
+  return G;
+}
+
 constexpr Group blocked_group(int r) {
   Group G{};
   G.r = r;
@@ -112,6 +124,7 @@ constexpr Program make_tile_sort(int L, int r) {
   Program P{};
   P.L = L;
   P.r = r;
+  P.g[P.ngroups++] = io_group(L, r);
   Group g0 = blocked_group(r);
   const int pin = L < r ? L : r;
   for (int p = 1; p <= pin; ++p) {
@@ -120,22 +133,45 @@ constexpr Program make_tile_sort(int L, int r) {
   }
   P.g[P.ngroups++] = g0;
   for (int p = r + 1; p <= L; ++p) add_merge_bits(P, p - 1, true);
+  P.g[P.ngroups++] = io_group(L, r);
   return P;
 }
 
 // The last L steps of a phase longer than the tile: strides 2^(L-1) .. 1,
-// smaller key to the lower index, on each tile.
+// smaller key to the lower index, on each tile.  The first layout also holds
+// index bits 0 and 1, so every thread loads 4 consecutive keys at a time.
 constexpr Program make_tile_merge(int L, int r) {
   Program P{};
   P.L = L;
   P.r = r;
-  add_merge_bits(P, L - 1, false);
+  Group G{};
+  G.r = r;
+  G.v[0] = 1u;
+  G.v[1] = 2u;
+  for (int m = 2; m < r; ++m) {
+    G.v[m] = 1u << (L - 1 - (m - 2));
+    G.d[G.nsteps++] = 1u << m;
+  }
+  P.g[P.ngroups++] = G;
+  add_merge_bits(P, L - 1 - (r - 2), false);
+  P.g[P.ngroups++] = io_group(L, r);
   return P;
 }
 
 constexpr bool layout_is_vector4(const Group& G) {
   return G.r >= 2 && G.v[0] == 1u && G.v[1] == 2u;
 }
+
+// Every basis vector a single index bit: then base(t) and off(j) have no bit
+// in common and base ^ off == base + off.
+constexpr bool layout_is_unit(const Group& G) {
+  for (int m = 0; m < G.r; ++m)
+    if ((G.v[m] & (G.v[m] - 1u)) != 0) return false;
+  return true;
+}
+
+// The LDS swizzle of device.hpp, which is linear over XOR.
+constexpr uint32_t swz_const(uint32_t i) { return i ^ ((i >> 5) & 31u); }
 
 // Total compare-exchange steps a program performs (for checks).
 constexpr int program_steps(const Program& P) {

@@ -40,7 +40,7 @@ def test_argument_errors_are_synchronous(lib):
     assert lib.bitonic_sort_plan_i32(None, 0, 1, ctypes.byref(bad), None) == -1
     bad = B.bitonic_plan(3, 13, 9, 0)
     assert lib.bitonic_sort_plan_i32(None, 0, 1, ctypes.byref(bad), None) == -1
-    bad = B.bitonic_plan(3, 13, 4, 1)
+    bad = B.bitonic_plan(3, 13, 4, 17)
     assert lib.bitonic_sort_plan_i32(None, 0, 1, ctypes.byref(bad), None) == -1
     assert lib.bitonic_network_phases_i32(None, 4, 1, 0, None, None) == -1
     assert lib.bitonic_sort_segmented_i32(None, None, -1, 1, None) == -1
@@ -48,8 +48,10 @@ def test_argument_errors_are_synchronous(lib):
     assert lib.bitonic_sort_segmented_i32(None, None, 3, 1, None) == -1
     assert lib.bitonic_sort_segmented_bounded_i32(None, None, 3, -1, 1, None) == -1
     assert lib.bitonic_keygen_i32(None, -1, 0, 0, None) == -1
-    assert lib.bitonic_set_tuning(99, 0) == -1
-    assert lib.bitonic_set_tuning(0, 6) == -1
+    assert lib.bitonic_set_tuning(99, 0, 0) == -1
+    assert lib.bitonic_set_tuning(0, 6, 0) == -1
+    assert lib.bitonic_set_tuning(0, 0, 99) == -1
+    assert lib.bitonic_set_tuning(0, 0, -2) == -1
     assert lib.bitonic_load_tuning(b"/nonexistent/tuning.txt") == -1
 
 
@@ -90,5 +92,6 @@ def test_semi_plan_counts(lib):
 def test_headline_pass_count(lib):
     # n = 2^24 with 2^13-key tiles and up to 4 fused steps per HBM pass
     assert B.bitonic_plan_passes(2**24, ("optimized", 13, 4)) == 33
+    assert B.bitonic_plan_passes(2**24) == 30  # default: 2^13 tiles, 5 fused steps
     assert B.bitonic_plan_passes(0) == 0 and B.bitonic_plan_passes(1) == 0
     assert B.bitonic_plan_passes(-1) == -1
