@@ -47,6 +47,9 @@ def parse():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=0.0)
     ap.add_argument("--out", default="")
+    ap.add_argument("--counters", action="store_true",
+                    help="short run for rocprofv3 --pmc: one n-key device copy (the "
+                         "calibration kernel) and three sorts, no timing")
     return ap.parse_args()
 
 
@@ -229,6 +232,15 @@ def main():
     plan = ("optimized", args.tile, args.fuse)
     n = args.n
     src = torch.from_numpy(W.uniform_i32(W.SEED_BASE + 2, n)).cuda()
+    if args.counters:
+        dst = torch.empty_like(src)
+        dst.copy_(src)          # calibration: reads and writes 4n bytes each
+        for _ in range(3):
+            buf = src.clone()
+            B.bitonic_sort_plan_i32(buf, True, plan)
+        torch.cuda.synchronize()
+        log(f"[bench] counters run done: copy of {4 * n} bytes, 3 sorts of n={n}")
+        return
     passes = B.bitonic_plan_passes(n, plan)
     log(f"[bench] n={n} passes={passes}; timing {args.steps} steps after {args.warmup} warm-up")
     ms, wall, ok = time_sorts(torch, B, src, args.steps, args.warmup, plan)

@@ -33,9 +33,10 @@
  *  - Errors in the arguments are reported synchronously and nothing is
  *    enqueued.  No exception crosses this interface.
  *  - Calls are reentrant on different streams.  The segmented sort uses a
- *    per-device scratch buffer that the library allocates on first use (or
- *    when a larger one is needed); two segmented calls on different streams
- *    of one device must not overlap in time.
+ *    scratch buffer per (device, stream) that the library allocates on first
+ *    use on that stream (or when a larger one is needed, after waiting for
+ *    the stream); segmented calls on one stream are ordered by the stream,
+ *    calls on different streams use different buffers.
  */
 #ifndef BITONIC_MI355X_H
 #define BITONIC_MI355X_H
@@ -80,18 +81,27 @@ int bitonic_sort_i32(int32_t* keys, int64_t n, int ascending, void* stream);
  *   nseg       number of segments, >= 0; 0 enqueues nothing
  *   ascending  as above, for every segment
  *   stream     hipStream_t
- * The offsets are read on the device only, so the call never blocks; bad
- * offsets are undefined behaviour.  Returns BITONIC_OK, BITONIC_EINVAL,
- * BITONIC_ENOMEM or BITONIC_ELAUNCH.
+ * The launch sequence depends on the largest segment: this call reads
+ * offsets[0] and offsets[nseg] back to the host (one blocking copy on
+ * `stream`) to bound it.  bitonic_sort_segmented_bounded_i32 takes the bound
+ * from the caller and never blocks.  Bad offsets are undefined behaviour.
+ * Returns BITONIC_OK, BITONIC_EINVAL, BITONIC_ENOMEM (scratch), BITONIC_EDEVICE
+ * or BITONIC_ELAUNCH.
  */
 int bitonic_sort_segmented_i32(int32_t* keys, const int64_t* offsets,
                                int64_t nseg, int ascending, void* stream);
 
 /*
  * As bitonic_sort_segmented_i32, with a host-side bound: every segment holds
- * at most max_seg_len keys (0 = unknown).  The bound only prunes launches
- * for merge phases no segment can reach; a segment longer than the bound is
- * undefined behaviour.
+ * at most max_seg_len keys (0 = unknown: then offsets[0] and offsets[nseg]
+ * are read back, as above).  With a bound the call only enqueues work and can
+ * be captured into a HIP graph (once the stream's scratch buffer is large
+ * enough: the buffer is never allocated during a capture, BITONIC_ENOMEM).
+ * The bound fixes how many merge phases are enqueued; a segment longer than
+ * the bound is undefined behaviour.  Launches: a prep kernel, one persistent
+ * kernel for all segments of up to 2^13 keys, and, if the bound exceeds 2^13,
+ * one tile-sort launch plus, per phase p = 14 .. ceil(log2 bound), the fused
+ * long-stride passes and one tile merge.
  */
 int bitonic_sort_segmented_bounded_i32(int32_t* keys, const int64_t* offsets,
                                        int64_t nseg, int64_t max_seg_len,

@@ -14,6 +14,7 @@
 #include <cstdio>
 #include <cstring>
 #include <mutex>
+#include <vector>
 
 #include "bitonic.h"
 #include "launch.hpp"
@@ -175,7 +176,6 @@ static int finish_launches() {
 constexpr int kMaxDevices = 64;
 struct DeviceState {
   std::atomic<int> cus{0};
-  uint32_t* counter = nullptr;
 };
 static DeviceState g_dev[kMaxDevices];
 static std::mutex g_dev_mu;
@@ -194,15 +194,49 @@ static int device_cus(int dev) {
   return c;
 }
 
-static int device_counter(int dev, uint32_t** out) {
+// Scratch of the segmented sort, one buffer per (device, stream), grown on
+// demand and kept until the process ends.  Calls on different streams use
+// different buffers, so they may overlap; a buffer is never allocated while
+// its stream is being captured into a graph.
+struct ScratchSlot {
+  int dev;
+  hipStream_t stream;
+  void* ptr;
+  size_t bytes;
+};
+static std::vector<ScratchSlot> g_scratch;
+
+static int stream_scratch(int dev, hipStream_t st, size_t bytes, void** out) {
   std::lock_guard<std::mutex> lock(g_dev_mu);
-  DeviceState& d = g_dev[dev];
-  if (!d.counter) {
-    void* p = nullptr;
-    if (hipMalloc(&p, 256) != hipSuccess) return BITONIC_ENOMEM;
-    d.counter = static_cast<uint32_t*>(p);
+  for (auto& s : g_scratch) {
+    if (s.dev == dev && s.stream == st) {
+      if (s.bytes >= bytes) {
+        *out = s.ptr;
+        return BITONIC_OK;
+      }
+      hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+      if (hipStreamIsCapturing(st, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
+        return BITONIC_ENOMEM;  // cannot grow inside a capture
+      // the old buffer may still be in use by earlier work on this stream
+      if (hipStreamSynchronize(st) != hipSuccess) return BITONIC_EDEVICE;
+      (void)hipFree(s.ptr);
+      s.ptr = nullptr;
+      s.bytes = 0;
+      size_t want = bytes + bytes / 2;
+      if (hipMalloc(&s.ptr, want) != hipSuccess) return BITONIC_ENOMEM;
+      s.bytes = want;
+      *out = s.ptr;
+      return BITONIC_OK;
+    }
   }
-  *out = d.counter;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(st, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
+    return BITONIC_ENOMEM;
+  void* ptr = nullptr;
+  const size_t want = bytes < (size_t(1) << 20) ? (size_t(1) << 20) : bytes;
+  if (hipMalloc(&ptr, want) != hipSuccess) return BITONIC_ENOMEM;
+  g_scratch.push_back({dev, st, ptr, want});
+  *out = ptr;
   return BITONIC_OK;
 }
 
@@ -369,17 +403,52 @@ int bitonic_sort_segmented_bounded_i32(int32_t* keys, const int64_t* offsets, in
   if (max_seg_len > (int64_t(1) << 31)) return BITONIC_EUNSUPPORTED;
   if (nseg == 0) return BITONIC_OK;
   if (keys == nullptr || offsets == nullptr) return BITONIC_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
   int dev = 0;
   int rc = current_device(&dev);
   if (rc) return rc;
-  uint32_t* counter = nullptr;
-  rc = device_counter(dev, &counter);
+  if (max_seg_len == 0) {
+    // No bound given: read the first and last offsets (a blocking copy).
+    int64_t ends[2] = {0, 0};
+    if (hipMemcpyAsync(&ends[0], offsets, sizeof(int64_t), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipMemcpyAsync(&ends[1], offsets + nseg, sizeof(int64_t), hipMemcpyDeviceToHost, st) !=
+            hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      return BITONIC_EDEVICE;
+    max_seg_len = ends[1] - ends[0];
+    if (max_seg_len < 0) return BITONIC_EINVAL;
+    if (max_seg_len > (int64_t(1) << 31)) max_seg_len = int64_t(1) << 31;
+  }
+  void* base = nullptr;
+  rc = stream_scratch(dev, st, seg_scratch_bytes(nseg), &base);
   if (rc) return rc;
+  const SegScratch sc = seg_scratch_carve(base, nseg);
+  const int32_t flip = ascending ? 0 : -1;
+  const int cus = device_cus(dev);
   (void)hipGetLastError();
-  const int64_t slots = (int64_t)device_cus(dev) * 4;
-  const int64_t grid = slots < nseg ? slots : nseg;
-  launch_segmented(keys, offsets, nseg, ascending ? 0 : -1, counter, (int)grid,
-                   (hipStream_t)stream);
+  launch_seg_prep(offsets, nseg, sc, st);
+  const int64_t items_bound = nseg;  // at most one item per segment
+  const int small_grid = (int)((int64_t)cus * 4 < items_bound ? (int64_t)cus * 4 : items_bound);
+  launch_seg_small(keys, offsets, sc, flip, small_grid, st);
+  const int M = ceil_log2(max_seg_len);
+  if (M > 13) {
+    const int grid = cus * 4;
+    launch_seg_tiles(false, keys, offsets, sc, 14, flip, grid, st);
+    const int fuse = g_fuse.load() < kSegFuseMax ? g_fuse.load() : kSegFuseMax;
+    for (int p = 14; p <= M; ++p) {
+      const int nb = p - 13;
+      const int npass = (nb + fuse - 1) / fuse;
+      int top = p - 1;
+      for (int i = 0; i < npass; ++i) {
+        const int left = top - 13 + 1;
+        const int f = (left + (npass - i) - 1) / (npass - i);
+        const int q = top - f + 1;
+        launch_seg_pass(f, i == 0, keys, offsets, sc, p, q, flip, grid, st);
+        top = q - 1;
+      }
+      launch_seg_tiles(true, keys, offsets, sc, p, flip, grid, st);
+    }
+  }
   return finish_launches();
 }
 

@@ -58,8 +58,11 @@ struct Prog {
   static constexpr int R = 1 << R_LOG_;
   static constexpr int NT = 1 << (L_ - R_LOG_);
   static constexpr int T = 1 << L_;
-  static constexpr Program value =
-      KIND_ == 0 ? make_tile_sort(L_, R_LOG_) : make_tile_merge(L_, R_LOG_);
+  static constexpr bool VEC = KIND_ < 2;  // 16-byte vector global I/O allowed
+  // Recompute each layout's thread base at its regroup (fewer registers,
+  // more ALU); used by the segment kernels, which run several programs.
+  static constexpr bool LEAN = KIND_ >= 2;
+  static constexpr Program value = make_program(L_, R_LOG_, KIND_);
   static_assert(value.ngroups <= kMaxGroups, "program too long");
 };
 
@@ -93,6 +96,7 @@ template <class PR, int GA, int GB>
 __device__ __forceinline__ void regroup(int32_t (&x)[PR::R], int32_t* lds, uint32_t tid) {
   constexpr Group A = PR::value.g[GA];
   constexpr Group B = PR::value.g[GB];
+  if constexpr (PR::LEAN) asm volatile("" : "+v"(tid));
   const uint32_t sa = swz(deposit<free_mask(A, PR::L)>(tid));
   const uint32_t sb = swz(deposit<free_mask(B, PR::L)>(tid));
   __syncthreads();
@@ -133,7 +137,7 @@ __device__ __forceinline__ void load_tile(int32_t (&x)[PR::R], const int32_t* __
   constexpr Group gr = PR::value.g[G];
   const uint32_t base = deposit<free_mask(gr, PR::L)>(tid);
   if (valid >= (uint32_t)PR::T) {
-    if constexpr (layout_is_vector4(gr)) {
+    if constexpr (PR::VEC && layout_is_vector4(gr)) {
       static_for<0, PR::R / 4>([&](auto Q) {
         constexpr uint32_t o = goff(gr, 4u * Q);
         const uint32_t i = slot_index<PR, G, 4u * Q>(base);
@@ -160,7 +164,7 @@ __device__ __forceinline__ void store_tile(const int32_t (&x)[PR::R], int32_t* _
   constexpr Group gr = PR::value.g[G];
   const uint32_t base = deposit<free_mask(gr, PR::L)>(tid);
   if (valid >= (uint32_t)PR::T) {
-    if constexpr (layout_is_vector4(gr)) {
+    if constexpr (PR::VEC && layout_is_vector4(gr)) {
       static_for<0, PR::R / 4>([&](auto Q) {
         constexpr uint32_t o = goff(gr, 4u * Q);
         const uint32_t i = slot_index<PR, G, 4u * Q>(base);
@@ -177,6 +181,38 @@ __device__ __forceinline__ void store_tile(const int32_t (&x)[PR::R], int32_t* _
       if (i < valid) tile[i] = x[J] ^ flip;
     });
   }
+}
+
+// Fused long-stride steps on 4 columns x 2^F rows of registers x[4 rho + c]: the mirror step (if MIRROR) on the top row
+// bit, then half-cleaners on the remaining row bits, highest first.
+template <int F, bool MIRROR>
+__device__ __forceinline__ void pass_steps(int32_t (&x)[4 << F]) {
+  constexpr int ROWS = 1 << F;
+  constexpr int TOP = ROWS >> 1;
+  if constexpr (MIRROR) {
+    static_for<0, TOP>([&](auto RHO) {
+      static_for<0, 4>([&](auto C) { cmpx(x[4 * RHO + C], x[4 * (RHO + TOP) + C]); });
+    });
+  }
+  constexpr int NB = MIRROR ? F - 1 : F;
+  static_for<0, NB>([&](auto I) {
+    constexpr int b = NB - 1 - I;
+    static_for<0, ROWS>([&](auto RHO) {
+      constexpr int rho = RHO;
+      constexpr int partner = rho ^ (1 << b);
+      if constexpr (rho < partner) {
+        // rho has bit b clear; in a mirrored upper half the order is reversed
+        constexpr bool low = !(MIRROR && (rho & TOP));
+        static_for<0, 4>([&](auto C) {
+          if constexpr (low) {
+            cmpx(x[4 * rho + C], x[4 * partner + C]);
+          } else {
+            cmpx(x[4 * partner + C], x[4 * rho + C]);
+          }
+        });
+      }
+    });
+  });
 }
 
 // Sort (KIND 0) or merge (KIND 1) one tile that starts at `tile` and holds

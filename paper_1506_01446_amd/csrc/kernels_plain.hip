@@ -122,38 +122,6 @@ __device__ __forceinline__ void pass_store_row(const int32_t* x, int32_t* __rest
   }
 }
 
-// The F steps on the registers: the mirror step (if MIRROR) on the top row
-// bit, then half-cleaners on the remaining row bits, highest first.
-template <int F, bool MIRROR>
-__device__ __forceinline__ void pass_steps(int32_t (&x)[4 << F]) {
-  constexpr int ROWS = 1 << F;
-  constexpr int TOP = ROWS >> 1;
-  if constexpr (MIRROR) {
-    static_for<0, TOP>([&](auto RHO) {
-      static_for<0, 4>([&](auto C) { cmpx(x[4 * RHO + C], x[4 * (RHO + TOP) + C]); });
-    });
-  }
-  constexpr int NB = MIRROR ? F - 1 : F;
-  static_for<0, NB>([&](auto I) {
-    constexpr int b = NB - 1 - I;
-    static_for<0, ROWS>([&](auto RHO) {
-      constexpr int rho = RHO;
-      constexpr int partner = rho ^ (1 << b);
-      if constexpr (rho < partner) {
-        // rho has bit b clear; in a mirrored upper half the order is reversed
-        constexpr bool low = !(MIRROR && (rho & TOP));
-        static_for<0, 4>([&](auto C) {
-          if constexpr (low) {
-            cmpx(x[4 * rho + C], x[4 * partner + C]);
-          } else {
-            cmpx(x[4 * partner + C], x[4 * rho + C]);
-          }
-        });
-      }
-    });
-  });
-}
-
 // Thread g0 + blockIdx.x * 256 + threadIdx.x.  BOUNDED == false: the
 // thread's whole 2^(q+F) block lies below n, every row moves as a 16-byte
 // vector and nothing is checked.  Because 256 divides 2^(q-2), a workgroup
@@ -281,7 +249,7 @@ __global__ __launch_bounds__(256) void step_kernel(int32_t* __restrict__ keys, u
 // ---------------------------------------------------------------------------
 // launchers
 
-constexpr int kTileRegLog = 5;  // 32 keys per thread in the tile kernels
+constexpr int kTileRegLog = kTileRegLogPlain;
 
 template <int L>
 static void launch_tile_L(int kind, int32_t* keys, uint32_t n, int32_t flip, uint32_t max_blocks,

@@ -1,130 +1,358 @@
-// Segmented sort: many independent arrays described by a CSR offset table,
-// sorted in one persistent launch.  Each segment runs the same flip network
-// as the single-array sort, padded virtually to its own power of two.
+// Segmented sort: many independent arrays described by a CSR offset table.
+// Every segment of length len runs the flip network of the single-array sort
+// on its own padded size 2^m (m = ceil(log2 len), its "class"), with the keys
+// past len left virtual.
 //
-// Workgroups pull segment indices from an atomic counter (in the library's
-// per-device scratch), so the launch needs no host knowledge of the segment
-// sizes.  A segment of up to 2^kSegTile keys is sorted in LDS; a longer one is
-// sorted by its workgroup in place: every 2^kSegTile chunk is sorted in LDS,
-// then for each further phase the long-stride steps run over the segment in
-// global memory (it stays in L2) and the short-stride tail runs per chunk in
-// LDS.  Within one workgroup, a barrier orders the global stores of one step
-// before the loads of the next.
+// Launch sequence (all on one stream, no host synchronisation):
+//   seg_prep_kernel      one workgroup classifies the segments: class
+//                        counts, segment ids bucketed by class (largest
+//                        first), prefix sums over the big segments
+//   seg_small_kernel     persistent; every work item is up to 256 / 2^(m-5)
+//                        segments of one class m <= 13, each sorted by its own
+//                        group of threads with the register tile programs
+//                        (scalar I/O, group-private LDS region); items are
+//                        taken from an atomic counter, largest class first
+//   seg_tile_kernel      tile sort of every 2^13-key tile of the big segments
+//                        (class > 13), grid-stride over a device-side tile list
+//   seg_pass_kernel and  per phase p > 13: the fused long-stride steps and the
+//   seg_tile_kernel      tile merges of the big segments of class >= p
+// The host only needs an upper bound on the largest class to know how many
+// phases to enqueue.
 #include "device.hpp"
 #include "launch.hpp"
 #include "segmented.hpp"
 
 namespace bitonic {
 
-constexpr int kSegTile = 13;
+constexpr int kSegTileLog = 13;
 constexpr int kSegThreads = 256;
 
-__device__ __forceinline__ int ceil_log2_u32(uint32_t n) {
-  return n <= 1 ? 0 : 32 - __clz(n - 1);
+__device__ __forceinline__ int ceil_log2_u64(uint64_t n) {
+  return n <= 1 ? 0 : 64 - __clzll(n - 1);
 }
 
-// One step of the network on LDS keys s[0, T): comparators of bit sb.
-__device__ __forceinline__ void seg_lds_step(int32_t* s, uint32_t T, int sb, bool mirror) {
-  for (uint32_t c = threadIdx.x; c < (T >> 1); c += kSegThreads) {
-    const uint32_t i = ((c >> sb) << (sb + 1)) | (c & ((1u << sb) - 1u));
-    const uint32_t j = mirror ? (i ^ ((2u << sb) - 1u)) : (i | (1u << sb));
-    const int32_t a = s[i], b = s[j];
-    s[i] = min(a, b);
-    s[j] = max(a, b);
-  }
+// Small classes 13, 12, ..., 6, and "<= 5" (index 8): segments per item.
+__device__ __forceinline__ int small_class_of_index(int i) { return 13 - i; }  // 5 for i == 8
+__device__ __forceinline__ uint32_t small_per_item(int cls) {
+  return cls <= 5 ? 256u : (256u >> (cls - 5));
+}
+
+// ---------------------------------------------------------------------------
+// prep
+
+__global__ __launch_bounds__(1024) void seg_prep_kernel(const int64_t* __restrict__ offsets,
+                                                        int64_t nseg, SegMeta* __restrict__ meta,
+                                                        uint32_t* __restrict__ small_ids,
+                                                        uint32_t* __restrict__ big_ids,
+                                                        uint64_t* __restrict__ big_keys,
+                                                        uint64_t* __restrict__ big_tiles) {
+  __shared__ uint32_t cnt[32];
+  __shared__ uint32_t cur[32];
+  __shared__ uint64_t part_k[1024];
+  __shared__ uint64_t part_t[1024];
+  __shared__ uint32_t nbig_s;
+  const uint32_t tid = threadIdx.x;
+  if (tid < 32) cnt[tid] = 0;
   __syncthreads();
-}
-
-// Load `valid` keys (pad to T with the sentinel) into LDS.
-__device__ __forceinline__ void seg_lds_load(int32_t* s, const int32_t* src, uint32_t T,
-                                             uint32_t valid, int32_t flip) {
-  for (uint32_t i = threadIdx.x; i < T; i += kSegThreads)
-    s[i] = i < valid ? (src[i] ^ flip) : kPad;
-  __syncthreads();
-}
-
-__device__ __forceinline__ void seg_lds_store(const int32_t* s, int32_t* dst, uint32_t valid,
-                                              int32_t flip) {
-  for (uint32_t i = threadIdx.x; i < valid; i += kSegThreads) dst[i] = s[i] ^ flip;
-  __syncthreads();
-}
-
-// One step over a whole segment in global memory (virtual padding at len).
-__device__ __forceinline__ void seg_global_step(int32_t* a, uint32_t len, uint32_t half, int sb,
-                                                bool mirror, int32_t flip) {
-  for (uint32_t c = threadIdx.x; c < half; c += kSegThreads) {
-    const uint32_t i = ((c >> sb) << (sb + 1)) | (c & ((1u << sb) - 1u));
-    const uint32_t j = mirror ? (i ^ ((2u << sb) - 1u)) : (i | (1u << sb));
-    if (j >= len) continue;
-    const int32_t x = a[i] ^ flip, y = a[j] ^ flip;
-    if (x > y) {
-      a[i] = y ^ flip;
-      a[j] = x ^ flip;
-    }
-  }
-  __syncthreads();
-}
-
-__global__ __launch_bounds__(kSegThreads) void seg_persistent_kernel(
-    int32_t* __restrict__ keys, const int64_t* __restrict__ offsets, int64_t nseg, int32_t flip,
-    uint32_t* __restrict__ counter) {
-  __shared__ int32_t s[1 << kSegTile];
-  __shared__ int64_t item;
-  for (;;) {
-    if (threadIdx.x == 0) item = (int64_t)atomicAdd(counter, 1u);
-    __syncthreads();
-    const int64_t seg = item;
-    __syncthreads();
-    if (seg >= nseg) break;
-    const int64_t off = offsets[seg];
-    const uint32_t len = (uint32_t)(offsets[seg + 1] - off);
+  for (int64_t s = tid; s < nseg; s += 1024) {
+    const uint64_t len = (uint64_t)(offsets[s + 1] - offsets[s]);
     if (len <= 1) continue;
-    int32_t* a = keys + off;
-    const int m = ceil_log2_u32(len);
-    if (m <= kSegTile) {
-      const uint32_t T = 1u << m;
-      seg_lds_load(s, a, T, len, flip);
-      for (int p = 1; p <= m; ++p) {
-        seg_lds_step(s, T, p - 1, true);
-        for (int sb = p - 2; sb >= 0; --sb) seg_lds_step(s, T, sb, false);
-      }
-      seg_lds_store(s, a, len, flip);
-      continue;
+    int c = ceil_log2_u64(len);
+    if (c < 5) c = 5;
+    atomicAdd(&cnt[c], 1u);
+  }
+  __syncthreads();
+  if (tid == 0) {
+    // small buckets, class 13 first
+    uint32_t pos = 0, items = 0;
+    for (int i = 0; i < kSmallClasses; ++i) {
+      const int c = small_class_of_index(i);
+      meta->small_start[i] = pos;
+      meta->small_count[i] = cnt[c];
+      meta->item_prefix[i] = items;
+      cur[c] = pos;
+      pos += cnt[c];
+      const uint32_t per = small_per_item(c);
+      items += (cnt[c] + per - 1) / per;
     }
-    constexpr uint32_t T = 1u << kSegTile;
-    const uint32_t nchunks = (len + T - 1) >> kSegTile;
-    for (uint32_t ch = 0; ch < nchunks; ++ch) {
-      const uint32_t c0 = ch << kSegTile;
-      const uint32_t valid = min(len - c0, T);
-      seg_lds_load(s, a + c0, T, valid, flip);
-      for (int p = 1; p <= kSegTile; ++p) {
-        seg_lds_step(s, T, p - 1, true);
-        for (int sb = p - 2; sb >= 0; --sb) seg_lds_step(s, T, sb, false);
-      }
-      seg_lds_store(s, a + c0, valid, flip);
+    meta->item_prefix[kSmallClasses] = items;
+    meta->small_items = items;
+    meta->small_counter = 0;
+    // big buckets, largest class first
+    uint32_t bpos = 0;
+    int maxc = 0;
+    for (int c = 31; c > kSegTileLog; --c) {
+      cur[c] = bpos;
+      bpos += cnt[c];
+      meta->big_ge[c] = bpos;  // segments of class >= c
+      if (cnt[c] && !maxc) maxc = c;
     }
-    const uint32_t half = 1u << (m - 1);
-    for (int p = kSegTile + 1; p <= m; ++p) {
-      for (int sb = p - 1; sb >= kSegTile; --sb) seg_global_step(a, len, half, sb, sb == p - 1, flip);
-      for (uint32_t ch = 0; ch < nchunks; ++ch) {
-        const uint32_t c0 = ch << kSegTile;
-        const uint32_t valid = min(len - c0, T);
-        seg_lds_load(s, a + c0, T, valid, flip);
-        for (int sb = kSegTile - 1; sb >= 0; --sb) seg_lds_step(s, T, sb, false);
-        seg_lds_store(s, a + c0, valid, flip);
-      }
+    for (int c = 0; c <= kSegTileLog; ++c) meta->big_ge[c] = bpos;
+    meta->big_ge[32] = 0;
+    meta->nbig = bpos;
+    meta->max_class = maxc;
+    nbig_s = bpos;
+  }
+  __syncthreads();
+  for (int64_t s = tid; s < nseg; s += 1024) {
+    const uint64_t len = (uint64_t)(offsets[s + 1] - offsets[s]);
+    if (len <= 1) continue;
+    int c = ceil_log2_u64(len);
+    if (c < 5) c = 5;
+    const uint32_t slot = atomicAdd(&cur[c], 1u);
+    if (c <= kSegTileLog)
+      small_ids[slot] = (uint32_t)s;
+    else
+      big_ids[slot] = (uint32_t)s;
+  }
+  __syncthreads();
+  // exclusive prefix sums over the big list (padded keys, real tiles)
+  const uint32_t nbig = nbig_s;
+  const uint32_t chunk = (nbig + 1023) / 1024;
+  const uint32_t b0 = tid * chunk;
+  const uint32_t b1 = min(b0 + chunk, nbig);
+  uint64_t sk = 0, st = 0;
+  for (uint32_t i = b0; i < b1; ++i) {
+    const uint32_t s = big_ids[i];
+    const uint64_t len = (uint64_t)(offsets[s + 1] - offsets[s]);
+    sk += 1ull << ceil_log2_u64(len);
+    st += (len + (1u << kSegTileLog) - 1) >> kSegTileLog;
+  }
+  part_k[tid] = sk;
+  part_t[tid] = st;
+  __syncthreads();
+  if (tid == 0) {
+    uint64_t ak = 0, at = 0;
+    for (int i = 0; i < 1024; ++i) {
+      const uint64_t k = part_k[i], t = part_t[i];
+      part_k[i] = ak;
+      part_t[i] = at;
+      ak += k;
+      at += t;
+    }
+    big_keys[nbig] = ak;
+    big_tiles[nbig] = at;
+  }
+  __syncthreads();
+  sk = part_k[tid];
+  st = part_t[tid];
+  for (uint32_t i = b0; i < b1; ++i) {
+    const uint32_t s = big_ids[i];
+    const uint64_t len = (uint64_t)(offsets[s + 1] - offsets[s]);
+    big_keys[i] = sk;
+    big_tiles[i] = st;
+    sk += 1ull << ceil_log2_u64(len);
+    st += (len + (1u << kSegTileLog) - 1) >> kSegTileLog;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// small segments
+
+// Not inlined: each class's program keeps its own register allocation
+// instead of the kernel carrying the union of all of them.
+template <int L>
+__device__ __attribute__((noinline)) void seg_small_item(int32_t* __restrict__ keys,
+                                               const int64_t* __restrict__ offsets,
+                                               const uint32_t* __restrict__ ids, uint32_t first,
+                                               uint32_t count, int32_t flip, int32_t* lds) {
+  using PR = Prog<L, kTileRegLogSeg, 2>;
+  constexpr uint32_t NT = PR::NT;
+  const uint32_t grp = threadIdx.x / NT;
+  const uint32_t ltid = threadIdx.x % NT;
+  int32_t* p = keys;
+  uint32_t len = 0;
+  if (grp < count) {
+    const uint32_t s = ids[first + grp];
+    const int64_t off = offsets[s];
+    p = keys + off;
+    len = (uint32_t)(offsets[s + 1] - off);
+  }
+  tile_program<PR>(p, len, flip, lds + grp * PR::T, ltid);
+}
+
+__global__ __launch_bounds__(kSegThreads) void seg_small_kernel(
+    int32_t* __restrict__ keys, const int64_t* __restrict__ offsets, SegMeta* __restrict__ meta,
+    const uint32_t* __restrict__ small_ids, int32_t flip) {
+  __shared__ int32_t lds[kSegThreads << kTileRegLogSeg];
+  __shared__ uint32_t item_s;
+  const uint32_t total = meta->small_items;
+  for (;;) {
+    if (threadIdx.x == 0) item_s = atomicAdd(&meta->small_counter, 1u);
+    __syncthreads();
+    const uint32_t item = item_s;
+    __syncthreads();
+    if (item >= total) break;
+    int ci = 0;
+    while (ci + 1 < kSmallClasses && meta->item_prefix[ci + 1] <= item) ++ci;
+    const int cls = small_class_of_index(ci);
+    const uint32_t per = small_per_item(cls);
+    const uint32_t k = item - meta->item_prefix[ci];
+    const uint32_t first = meta->small_start[ci] + k * per;
+    const uint32_t left = meta->small_count[ci] - k * per;
+    const uint32_t count = left < per ? left : per;
+    switch (cls) {
+      case 13: seg_small_item<13>(keys, offsets, small_ids, first, count, flip, lds); break;
+      case 12: seg_small_item<12>(keys, offsets, small_ids, first, count, flip, lds); break;
+      case 11: seg_small_item<11>(keys, offsets, small_ids, first, count, flip, lds); break;
+      case 10: seg_small_item<10>(keys, offsets, small_ids, first, count, flip, lds); break;
+      case 9: seg_small_item<9>(keys, offsets, small_ids, first, count, flip, lds); break;
+      case 8: seg_small_item<8>(keys, offsets, small_ids, first, count, flip, lds); break;
+      case 7: seg_small_item<7>(keys, offsets, small_ids, first, count, flip, lds); break;
+      case 6: seg_small_item<6>(keys, offsets, small_ids, first, count, flip, lds); break;
+      default: seg_small_item<5>(keys, offsets, small_ids, first, count, flip, lds); break;
     }
   }
 }
 
-__global__ void seg_reset_kernel(uint32_t* counter) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0u;
+// ---------------------------------------------------------------------------
+// big segments
+
+// Largest i in [0, cnt) with prefix[i] <= v (prefix nondecreasing, prefix[0] = 0).
+__device__ __forceinline__ uint32_t upper_index(const uint64_t* __restrict__ prefix, uint32_t cnt,
+                                                uint64_t v) {
+  uint32_t lo = 0, hi = cnt;  // answer in [lo, hi)
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (prefix[mid] <= v) lo = mid;
+    else hi = mid;
+  }
+  return lo;
 }
 
-void launch_segmented(int32_t* keys, const int64_t* offsets, int64_t nseg, int32_t flip,
-                      uint32_t* counter, int grid, hipStream_t st) {
-  seg_reset_kernel<<<1, 64, 0, st>>>(counter);
-  seg_persistent_kernel<<<grid, kSegThreads, 0, st>>>(keys, offsets, nseg, flip, counter);
+// Every 2^13-key tile of the big segments of class >= cls_min: sort
+// (KIND 2) or merge (KIND 3).
+template <int KIND>
+__global__ __launch_bounds__(kSegThreads) void seg_tile_kernel(
+    int32_t* __restrict__ keys, const int64_t* __restrict__ offsets,
+    const SegMeta* __restrict__ meta, const uint32_t* __restrict__ big_ids,
+    const uint64_t* __restrict__ big_tiles, int cls_min, int32_t flip) {
+  using PR = Prog<kSegTileLog, kTileRegLogSeg, KIND>;
+  static_assert(PR::NT == kSegThreads, "one tile per workgroup");
+  __shared__ int32_t lds[PR::T];
+  const uint32_t cnt = meta->big_ge[cls_min];
+  const uint64_t total = big_tiles[cnt];
+  for (uint64_t u = blockIdx.x; u < total; u += gridDim.x) {
+    // recompute the layouts' thread bases per tile instead of holding them
+    uint32_t tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    const uint32_t i = upper_index(big_tiles, cnt, u);
+    const uint64_t tile = u - big_tiles[i];
+    const uint32_t s = big_ids[i];
+    const int64_t off = offsets[s];
+    const uint64_t len = (uint64_t)(offsets[s + 1] - off);
+    const uint64_t t0 = tile << kSegTileLog;
+    const uint64_t left = len - t0;
+    const uint32_t valid = left < (uint64_t)PR::T ? (uint32_t)left : (uint32_t)PR::T;
+    tile_program<PR>(keys + off + t0, valid, flip, lds, tid);
+    __syncthreads();  // LDS reuse by the next tile
+  }
+}
+
+// Segment-local index of register slot (RHO, J) of a pass unit: row RHO of
+// the block at blk, column c0 + threadIdx.x + 256 J (mirrored rows: the
+// mirror image inside the block).
+template <int F, bool MIRROR, int RHO, int J>
+__device__ __forceinline__ uint32_t seg_pass_index(uint32_t blk, uint32_t c0, int q) {
+  constexpr int ROWS = 1 << F;
+  constexpr int TOP = ROWS >> 1;
+  const uint32_t col = c0 + threadIdx.x + 256u * (uint32_t)J;
+  if constexpr (MIRROR && (RHO & TOP))
+    return blk + ((uint32_t)((ROWS - 1) ^ (RHO & (TOP - 1))) << q) + (((1u << q) - 1u) - col);
+  else
+    return blk + ((uint32_t)RHO << q) + col;
+}
+
+// F fused long-stride steps (bits q+F-1 .. q) over the big segments of class
+// >= cls.  A workgroup unit is 1024 consecutive columns x 2^F rows of one
+// 2^(q+F)-key block of one segment; thread t holds columns c0 + t + 256 j
+// (j = 0..3), so every load and store of a wave is 256 consecutive bytes.
+template <int F, bool MIRROR>
+__global__ __launch_bounds__(kSegThreads) void seg_pass_kernel(
+    int32_t* __restrict__ keys, const int64_t* __restrict__ offsets,
+    const SegMeta* __restrict__ meta, const uint32_t* __restrict__ big_ids,
+    const uint64_t* __restrict__ big_keys, int cls, int q, int32_t flip) {
+  constexpr int ROWS = 1 << F;
+  constexpr int TOP = ROWS >> 1;
+  constexpr int UNIT_LOG = 10 + F;  // keys per unit = 1024 columns x 2^F rows
+  const uint32_t cnt = meta->big_ge[cls];
+  const uint64_t total = big_keys[cnt] >> UNIT_LOG;
+  for (uint64_t u = blockIdx.x; u < total; u += gridDim.x) {
+    const uint64_t key0 = u << UNIT_LOG;
+    const uint32_t i = upper_index(big_keys, cnt, key0);
+    const uint64_t lk = key0 - big_keys[i];  // unit's first key, segment-local
+    const uint32_t s = big_ids[i];
+    const int64_t off = offsets[s];
+    const uint32_t len = (uint32_t)(offsets[s + 1] - off);
+    int32_t* a = keys + off;
+    // unit -> block and column run: a block holds 2^q / 1024 units;
+    // segment-local indices fit 32 bits (segments hold < 2^31 keys)
+    const uint32_t lu = (uint32_t)(lk >> UNIT_LOG);
+    const int upb_log = q - 10;
+    const uint32_t blk = (lu >> upb_log) << (q + F);
+    const uint32_t c0 = (lu & ((1u << upb_log) - 1u)) << 10;
+    int32_t x[4 * ROWS];
+    static_for<0, ROWS>([&](auto RHO) {
+      static_for<0, 4>([&](auto J) {
+        const uint32_t idx = seg_pass_index<F, MIRROR, RHO, J>(blk, c0, q);
+        x[4 * RHO + J] = idx < len ? (a[idx] ^ flip) : kPad;
+      });
+    });
+    pass_steps<F, MIRROR>(x);
+    static_for<0, ROWS>([&](auto RHO) {
+      static_for<0, 4>([&](auto J) {
+        const uint32_t idx = seg_pass_index<F, MIRROR, RHO, J>(blk, c0, q);
+        if (idx < len) a[idx] = x[4 * RHO + J] ^ flip;
+      });
+    });
+  }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+
+void launch_seg_prep(const int64_t* offsets, int64_t nseg, const SegScratch& sc, hipStream_t st) {
+  seg_prep_kernel<<<1, 1024, 0, st>>>(offsets, nseg, sc.meta, sc.small_ids, sc.big_ids,
+                                      sc.big_keys, sc.big_tiles);
+}
+
+void launch_seg_small(int32_t* keys, const int64_t* offsets, const SegScratch& sc, int32_t flip,
+                      int grid, hipStream_t st) {
+  seg_small_kernel<<<grid, kSegThreads, 0, st>>>(keys, offsets, sc.meta, sc.small_ids, flip);
+}
+
+void launch_seg_tiles(bool merge, int32_t* keys, const int64_t* offsets, const SegScratch& sc,
+                      int cls_min, int32_t flip, int grid, hipStream_t st) {
+  if (merge)
+    seg_tile_kernel<3><<<grid, kSegThreads, 0, st>>>(keys, offsets, sc.meta, sc.big_ids,
+                                                     sc.big_tiles, cls_min, flip);
+  else
+    seg_tile_kernel<2><<<grid, kSegThreads, 0, st>>>(keys, offsets, sc.meta, sc.big_ids,
+                                                     sc.big_tiles, cls_min, flip);
+}
+
+template <int F>
+static void launch_seg_pass_F(bool mirror, int32_t* keys, const int64_t* offsets,
+                              const SegScratch& sc, int cls, int q, int32_t flip, int grid,
+                              hipStream_t st) {
+  if (mirror)
+    seg_pass_kernel<F, true><<<grid, kSegThreads, 0, st>>>(keys, offsets, sc.meta, sc.big_ids,
+                                                           sc.big_keys, cls, q, flip);
+  else
+    seg_pass_kernel<F, false><<<grid, kSegThreads, 0, st>>>(keys, offsets, sc.meta, sc.big_ids,
+                                                            sc.big_keys, cls, q, flip);
+}
+
+void launch_seg_pass(int f, bool mirror, int32_t* keys, const int64_t* offsets,
+                     const SegScratch& sc, int cls, int q, int32_t flip, int grid,
+                     hipStream_t st) {
+  switch (f) {
+    case 1: launch_seg_pass_F<1>(mirror, keys, offsets, sc, cls, q, flip, grid, st); break;
+    case 2: launch_seg_pass_F<2>(mirror, keys, offsets, sc, cls, q, flip, grid, st); break;
+    case 3: launch_seg_pass_F<3>(mirror, keys, offsets, sc, cls, q, flip, grid, st); break;
+    case 4: launch_seg_pass_F<4>(mirror, keys, offsets, sc, cls, q, flip, grid, st); break;
+    default: break;
+  }
 }
 
 }  // namespace bitonic

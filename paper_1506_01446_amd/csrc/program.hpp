@@ -85,6 +85,16 @@ constexpr Group io_group(int L, int r) {
   return G;
 }
 
+// Layout for scalar global loads and stores (keys not 16-byte aligned, e.g.
+// segments): the registers hold the top r tile bits, so lanes step through
+// consecutive keys.
+constexpr Group io_scalar_group(int L, int r) {
+  Group G{};
+  G.r = r;
+  for (int m = 0; m < r; ++m) G.v[m] = 1u << (L - 1 - m);
+  return G;
+}
+
 constexpr Group blocked_group(int r) {
   Group G{};
   G.r = r;
@@ -156,6 +166,45 @@ constexpr Program make_tile_merge(int L, int r) {
   add_merge_bits(P, L - 1 - (r - 2), false);
   P.g[P.ngroups++] = io_group(L, r);
   return P;
+}
+
+// Phases 1..L with scalar I/O.  A tile of L == r bits is one thread's
+// registers: a single blocked group and no LDS.
+constexpr Program make_tile_sort_scalar(int L, int r) {
+  Program P{};
+  P.L = L;
+  P.r = r;
+  if (L > r) P.g[P.ngroups++] = io_scalar_group(L, r);
+  Group g0 = blocked_group(r);
+  const int pin = L < r ? L : r;
+  for (int p = 1; p <= pin; ++p) {
+    g0.d[g0.nsteps++] = (1u << p) - 1u;
+    for (int b = p - 2; b >= 0; --b) g0.d[g0.nsteps++] = 1u << b;
+  }
+  P.g[P.ngroups++] = g0;
+  for (int p = r + 1; p <= L; ++p) add_merge_bits(P, p - 1, true);
+  if (L > r) P.g[P.ngroups++] = io_scalar_group(L, r);
+  return P;
+}
+
+// Strides 2^(L-1) .. 1 with scalar I/O: the first merge group's layout (the
+// top r bits in registers) is already the scalar I/O layout.
+constexpr Program make_tile_merge_scalar(int L, int r) {
+  Program P{};
+  P.L = L;
+  P.r = r;
+  add_merge_bits(P, L - 1, false);
+  P.g[P.ngroups++] = io_scalar_group(L, r);
+  return P;
+}
+
+// Program kinds: 0 sort, 1 merge (16-byte vector I/O); 2 sort, 3 merge
+// (scalar I/O).
+constexpr Program make_program(int L, int r, int kind) {
+  return kind == 0   ? make_tile_sort(L, r)
+         : kind == 1 ? make_tile_merge(L, r)
+         : kind == 2 ? make_tile_sort_scalar(L, r)
+                     : make_tile_merge_scalar(L, r);
 }
 
 constexpr bool layout_is_vector4(const Group& G) {

@@ -1,4 +1,4 @@
-// Host-side launcher of the segmented sort (internal interface).
+// Segmented sort: scratch layout and launchers (internal interface).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -6,9 +6,61 @@
 
 namespace bitonic {
 
-// Enqueue the counter reset and the persistent segmented kernel with `grid`
-// workgroups.  `counter` is a device word of the library's scratch.
-void launch_segmented(int32_t* keys, const int64_t* offsets, int64_t nseg, int32_t flip,
-                      uint32_t* counter, int grid, hipStream_t st);
+constexpr int kTileRegLogSeg = 5;  // 32 keys per thread
+constexpr int kSmallClasses = 9;   // classes 13, 12, ..., 6 and "<= 5"
+constexpr int kSegFuseMax = 3;
+
+// Written by the prep kernel, read by the others (device memory).
+struct SegMeta {
+  uint32_t small_counter;  // work queue of the small-segment kernel
+  uint32_t small_items;    // work items in all
+  uint32_t nbig;           // segments of class > 13
+  int32_t max_class;       // largest class present (0 if no big segment)
+  uint32_t small_start[kSmallClasses];  // first id of each small class bucket
+  uint32_t small_count[kSmallClasses];
+  uint32_t item_prefix[kSmallClasses + 1];
+  uint32_t big_ge[33];     // number of big segments of class >= c
+};
+
+// Pointers into the scratch buffer of one segmented call (device memory).
+struct SegScratch {
+  SegMeta* meta;
+  uint32_t* small_ids;   // nseg entries, bucketed by class, class 13 first
+  uint32_t* big_ids;     // nseg entries, largest class first
+  uint64_t* big_keys;    // nseg + 1: exclusive prefix of padded sizes
+  uint64_t* big_tiles;   // nseg + 1: exclusive prefix of 2^13-key tiles
+};
+
+inline size_t seg_scratch_bytes(int64_t nseg) {
+  const size_t n = (size_t)nseg + 1;
+  return 1024 + 2 * ((4 * n + 255) & ~size_t(255)) + 2 * ((8 * n + 255) & ~size_t(255));
+}
+
+inline SegScratch seg_scratch_carve(void* base, int64_t nseg) {
+  const size_t n = (size_t)nseg + 1;
+  char* p = static_cast<char*>(base);
+  SegScratch s;
+  s.meta = reinterpret_cast<SegMeta*>(p);
+  p += 1024;
+  s.small_ids = reinterpret_cast<uint32_t*>(p);
+  p += (4 * n + 255) & ~size_t(255);
+  s.big_ids = reinterpret_cast<uint32_t*>(p);
+  p += (4 * n + 255) & ~size_t(255);
+  s.big_keys = reinterpret_cast<uint64_t*>(p);
+  p += (8 * n + 255) & ~size_t(255);
+  s.big_tiles = reinterpret_cast<uint64_t*>(p);
+  return s;
+}
+
+void launch_seg_prep(const int64_t* offsets, int64_t nseg, const SegScratch& sc, hipStream_t st);
+void launch_seg_small(int32_t* keys, const int64_t* offsets, const SegScratch& sc, int32_t flip,
+                      int grid, hipStream_t st);
+// Tile sort (merge == false) or tile merge of the big segments of class >= cls_min.
+void launch_seg_tiles(bool merge, int32_t* keys, const int64_t* offsets, const SegScratch& sc,
+                      int cls_min, int32_t flip, int grid, hipStream_t st);
+// f fused steps on bits q+f-1 .. q of the big segments of class >= cls.
+void launch_seg_pass(int f, bool mirror, int32_t* keys, const int64_t* offsets,
+                     const SegScratch& sc, int cls, int q, int32_t flip, int grid,
+                     hipStream_t st);
 
 }  // namespace bitonic

@@ -26,7 +26,7 @@ static uint32_t deposit_rt(uint32_t mask, uint32_t t) {
 static uint32_t swz(uint32_t i) { return i ^ ((i >> 5) & 31u); }
 
 static Program make(int L, int r, int kind) {
-  return kind == 0 ? make_tile_sort(L, r) : make_tile_merge(L, r);
+  return make_program(L, r, kind);
 }
 
 extern "C" {

@@ -199,3 +199,35 @@ def test_segmented_equals_looped():
         B.bitonic_sort_i32(t[off[s]:off[s + 1]], True)
     torch.cuda.synchronize()
     assert np.array_equal(batched, t.cpu().numpy())
+
+
+def test_segmented_big_classes_unaligned():
+    """Segments spanning classes 14..21 next to tiny ones, starting at
+    offsets that are not 16-byte aligned, both directions, bounded and not."""
+    lens = np.array([(1 << 14) + 1, 1 << 15, (1 << 15) + 7, (1 << 17) - 3, 1 << 18, 300001,
+                     (1 << 20) + 5, 5, 0, 8193, 2, (1 << 21) + 11], dtype=np.int64)
+    off = W.offsets_from_lengths(lens) + 3
+    keys = W.uniform_i32(41, int(off[-1]) + 9)
+    for asc in (True, False):
+        want = keys.copy()
+        want[off[0]:off[-1]] = O.sort_segmented_i32(keys[off[0]:off[-1]], off - off[0], asc)
+        assert np.array_equal(gpu_sort_segmented(keys, off, asc), want), asc
+        got = gpu_sort_segmented(keys, off, asc, max_seg_len=int(lens.max()))
+        assert np.array_equal(got, want), ("bounded", asc)
+
+
+def test_segmented_many_small():
+    lens = (W.splitmix64(77, 0, 20000) % np.uint64(70)).astype(np.int64)
+    off = W.offsets_from_lengths(lens)
+    keys = W.uniform_i32(78, int(off[-1]))
+    for asc in (True, False):
+        got = gpu_sort_segmented(keys, off, asc, max_seg_len=int(lens.max()))
+        assert np.array_equal(got, O.sort_segmented_i32(keys, off, asc)), asc
+
+
+def test_segmented_repeated_calls_reuse_scratch():
+    """Calls of growing and shrinking size on one stream (scratch reuse)."""
+    for nseg, seed in ((10, 1), (5000, 2), (3, 3), (9000, 4)):
+        keys, off = W.batched_workload(nseg=nseg, seed=seed, max_log2=15)
+        got = gpu_sort_segmented(keys, off, True)
+        assert np.array_equal(got, O.sort_segmented_i32(keys, off, True)), nseg

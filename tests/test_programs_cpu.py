@@ -86,3 +86,26 @@ def test_lds_bank_conflicts(emu, L, kind):
     # no half-wave access of any regrouping puts two lanes on one bank
     assert emu.worst_bank_conflict(L, 5, kind, 32) == 1
     assert emu.worst_bank_conflict(L, 5, kind, 64) == 1
+
+
+@pytest.mark.parametrize("L", list(range(5, 14)))
+def test_scalar_io_programs(emu, L):
+    """Programs with scalar I/O (used for segments, any alignment): sort and
+    merge, full and partial tiles, down to one thread per 32-key tile."""
+    T = 1 << L
+    for valid in sorted({T, T - 1, T // 2 + 3, 1, 2}):
+        if valid < 1:
+            continue
+        keys = W.uniform_i32(L * 1000 + valid, T)
+        out, steps = _run(emu, L, 5, 2, keys, valid)
+        assert steps == L * (L + 1) // 2
+        assert (out[:valid] == np.sort(keys[:valid])).all()
+        assert (out[valid:] == keys[valid:]).all()
+    keys = W.uniform_i32(L + 77, T)
+    cut = T // 3
+    bit = np.concatenate([np.sort(keys[:cut]), np.sort(keys[cut:])[::-1]])
+    out, steps = _run(emu, L, 5, 3, bit, T)
+    assert steps == L and (out == np.sort(keys)).all()
+    if L > 5:
+        assert emu.worst_bank_conflict(L, 5, 2, 32) == 1
+        assert emu.worst_bank_conflict(L, 5, 3, 32) == 1
