@@ -12,9 +12,13 @@ Printed JSON line (one line, rank 0):
   value        Gkeys/s at n = 2^24
   roofline     the kernel class taking most of a sort's time: algorithmic
                bytes per launch (8 n: every key read and written once)
-               over its average launch duration, timed with HIP events
-               recorded between the launches of extra sorts run right after
-               the timed steps, against the 8 TB/s HBM peak
+               over its average launch duration, against the 8 TB/s HBM
+               peak.  The duration is timed live with two HIP events on the
+               launch stream around repeated back-to-back launches of each
+               kernel of the plan, right after the timed steps.  `traffic` is
+               the HBM bytes per launch from the committed rocprofv3 counter
+               summary (profiles/sort_n<n>_hbm_traffic.txt), null when the
+               kernel sources changed since those counters were taken
   cpu_baseline the CPU oracle (std::sort, one thread) on a bounded sample
   extra        n = 10,000,000, per-kernel table, batched vs looped
                segmented sorting, serving latency when run
@@ -45,7 +49,7 @@ def parse():
     ap.add_argument("--fuse", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
-    ap.add_argument("--serve-seconds", type=float, default=0.0)
+    ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--out", default="")
     ap.add_argument("--counters", action="store_true",
                     help="short run for rocprofv3 --pmc: one n-key device copy (the "
@@ -119,6 +123,50 @@ def kernel_table(torch, B, src, plan, repeats=10):
                      "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)})
     rows.sort(key=lambda r: -r["total_us_per_sort"])
     return rows
+
+
+def kernel_source_hash() -> str:
+    """sha256[:16] over the library's kernel sources (names and contents)."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_1506_01446_amd", "csrc", "*"))):
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+KERNEL_CLASS = {"tile_kernel<13, 5, 1>": "tile_merge", "tile_kernel<13, 5, 0>": "tile_sort"}
+
+
+def committed_traffic(kernel: str, n: int):
+    """HBM bytes per launch of a kernel class from the committed rocprofv3
+    counter summary (profiles/), or None if there is none for this n or the
+    kernel sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"sort_n{n}_hbm_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    rows, digest = [], None
+    with open(path) as f:
+        for ln in f:
+            if ln.startswith("# kernel sources sha256[:16]:"):
+                digest = ln.rsplit(":", 1)[1].strip()
+            elif ln.strip() and not ln.startswith("#"):
+                # name (contains commas), fetch_kib, write_kib, bytes, ratio
+                rows.append([c.strip() for c in ln.rsplit(",", 4)])
+    if digest != kernel_source_hash():
+        return None
+    vals = []
+    for r in rows:
+        name = r[0]
+        cls = KERNEL_CLASS.get(name)
+        if cls is None and name.startswith("global_pass_kernel<"):
+            f_, _, bounded = name[len("global_pass_kernel<"):-1].split(", ")
+            cls = f"global_pass_f{f_}" if bounded == "false" else None
+        if cls == kernel:
+            vals.append(float(r[3]))
+    return round(sum(vals) / len(vals)) if vals else None
 
 
 def cpu_baseline(n):
@@ -251,7 +299,8 @@ def main():
     dom = rows[0]
     roofline = {"bound": "hbm", "kernel": dom["kernel"],
                 "achieved": dom["algorithmic_GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(dom["algorithmic_GBps"] / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(dom["algorithmic_GBps"] / HBM_PEAK_GBS, 4),
+                "traffic": committed_traffic(dom["kernel"], n),
                 "bytes_per_launch": 8 * n}
     gp = [r for r in rows if r["kernel"].startswith("global_pass")]
     log(f"[bench] kernels: {json.dumps(rows)}")

@@ -207,13 +207,45 @@ int bitonic_sort_plan_launches_i32(int32_t* keys, int64_t n, int ascending,
 /*
  * Tuning.  bitonic_set_tuning(tile_log2, fuse, merge_blocks_per_cu) changes
  * the library's default plan for BITONIC_PLAN_AUTO (values as in
- * bitonic_plan; 0 keeps the current value).  bitonic_load_tuning reads the
- * same values from a text file written by the autotuner ("tile_log2 <t>",
- * "fuse <f>", "merge_blocks_per_cu <b>" lines).  Both return BITONIC_OK or
- * BITONIC_EINVAL; they are not thread-safe with concurrent sorts.
+ * bitonic_plan; 0 keeps the current value).  bitonic_set_tuning_value sets
+ * one value by name: "tile_log2", "fuse", "merge_blocks_per_cu" (as in
+ * bitonic_plan) or "seg_blocks_per_cu" (1..16, workgroups per compute unit of
+ * the persistent small-segment kernel); bitonic_get_tuning_value reads one.
+ * bitonic_load_tuning reads "<name> <value>" lines (the autotuner's output
+ * file).  All return BITONIC_OK or BITONIC_EINVAL; they are not thread-safe
+ * with concurrent sorts.
  */
 int bitonic_set_tuning(int tile_log2, int fuse, int merge_blocks_per_cu);
+int bitonic_set_tuning_value(const char* key, int value);
+int bitonic_get_tuning_value(const char* key, int* value);
 int bitonic_load_tuning(const char* path);
+
+/*
+ * HIP graphs.  A bitonic_graph is a captured launch sequence, replayed with
+ * one call and no per-kernel host work.  The device pointers (and n, nseg,
+ * the bound, the direction and the plan) are fixed at capture; the keys and
+ * offsets they point to may change between replays (an offsets table of
+ * fixed capacity can describe fewer segments by making the rest empty).
+ *
+ * bitonic_graph_capture_sort_i32: the single-array sort of keys[0, n).
+ * bitonic_graph_capture_segmented_i32: the segmented sort with a host bound
+ *   max_seg_len >= 1 on the segment length; the graph owns its own scratch
+ *   buffer (allocated here), so replays of one graph must not overlap each
+ *   other, while different graphs may run concurrently.
+ * bitonic_graph_launch enqueues one replay on `stream` (hipStream_t).
+ * bitonic_graph_destroy frees the graph (and its scratch) -- only after every
+ * replay has finished.
+ * Returns BITONIC_OK, BITONIC_EINVAL, BITONIC_ENOMEM, BITONIC_ELAUNCH or
+ * BITONIC_EDEVICE (capture failed).
+ */
+typedef struct bitonic_graph bitonic_graph;
+int bitonic_graph_capture_sort_i32(bitonic_graph** out, int32_t* keys, int64_t n,
+                                   int ascending, const bitonic_plan* plan);
+int bitonic_graph_capture_segmented_i32(bitonic_graph** out, int32_t* keys,
+                                        const int64_t* offsets, int64_t nseg,
+                                        int64_t max_seg_len, int ascending);
+int bitonic_graph_launch(bitonic_graph* g, void* stream);
+int bitonic_graph_destroy(bitonic_graph* g);
 
 /*
  * Input generator (not part of the sorting method): writes

@@ -62,6 +62,15 @@ def load() -> ctypes.CDLL:
         "bitonic_plan_passes": ([ctypes.c_int64, ctypes.POINTER(bitonic_plan)],
                                 ctypes.c_int64),
         "bitonic_set_tuning": ([ctypes.c_int, ctypes.c_int, ctypes.c_int], ctypes.c_int),
+        "bitonic_set_tuning_value": ([ctypes.c_char_p, ctypes.c_int], ctypes.c_int),
+        "bitonic_get_tuning_value": ([ctypes.c_char_p, ctypes.POINTER(ctypes.c_int)],
+                                     ctypes.c_int),
+        "bitonic_graph_capture_sort_i32": ([ctypes.POINTER(vp), vp, ctypes.c_int64, ctypes.c_int,
+                                            ctypes.POINTER(bitonic_plan)], ctypes.c_int),
+        "bitonic_graph_capture_segmented_i32": ([ctypes.POINTER(vp), vp, vp, ctypes.c_int64,
+                                                 ctypes.c_int64, ctypes.c_int], ctypes.c_int),
+        "bitonic_graph_launch": ([vp, vp], ctypes.c_int),
+        "bitonic_graph_destroy": ([vp], ctypes.c_int),
         "bitonic_load_tuning": ([ctypes.c_char_p], ctypes.c_int),
         "bitonic_keygen_i32": ([vp, ctypes.c_int64, ctypes.c_uint64, ctypes.c_int64, vp],
                                ctypes.c_int),
@@ -264,6 +273,55 @@ def bitonic_sort_plan_launches_i32(keys, first: int, count: int, ascending: bool
 def bitonic_set_tuning(tile_log2: int = 0, fuse: int = 0, merge_blocks_per_cu: int = 0) -> None:
     _check("bitonic_set_tuning", load().bitonic_set_tuning(int(tile_log2), int(fuse),
                                                            int(merge_blocks_per_cu)))
+
+
+def bitonic_set_tuning_value(key: str, value: int) -> None:
+    _check("bitonic_set_tuning_value", load().bitonic_set_tuning_value(key.encode(), int(value)))
+
+
+def bitonic_get_tuning_value(key: str) -> int:
+    v = ctypes.c_int()
+    _check("bitonic_get_tuning_value", load().bitonic_get_tuning_value(key.encode(),
+                                                                       ctypes.byref(v)))
+    return int(v.value)
+
+
+class BitonicGraph:
+    """A captured sort (bitonic_graph_*): replay with launch(), free with
+    close() once every replay has finished."""
+
+    def __init__(self, handle):
+        self.handle = handle
+
+    def launch(self, stream=None) -> None:
+        _check("bitonic_graph_launch", load().bitonic_graph_launch(self.handle, _stream(stream)))
+
+    def close(self) -> None:
+        if self.handle:
+            load().bitonic_graph_destroy(self.handle)
+            self.handle = None
+
+
+def bitonic_graph_capture_sort_i32(keys, ascending: bool = True, plan=None) -> BitonicGraph:
+    ptr = _keys_ptr(keys)
+    p = _plan(plan)
+    h = ctypes.c_void_p()
+    _check("bitonic_graph_capture_sort_i32",
+           load().bitonic_graph_capture_sort_i32(ctypes.byref(h), ptr, keys.numel(),
+                                                 int(bool(ascending)), _plan_ref(p)))
+    return BitonicGraph(h)
+
+
+def bitonic_graph_capture_segmented_i32(keys, offsets, max_seg_len: int,
+                                        ascending: bool = True) -> BitonicGraph:
+    kp = _keys_ptr(keys)
+    op = _keys_ptr(offsets, "int64")
+    h = ctypes.c_void_p()
+    _check("bitonic_graph_capture_segmented_i32",
+           load().bitonic_graph_capture_segmented_i32(ctypes.byref(h), kp, op,
+                                                      max(offsets.numel() - 1, 0),
+                                                      int(max_seg_len), int(bool(ascending))))
+    return BitonicGraph(h)
 
 
 def bitonic_load_tuning(path: str) -> None:

@@ -14,6 +14,7 @@
 #include <cstdio>
 #include <cstring>
 #include <mutex>
+#include <new>
 #include <vector>
 
 #include "bitonic.h"
@@ -25,6 +26,7 @@ namespace bitonic {
 static std::atomic<int> g_tile_log2{13};
 static std::atomic<int> g_fuse{5};
 static std::atomic<int> g_merge_bpc{0};  // 0: one tile per workgroup
+static std::atomic<int> g_seg_bpc{4};    // small-segment workgroups per compute unit
 
 struct Resolved {
   int kind;
@@ -249,9 +251,86 @@ static int bind_device(Resolved* r) {
   return BITONIC_OK;
 }
 
+// The launch sequence of one segmented sort (see kernels_segmented.hip) on
+// the given scratch buffer (seg_scratch_bytes(nseg) bytes).
+static void enqueue_segmented(int32_t* keys, const int64_t* offsets, int64_t nseg,
+                              int64_t max_seg_len, int32_t flip, void* scratch, int cus,
+                              hipStream_t st) {
+  const SegScratch sc = seg_scratch_carve(scratch, nseg);
+  launch_seg_prep(offsets, nseg, sc, st);
+  const int64_t slots = (int64_t)cus * g_seg_bpc.load();
+  const int small_grid = (int)(slots < nseg ? slots : nseg);
+  launch_seg_small(keys, offsets, sc, flip, small_grid, st);
+  const int M = ceil_log2(max_seg_len);
+  if (M <= 13) return;
+  const int grid = cus * 4;
+  launch_seg_tiles(false, keys, offsets, sc, 14, flip, grid, st);
+  const int fuse = g_fuse.load() < kSegFuseMax ? g_fuse.load() : kSegFuseMax;
+  for (int p = 14; p <= M; ++p) {
+    const int nb = p - 13;
+    const int npass = (nb + fuse - 1) / fuse;
+    int top = p - 1;
+    for (int i = 0; i < npass; ++i) {
+      const int left = top - 13 + 1;
+      const int f = (left + (npass - i) - 1) / (npass - i);
+      const int q = top - f + 1;
+      launch_seg_pass(f, i == 0, keys, offsets, sc, p, q, flip, grid, st);
+      top = q - 1;
+    }
+    launch_seg_tiles(true, keys, offsets, sc, p, flip, grid, st);
+  }
+}
+
 }  // namespace bitonic
 
 using namespace bitonic;
+
+// ---------------------------------------------------------------------------
+// HIP graphs
+
+struct bitonic_graph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  void* scratch = nullptr;
+};
+
+// Capture what `enqueue` puts on a private stream into an executable graph.
+template <class F>
+static int capture_graph(bitonic_graph** out, void* scratch, F&& enqueue) {
+  hipStream_t cs = nullptr;
+  if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return BITONIC_EDEVICE;
+  (void)hipGetLastError();
+  int rc = BITONIC_OK;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    rc = BITONIC_EDEVICE;
+  } else {
+    enqueue(cs);
+    const hipError_t le = hipGetLastError();
+    const hipError_t ce = hipStreamEndCapture(cs, &graph);
+    if (le != hipSuccess) rc = BITONIC_ELAUNCH;
+    else if (ce != hipSuccess || graph == nullptr) rc = BITONIC_EDEVICE;
+    else if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) rc = BITONIC_EDEVICE;
+  }
+  (void)hipStreamDestroy(cs);
+  if (rc) {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    return rc;
+  }
+  bitonic_graph* g = new (std::nothrow) bitonic_graph;
+  if (!g) {
+    (void)hipGraphExecDestroy(exec);
+    (void)hipGraphDestroy(graph);
+    return BITONIC_ENOMEM;
+  }
+  g->graph = graph;
+  g->exec = exec;
+  g->scratch = scratch;
+  *out = g;
+  return BITONIC_OK;
+}
 
 extern "C" {
 
@@ -369,33 +448,6 @@ int bitonic_sort_plan_launches_i32(int32_t* keys, int64_t n, int ascending,
   return finish_launches();
 }
 
-int bitonic_set_tuning(int tile_log2, int fuse, int merge_blocks_per_cu) {
-  if (tile_log2 && !tile_log2_supported(tile_log2)) return BITONIC_EINVAL;
-  if (fuse && (fuse < 1 || fuse > kFuseMax)) return BITONIC_EINVAL;
-  if (merge_blocks_per_cu < -1 || merge_blocks_per_cu > 16) return BITONIC_EINVAL;
-  if (tile_log2) g_tile_log2.store(tile_log2);
-  if (fuse) g_fuse.store(fuse);
-  if (merge_blocks_per_cu > 0) g_merge_bpc.store(merge_blocks_per_cu);
-  if (merge_blocks_per_cu < 0) g_merge_bpc.store(0);
-  return BITONIC_OK;
-}
-
-int bitonic_load_tuning(const char* path) {
-  if (!path) return BITONIC_EINVAL;
-  FILE* f = std::fopen(path, "r");
-  if (!f) return BITONIC_EINVAL;
-  int tile = 0, fuse = 0, bpc = 0;
-  char key[64];
-  int val;
-  while (std::fscanf(f, "%63s %d", key, &val) == 2) {
-    if (!std::strcmp(key, "tile_log2")) tile = val;
-    else if (!std::strcmp(key, "fuse")) fuse = val;
-    else if (!std::strcmp(key, "merge_blocks_per_cu")) bpc = val;
-  }
-  std::fclose(f);
-  return bitonic_set_tuning(tile, fuse, bpc);
-}
-
 int bitonic_sort_segmented_bounded_i32(int32_t* keys, const int64_t* offsets, int64_t nseg,
                                        int64_t max_seg_len, int ascending, void* stream) {
   if (nseg < 0 || max_seg_len < 0) return BITONIC_EINVAL;
@@ -422,39 +474,118 @@ int bitonic_sort_segmented_bounded_i32(int32_t* keys, const int64_t* offsets, in
   void* base = nullptr;
   rc = stream_scratch(dev, st, seg_scratch_bytes(nseg), &base);
   if (rc) return rc;
-  const SegScratch sc = seg_scratch_carve(base, nseg);
-  const int32_t flip = ascending ? 0 : -1;
-  const int cus = device_cus(dev);
   (void)hipGetLastError();
-  launch_seg_prep(offsets, nseg, sc, st);
-  const int64_t items_bound = nseg;  // at most one item per segment
-  const int small_grid = (int)((int64_t)cus * 4 < items_bound ? (int64_t)cus * 4 : items_bound);
-  launch_seg_small(keys, offsets, sc, flip, small_grid, st);
-  const int M = ceil_log2(max_seg_len);
-  if (M > 13) {
-    const int grid = cus * 4;
-    launch_seg_tiles(false, keys, offsets, sc, 14, flip, grid, st);
-    const int fuse = g_fuse.load() < kSegFuseMax ? g_fuse.load() : kSegFuseMax;
-    for (int p = 14; p <= M; ++p) {
-      const int nb = p - 13;
-      const int npass = (nb + fuse - 1) / fuse;
-      int top = p - 1;
-      for (int i = 0; i < npass; ++i) {
-        const int left = top - 13 + 1;
-        const int f = (left + (npass - i) - 1) / (npass - i);
-        const int q = top - f + 1;
-        launch_seg_pass(f, i == 0, keys, offsets, sc, p, q, flip, grid, st);
-        top = q - 1;
-      }
-      launch_seg_tiles(true, keys, offsets, sc, p, flip, grid, st);
-    }
-  }
+  enqueue_segmented(keys, offsets, nseg, max_seg_len, ascending ? 0 : -1, base, device_cus(dev),
+                    st);
   return finish_launches();
 }
 
 int bitonic_sort_segmented_i32(int32_t* keys, const int64_t* offsets, int64_t nseg,
                                int ascending, void* stream) {
   return bitonic_sort_segmented_bounded_i32(keys, offsets, nseg, 0, ascending, stream);
+}
+
+int bitonic_set_tuning(int tile_log2, int fuse, int merge_blocks_per_cu) {
+  if (tile_log2 && !tile_log2_supported(tile_log2)) return BITONIC_EINVAL;
+  if (fuse && (fuse < 1 || fuse > kFuseMax)) return BITONIC_EINVAL;
+  if (merge_blocks_per_cu < -1 || merge_blocks_per_cu > 16) return BITONIC_EINVAL;
+  if (tile_log2) g_tile_log2.store(tile_log2);
+  if (fuse) g_fuse.store(fuse);
+  if (merge_blocks_per_cu > 0) g_merge_bpc.store(merge_blocks_per_cu);
+  if (merge_blocks_per_cu < 0) g_merge_bpc.store(0);
+  return BITONIC_OK;
+}
+
+int bitonic_set_tuning_value(const char* key, int value) {
+  if (!key) return BITONIC_EINVAL;
+  if (!std::strcmp(key, "tile_log2")) return bitonic_set_tuning(value, 0, 0);
+  if (!std::strcmp(key, "fuse")) return value ? bitonic_set_tuning(0, value, 0) : BITONIC_EINVAL;
+  if (!std::strcmp(key, "merge_blocks_per_cu"))
+    return value ? bitonic_set_tuning(0, 0, value) : BITONIC_EINVAL;
+  if (!std::strcmp(key, "seg_blocks_per_cu")) {
+    if (value < 1 || value > 16) return BITONIC_EINVAL;
+    g_seg_bpc.store(value);
+    return BITONIC_OK;
+  }
+  return BITONIC_EINVAL;
+}
+
+int bitonic_get_tuning_value(const char* key, int* value) {
+  if (!key || !value) return BITONIC_EINVAL;
+  if (!std::strcmp(key, "tile_log2")) *value = g_tile_log2.load();
+  else if (!std::strcmp(key, "fuse")) *value = g_fuse.load();
+  else if (!std::strcmp(key, "merge_blocks_per_cu")) *value = g_merge_bpc.load() ? g_merge_bpc.load() : -1;
+  else if (!std::strcmp(key, "seg_blocks_per_cu")) *value = g_seg_bpc.load();
+  else return BITONIC_EINVAL;
+  return BITONIC_OK;
+}
+
+int bitonic_load_tuning(const char* path) {
+  if (!path) return BITONIC_EINVAL;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return BITONIC_EINVAL;
+  char key[64];
+  int val;
+  int rc = BITONIC_OK;
+  while (std::fscanf(f, "%63s %d", key, &val) == 2) {
+    const int r = bitonic_set_tuning_value(key, val);
+    if (r) rc = r;
+  }
+  std::fclose(f);
+  return rc;
+}
+
+int bitonic_graph_capture_sort_i32(bitonic_graph** out, int32_t* keys, int64_t n, int ascending,
+                                   const bitonic_plan* plan) {
+  if (!out) return BITONIC_EINVAL;
+  *out = nullptr;
+  int rc = check_sort_args(keys, n);
+  if (rc) return rc;
+  Resolved r;
+  rc = resolve(plan, &r);
+  if (rc) return rc;
+  fit_alignment(keys, &r);
+  rc = bind_device(&r);
+  if (rc) return rc;
+  return capture_graph(out, nullptr, [&](hipStream_t cs) {
+    if (n > 1) enqueue_plain(keys, (uint32_t)n, 64, ascending ? 0 : -1, r, cs, false);
+  });
+}
+
+int bitonic_graph_capture_segmented_i32(bitonic_graph** out, int32_t* keys,
+                                        const int64_t* offsets, int64_t nseg,
+                                        int64_t max_seg_len, int ascending) {
+  if (!out) return BITONIC_EINVAL;
+  *out = nullptr;
+  if (nseg < 0 || max_seg_len < 1) return BITONIC_EINVAL;
+  if (nseg >= (int64_t(1) << 31) || max_seg_len > (int64_t(1) << 31)) return BITONIC_EUNSUPPORTED;
+  if (nseg > 0 && (keys == nullptr || offsets == nullptr)) return BITONIC_EINVAL;
+  int dev = 0;
+  int rc = current_device(&dev);
+  if (rc) return rc;
+  void* scratch = nullptr;
+  if (nseg > 0 && hipMalloc(&scratch, seg_scratch_bytes(nseg)) != hipSuccess) return BITONIC_ENOMEM;
+  const int cus = device_cus(dev);
+  rc = capture_graph(out, scratch, [&](hipStream_t cs) {
+    if (nseg > 0)
+      enqueue_segmented(keys, offsets, nseg, max_seg_len, ascending ? 0 : -1, scratch, cus, cs);
+  });
+  if (rc && scratch) (void)hipFree(scratch);
+  return rc;
+}
+
+int bitonic_graph_launch(bitonic_graph* g, void* stream) {
+  if (!g || !g->exec) return BITONIC_EINVAL;
+  return hipGraphLaunch(g->exec, (hipStream_t)stream) == hipSuccess ? BITONIC_OK : BITONIC_ELAUNCH;
+}
+
+int bitonic_graph_destroy(bitonic_graph* g) {
+  if (!g) return BITONIC_OK;
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  if (g->scratch) (void)hipFree(g->scratch);
+  delete g;
+  return BITONIC_OK;
 }
 
 int bitonic_keygen_i32(int32_t* out, int64_t n, uint64_t seed, int64_t start, void* stream) {

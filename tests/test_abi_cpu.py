@@ -95,3 +95,47 @@ def test_headline_pass_count(lib):
     assert B.bitonic_plan_passes(2**24) == 30  # default: 2^13 tiles, 5 fused steps
     assert B.bitonic_plan_passes(0) == 0 and B.bitonic_plan_passes(1) == 0
     assert B.bitonic_plan_passes(-1) == -1
+
+
+def test_tuning_values_round_trip(lib, tmp_path):
+    from paper_1506_01446_amd import autotune
+    saved = {k: B.bitonic_get_tuning_value(k) for k in
+             ("tile_log2", "fuse", "merge_blocks_per_cu", "seg_blocks_per_cu")}
+    try:
+        p = tmp_path / "tuning.txt"
+        autotune.write_tuning(str(p), {"tile_log2": 12, "fuse": 3, "merge_blocks_per_cu": 4,
+                                       "seg_blocks_per_cu": 2})
+        B.bitonic_load_tuning(str(p))
+        assert B.bitonic_get_tuning_value("tile_log2") == 12
+        assert B.bitonic_get_tuning_value("fuse") == 3
+        assert B.bitonic_get_tuning_value("merge_blocks_per_cu") == 4
+        assert B.bitonic_get_tuning_value("seg_blocks_per_cu") == 2
+        # the default plan follows the tuning
+        assert B.bitonic_plan_passes(2**24) == _closed_form_optimized(24, 12, 3)
+        with pytest.raises(B.BitonicError):
+            B.bitonic_set_tuning_value("no_such_knob", 1)
+        with pytest.raises(B.BitonicError):
+            B.bitonic_set_tuning_value("seg_blocks_per_cu", 0)
+    finally:
+        for k, v in saved.items():
+            B.bitonic_set_tuning_value(k, v)
+    assert B.bitonic_get_tuning_value("merge_blocks_per_cu") == saved["merge_blocks_per_cu"]
+
+
+def test_graph_capture_argument_errors(lib):
+    h = ctypes.c_void_p()
+    assert lib.bitonic_graph_capture_sort_i32(None, None, 0, 1, None) == -1
+    assert lib.bitonic_graph_capture_sort_i32(ctypes.byref(h), None, 5, 1, None) == -1
+    assert lib.bitonic_graph_capture_segmented_i32(ctypes.byref(h), None, None, 3, 0, 1) == -1
+    assert lib.bitonic_graph_launch(None, None) == -1
+    assert lib.bitonic_graph_destroy(None) == 0
+
+
+def test_bench_traffic_lookup(monkeypatch):
+    import bench
+    got = bench.committed_traffic("tile_merge", 1 << 24)
+    if got is not None:   # the committed counters match the current kernel sources
+        assert abs(got / (8 * (1 << 24)) - 1) < 0.05
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: "0000000000000000")
+    assert bench.committed_traffic("tile_merge", 1 << 24) is None
+    assert bench.committed_traffic("tile_merge", 12345) is None
