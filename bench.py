@@ -51,6 +51,9 @@ def parse():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--out", default="")
+    ap.add_argument("--ablation", action="store_true",
+                    help="the paper's Table 1 layout on this GPU: Basic, Semi and "
+                         "Optimized plans for n = 2^17 .. 2^28, ms per sort")
     ap.add_argument("--counters", action="store_true",
                     help="short run for rocprofv3 --pmc: one n-key device copy (the "
                          "calibration kernel) and three sorts, no timing")
@@ -137,7 +140,8 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-KERNEL_CLASS = {"tile_kernel<13, 5, 1>": "tile_merge", "tile_kernel<13, 5, 0>": "tile_sort"}
+KERNEL_CLASS = {f"tile_kernel<{t}, 5, {k}>": ("tile_merge" if k else "tile_sort")
+                for t in (11, 12, 13, 14) for k in (0, 1)}
 
 
 def committed_traffic(kernel: str, n: int):
@@ -176,7 +180,7 @@ def cpu_baseline(n):
     from paper_1506_01446_amd import workloads as W
     keys = W.uniform_i32(W.SEED_BASE + 2, n)
     reps, total = 0, 0.0
-    while reps < 6 and total < 12.0:
+    while reps < 40 and total < 12.0:
         t0 = time.perf_counter()
         O.sort_i32(keys, True)
         total += time.perf_counter() - t0
@@ -263,6 +267,38 @@ def batched_vs_looped(torch, B, W):
             "bit_exact_vs_looped_sample": ok}
 
 
+def ablation(torch, B, W, out_path=""):
+    """Table 1 of the paper (section 5) re-measured here: Basic (one launch
+    per step), Semi (LDS tiles, one launch per long-stride step) and
+    Optimized (register tiles, fused passes) for the paper's sizes; the CPU
+    column is the oracle's std::sort on this host (one thread), context only."""
+    from oracle import oracle as O
+    rows = []
+    for k in range(17, 29):
+        n = 1 << k
+        src = torch.from_numpy(W.uniform_i32(W.SEED_BASE + k, n)).cuda()
+        row = {"n": n}
+        for name, plan in (("basic", ("basic",)), ("semi", ("semi", 12)),
+                           ("optimized", ("optimized", 0, 0))):
+            steps = 3 if k >= 26 or name == "basic" else 5
+            ms, _, ok = time_sorts(torch, B, src, steps, 1, plan)
+            row[name + "_ms"] = round(ms, 4)
+            row[name + "_ok"] = ok
+        if k <= 24:
+            keys = W.uniform_i32(W.SEED_BASE + k, n)
+            t0 = time.perf_counter()
+            O.sort_i32(keys, True)
+            row["cpu_std_sort_ms"] = round((time.perf_counter() - t0) * 1e3, 2)
+            row["ratio_cpu_over_optimized"] = round(row["cpu_std_sort_ms"] / row["optimized_ms"], 1)
+        log(json.dumps(row))
+        rows.append(row)
+        del src
+    if out_path:
+        with open(out_path, "w") as f:
+            json.dump(rows, f, indent=1)
+    return rows
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -280,6 +316,10 @@ def main():
     plan = ("optimized", args.tile, args.fuse)
     n = args.n
     src = torch.from_numpy(W.uniform_i32(W.SEED_BASE + 2, n)).cuda()
+    if args.ablation:
+        del src
+        ablation(torch, B, W, args.out)
+        return
     if args.counters:
         dst = torch.empty_like(src)
         dst.copy_(src)          # calibration: reads and writes 4n bytes each
@@ -340,8 +380,9 @@ def main():
             "config": {"workload": "bitonic sort of one array of n=2^24 uniform int32 keys "
                                    "(seeded SplitMix64), ascending, device-resident; "
                                    "plus n=10,000,000 in extra",
-                       "n": n, "plan": {"kind": "optimized", "tile_log2": args.tile or 13,
-                                        "fuse": args.fuse or 4},
+                       "n": n, "plan": {"kind": "optimized",
+                                        "tile_log2": args.tile or B.bitonic_get_tuning_value("tile_log2"),
+                                        "fuse": args.fuse or B.bitonic_get_tuning_value("fuse")},
                        "passes": passes, "parallelism": "single GPU"},
             "roofline": roofline, "cpu_baseline": cpu, "extra": extra}
     s = json.dumps(line)

@@ -128,7 +128,7 @@ enum bitonic_plan_kind {
 
 typedef struct bitonic_plan {
   int kind;                /* enum bitonic_plan_kind */
-  int tile_log2;           /* keys per on-chip tile = 2^tile_log2, 11..13 for
+  int tile_log2;           /* keys per on-chip tile = 2^tile_log2, 11..14 for
                               the optimized plan, 1..13 for semi (0 = library
                               choice) */
   int fuse;                /* max long-stride steps per HBM pass, 1..5

@@ -23,7 +23,7 @@
 
 namespace bitonic {
 
-static std::atomic<int> g_tile_log2{13};
+static std::atomic<int> g_tile_log2{14};
 static std::atomic<int> g_fuse{5};
 static std::atomic<int> g_merge_bpc{0};  // 0: one tile per workgroup
 static std::atomic<int> g_seg_bpc{4};    // small-segment workgroups per compute unit

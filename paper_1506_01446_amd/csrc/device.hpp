@@ -60,8 +60,9 @@ struct Prog {
   static constexpr int T = 1 << L_;
   static constexpr bool VEC = KIND_ < 2;  // 16-byte vector global I/O allowed
   // Recompute each layout's thread base at its regroup (fewer registers,
-  // more ALU); used by the segment kernels, which run several programs.
-  static constexpr bool LEAN = KIND_ >= 2;
+  // more ALU); used by the segment kernels, which run several programs, and
+  // by tiles of 2^14 keys, whose 512-thread workgroups need it to fit.
+  static constexpr bool LEAN = KIND_ >= 2 || L_ >= 14;
   static constexpr Program value = make_program(L_, R_LOG_, KIND_);
   static_assert(value.ngroups <= kMaxGroups, "program too long");
 };

@@ -273,6 +273,7 @@ void launch_tile(int L, int kind, int32_t* keys, uint32_t n, int32_t flip, uint3
     case 11: launch_tile_L<11>(kind, keys, n, flip, max_blocks, st); break;
     case 12: launch_tile_L<12>(kind, keys, n, flip, max_blocks, st); break;
     case 13: launch_tile_L<13>(kind, keys, n, flip, max_blocks, st); break;
+    case 14: launch_tile_L<14>(kind, keys, n, flip, max_blocks, st); break;
     default: break;
   }
 }

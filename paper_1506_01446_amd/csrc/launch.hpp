@@ -8,7 +8,7 @@ namespace bitonic {
 
 constexpr int kTileRegLogPlain = 5;  // 32 keys per thread in the tile kernels
 constexpr int kTileMinLog2 = 11;
-constexpr int kTileMaxLog2 = 13;
+constexpr int kTileMaxLog2 = 14;
 constexpr int kFuseMax = 5;
 constexpr int kLdsNetworkMaxLog2 = 13;
 

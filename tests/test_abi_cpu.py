@@ -63,7 +63,7 @@ def _closed_form_optimized(k, t, f):
     return 1 + sum(-(-(p - t) // f) + 1 for p in range(t + 1, k + 1))
 
 
-@pytest.mark.parametrize("t", [11, 12, 13])
+@pytest.mark.parametrize("t", [11, 12, 13, 14])
 @pytest.mark.parametrize("f", [1, 2, 3, 4, 5])
 def test_optimized_pass_count(lib, t, f):
     for k in range(1, 32):
@@ -92,7 +92,7 @@ def test_semi_plan_counts(lib):
 def test_headline_pass_count(lib):
     # n = 2^24 with 2^13-key tiles and up to 4 fused steps per HBM pass
     assert B.bitonic_plan_passes(2**24, ("optimized", 13, 4)) == 33
-    assert B.bitonic_plan_passes(2**24) == 30  # default: 2^13 tiles, 5 fused steps
+    assert B.bitonic_plan_passes(2**24) == 26  # default: 2^14 tiles, 5 fused steps
     assert B.bitonic_plan_passes(0) == 0 and B.bitonic_plan_passes(1) == 0
     assert B.bitonic_plan_passes(-1) == -1
 

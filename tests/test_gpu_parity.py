@@ -19,7 +19,8 @@ SIZES = [0, 1, 2, 3, 4, 5, 7, 8, 9, 15, 16, 17, 31, 33, 63, 64, 65, 127, 129, 25
          257, 1000, 1023, 1024, 1025, 2047, 2048, 2049, 4095, 4096, 4097, 8191, 8192, 8193,
          16383, 16385, 32768, 65535, 65536, 65537, 100003, 131075, 262144, 300001]
 PLANS = [("basic",), ("semi", 8), ("semi", 12)] + \
-        [("optimized", t, f) for t in (11, 12, 13) for f in (1, 2, 3, 4, 5)]
+        [("optimized", t, f) for t in (11, 12, 13, 14) for f in (1, 2, 3, 4, 5)] + \
+        [("optimized", 13, 5, 4), ("optimized", 14, 5, 2)]
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -79,8 +80,9 @@ def test_signed_extremes():
             assert np.array_equal(gpu_sort(keys, asc, plan), O.sort_i32(keys, asc))
 
 
-@pytest.mark.parametrize("plan", [("optimized", 11, 2), ("optimized", 13, 4), ("semi", 9),
-                                  ("basic",)], ids=lambda p: "-".join(map(str, p)))
+@pytest.mark.parametrize("plan", [("optimized", 11, 2), ("optimized", 13, 4),
+                                  ("optimized", 14, 5), ("semi", 9), ("basic",)],
+                         ids=lambda p: "-".join(map(str, p)))
 def test_per_phase_states(plan):
     """After phase p the GPU state equals the oracle network's state after
     phase p (every aligned 2^p block sorted), for every p."""
@@ -231,3 +233,39 @@ def test_segmented_repeated_calls_reuse_scratch():
         keys, off = W.batched_workload(nseg=nseg, seed=seed, max_log2=15)
         got = gpu_sort_segmented(keys, off, True)
         assert np.array_equal(got, O.sort_segmented_i32(keys, off, True)), nseg
+
+
+def _hashes(t, chunk=1 << 26):
+    s1 = torch.zeros((), dtype=torch.int64, device="cuda")
+    s2 = torch.zeros((), dtype=torch.int64, device="cuda")
+    for a in range(0, t.numel(), chunk):
+        c = t[a:a + chunk].to(torch.int64)
+        s1 += c.sum()
+        s2 += (c * c).sum()          # wraps mod 2^64, deterministically
+    return int(s1.item()), int(s2.item())
+
+
+@pytest.mark.parametrize("n", [1 << 31, (1 << 31) - 1])
+def test_maximum_size(n):
+    """The largest supported n: sorted order, the multiset (two hashes), the
+    extremes and sampled order statistics (counted independently)."""
+    print(f"[case] maximum size n={n}", flush=True)
+    t = torch.empty(n, dtype=torch.int32, device="cuda")
+    B.bitonic_keygen_i32(t, W.SEED_BASE + 99)
+    h0 = _hashes(t)
+    lo, hi = int(t.min().item()), int(t.max().item())
+    src = t.clone()                  # order statistics are counted in the input
+    B.bitonic_sort_i32(t, True)
+    torch.cuda.synchronize()
+    assert bool((t[1:] >= t[:-1]).all().item())
+    assert _hashes(t) == h0
+    assert int(t[0].item()) == lo and int(t[-1].item()) == hi
+    # the output at index i is the input's i-th order statistic:
+    # #(input < v) <= i < #(input <= v)
+    for i in (0, 1, n // 3, n // 2, n - 2, n - 1):
+        v = int(t[i].item())
+        below = int((src < v).sum().item())
+        upto = int((src <= v).sum().item())
+        assert below <= i < upto, i
+    del src, t
+    torch.cuda.empty_cache()
