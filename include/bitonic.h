@@ -71,6 +71,29 @@ const char* bitonic_status_string(int status);
 int bitonic_sort_i32(int32_t* keys, int64_t n, int ascending, void* stream);
 
 /*
+ * Key types.  All are 32-bit and sorted with the same network; a key type
+ * only changes the order-preserving map applied as keys are loaded and
+ * stored (the paper's future work, section 6, names other key types):
+ *   BITONIC_KEY_I32  signed two's-complement integers
+ *   BITONIC_KEY_U32  unsigned integers
+ *   BITONIC_KEY_F32  IEEE-754 binary32, in the totalOrder of IEEE 754-2008
+ *                    (-NaN < -inf < ... < -0 < +0 < ... < +inf < +NaN; NaNs
+ *                    ordered by their payload bits)
+ */
+enum bitonic_key_type {
+  BITONIC_KEY_I32 = 0,
+  BITONIC_KEY_U32 = 1,
+  BITONIC_KEY_F32 = 2
+};
+
+/*
+ * bitonic_sort_i32 for any key type (keys: device pointer to n 4-byte keys
+ * of that type).  Returns BITONIC_EINVAL for an unknown key_type, else as
+ * bitonic_sort_i32.
+ */
+int bitonic_sort_keys(void* keys, int64_t n, int key_type, int ascending, void* stream);
+
+/*
  * Sort every segment of a CSR table independently, in one batched launch
  * sequence (the network of section 3 applied per segment, each segment
  * padded virtually to its own power of two).
@@ -106,6 +129,12 @@ int bitonic_sort_segmented_i32(int32_t* keys, const int64_t* offsets,
 int bitonic_sort_segmented_bounded_i32(int32_t* keys, const int64_t* offsets,
                                        int64_t nseg, int64_t max_seg_len,
                                        int ascending, void* stream);
+
+/* bitonic_sort_segmented_bounded_i32 for any key type (max_seg_len 0 =
+ * unknown, as above). */
+int bitonic_sort_segmented_keys(void* keys, const int64_t* offsets, int64_t nseg,
+                                int64_t max_seg_len, int key_type, int ascending,
+                                void* stream);
 
 /*
  * Plans.  A plan fixes how the k(k+1)/2 steps of the network map onto

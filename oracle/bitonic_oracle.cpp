@@ -109,6 +109,56 @@ int oracle_sort_i32(int32_t* keys, int64_t n, int ascending) {
   return 0;
 }
 
+// IEEE 754-2008 totalOrder on binary32 bit patterns: negative values (sign
+// bit set) come before positive ones; among positives a larger magnitude
+// field is larger; among negatives a larger magnitude field is smaller.  NaNs
+// take their place by their bits (-NaN first, +NaN last), and -0 < +0.
+static bool f32_total_less(uint32_t a, uint32_t b) {
+  const bool na = (a >> 31) != 0, nb = (b >> 31) != 0;
+#if ORACLE_MUTANT == 7
+  // planted mistake: negatives ordered by increasing magnitude
+  if (na != nb) return na;
+  return (a & 0x7FFFFFFFu) < (b & 0x7FFFFFFFu);
+#else
+  if (na != nb) return na;
+  const uint32_t ma = a & 0x7FFFFFFFu, mb = b & 0x7FFFFFFFu;
+  return na ? (ma > mb) : (ma < mb);
+#endif
+}
+
+// Plain definitions for the other 32-bit key types (bit patterns in and out).
+int oracle_sort_u32(uint32_t* keys, int64_t n, int ascending) {
+  if (n < 0 || (n > 0 && keys == nullptr)) return -1;
+  std::sort(keys, keys + n);
+  if (!ascending) std::reverse(keys, keys + n);
+  return 0;
+}
+
+int oracle_sort_f32_bits(uint32_t* keys, int64_t n, int ascending) {
+  if (n < 0 || (n > 0 && keys == nullptr)) return -1;
+  std::sort(keys, keys + n, f32_total_less);
+  if (!ascending) std::reverse(keys, keys + n);
+  return 0;
+}
+
+// Plain definition for key type t (0 int32, 1 uint32, 2 float32 totalOrder)
+// on 32-bit patterns, per segment [offsets[s], offsets[s+1]).
+int oracle_sort_segmented_keys(uint32_t* keys, const int64_t* offsets, int64_t nseg,
+                               int key_type, int ascending) {
+  if (nseg < 0 || (nseg > 0 && offsets == nullptr) || key_type < 0 || key_type > 2) return -1;
+  for (int64_t s = 0; s < nseg; ++s)
+    if (offsets[s + 1] < offsets[s]) return -1;
+  for (int64_t s = 0; s < nseg; ++s) {
+    uint32_t* k = keys + offsets[s];
+    const int64_t len = offsets[s + 1] - offsets[s];
+    const int rc = key_type == 0   ? oracle_sort_i32(reinterpret_cast<int32_t*>(k), len, ascending)
+                   : key_type == 1 ? oracle_sort_u32(k, len, ascending)
+                                   : oracle_sort_f32_bits(k, len, ascending);
+    if (rc) return rc;
+  }
+  return 0;
+}
+
 // Plain definition, per segment [offsets[s], offsets[s+1]).
 int oracle_sort_segmented_i32(int32_t* keys, const int64_t* offsets,
                               int64_t nseg, int ascending) {

@@ -21,6 +21,7 @@ MUTANTS = {
     4: "keys compared as unsigned",
     5: "last step of every phase dropped",
     6: "padding with zeros instead of INT32_MAX",
+    7: "float32 negatives ordered by increasing magnitude",
 }
 
 

@@ -53,6 +53,13 @@ def _bind(lib: ctypes.CDLL) -> ctypes.CDLL:
     lib.oracle_bitonic_batch_i32.argtypes = [p32, ctypes.c_int64, ctypes.c_int64,
                                              ctypes.c_int, ctypes.c_int]
     lib.oracle_bitonic_batch_i32.restype = ctypes.c_int
+    pu = ctypes.POINTER(ctypes.c_uint32)
+    lib.oracle_sort_u32.argtypes = [pu, ctypes.c_int64, ctypes.c_int]
+    lib.oracle_sort_u32.restype = ctypes.c_int
+    lib.oracle_sort_f32_bits.argtypes = [pu, ctypes.c_int64, ctypes.c_int]
+    lib.oracle_sort_f32_bits.restype = ctypes.c_int
+    lib.oracle_sort_segmented_keys.argtypes = [pu, p64, ctypes.c_int64, ctypes.c_int, ctypes.c_int]
+    lib.oracle_sort_segmented_keys.restype = ctypes.c_int
     lib.oracle_mutant_id.argtypes = []
     lib.oracle_mutant_id.restype = ctypes.c_int
     return lib
@@ -90,6 +97,35 @@ def sort_i32(keys, ascending: bool = True, lib=None) -> np.ndarray:
     rc = lib.oracle_sort_i32(_p32(x), x.size, int(bool(ascending)))
     if rc:
         raise ValueError("oracle_sort_i32 rejected its arguments")
+    return x
+
+
+KEY_I32, KEY_U32, KEY_F32 = 0, 1, 2
+_KEY_DTYPES = {KEY_I32: np.int32, KEY_U32: np.uint32, KEY_F32: np.float32}
+
+
+def sort_keys(keys, key_type: int, ascending: bool = True, lib=None) -> np.ndarray:
+    """Plain definition for int32 / uint32 / float32 keys (float32 in IEEE
+    totalOrder).  Returns an array of the key type (bit-exact)."""
+    lib = lib or load()
+    x = np.ascontiguousarray(np.asarray(keys, dtype=_KEY_DTYPES[key_type])).copy()
+    bits = x.view(np.uint32)
+    fn = {KEY_I32: None, KEY_U32: lib.oracle_sort_u32, KEY_F32: lib.oracle_sort_f32_bits}[key_type]
+    if fn is None:
+        return sort_i32(x, ascending, lib).view(np.int32)
+    if fn(bits.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)), x.size, int(bool(ascending))):
+        raise ValueError("oracle rejected its arguments")
+    return x
+
+
+def sort_segmented_keys(keys, offsets, key_type: int, ascending: bool = True, lib=None):
+    lib = lib or load()
+    x = np.ascontiguousarray(np.asarray(keys, dtype=_KEY_DTYPES[key_type])).copy()
+    off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+    if lib.oracle_sort_segmented_keys(x.view(np.uint32).ctypes.data_as(
+            ctypes.POINTER(ctypes.c_uint32)), _p64(off), off.size - 1, int(key_type),
+            int(bool(ascending))):
+        raise ValueError("oracle rejected its arguments")
     return x
 
 

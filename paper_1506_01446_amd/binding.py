@@ -74,6 +74,9 @@ def load() -> ctypes.CDLL:
         "bitonic_load_tuning": ([ctypes.c_char_p], ctypes.c_int),
         "bitonic_keygen_i32": ([vp, ctypes.c_int64, ctypes.c_uint64, ctypes.c_int64, vp],
                                ctypes.c_int),
+        "bitonic_sort_keys": ([vp, ctypes.c_int64, ctypes.c_int, ctypes.c_int, vp], ctypes.c_int),
+        "bitonic_sort_segmented_keys": ([vp, vp, ctypes.c_int64, ctypes.c_int64, ctypes.c_int,
+                                         ctypes.c_int, vp], ctypes.c_int),
         "bitonic_plan_describe": ([ctypes.c_int64, ctypes.POINTER(bitonic_plan), vp, vp,
                                    ctypes.c_int64], ctypes.c_int64),
         "bitonic_sort_plan_launches_i32": ([vp, ctypes.c_int64, ctypes.c_int,
@@ -125,6 +128,30 @@ def _keys_ptr(keys, dtype_name: str = "int32"):
     return keys.data_ptr() if keys.numel() else None
 
 
+KEY_TYPES = {"int32": 0, "uint32": 1, "float32": 2}
+
+
+def _key_type(keys, key_type) -> int:
+    import torch
+    if key_type is not None:
+        return KEY_TYPES[key_type] if isinstance(key_type, str) else int(key_type)
+    by_dtype = {torch.int32: 0, torch.float32: 2}
+    if hasattr(torch, "uint32"):
+        by_dtype[torch.uint32] = 1
+    if keys.dtype not in by_dtype:
+        raise ValueError(f"no 32-bit key type for dtype {keys.dtype}")
+    return by_dtype[keys.dtype]
+
+
+def _any32_ptr(keys):
+    import torch
+    if not isinstance(keys, torch.Tensor):
+        raise TypeError("expected a torch tensor on the GPU")
+    if keys.element_size() != 4 or not keys.is_cuda or not keys.is_contiguous():
+        raise ValueError("expected a contiguous tensor of 4-byte keys on the GPU")
+    return keys.data_ptr() if keys.numel() else None
+
+
 def _plan(plan) -> bitonic_plan | None:
     if plan is None:
         return None
@@ -157,6 +184,26 @@ def bitonic_sort_i32(keys, ascending: bool = True, stream=None) -> None:
     ptr = _keys_ptr(keys)
     _check("bitonic_sort_i32",
            load().bitonic_sort_i32(ptr, keys.numel(), int(bool(ascending)), _stream(stream)))
+
+
+def bitonic_sort_keys(keys, ascending: bool = True, key_type=None, stream=None) -> None:
+    """Sort 4-byte keys in place: int32, uint32 or float32 (IEEE totalOrder),
+    taken from the tensor's dtype or given as key_type ("int32", "uint32",
+    "float32"; an int32 tensor may hold the bit patterns of another type)."""
+    ptr = _any32_ptr(keys)
+    _check("bitonic_sort_keys",
+           load().bitonic_sort_keys(ptr, keys.numel(), _key_type(keys, key_type),
+                                    int(bool(ascending)), _stream(stream)))
+
+
+def bitonic_sort_segmented_keys(keys, offsets, ascending: bool = True, key_type=None,
+                                max_seg_len: int = 0, stream=None) -> None:
+    kp = _any32_ptr(keys)
+    op = _keys_ptr(offsets, "int64")
+    _check("bitonic_sort_segmented_keys",
+           load().bitonic_sort_segmented_keys(kp, op, max(offsets.numel() - 1, 0),
+                                              int(max_seg_len), _key_type(keys, key_type),
+                                              int(bool(ascending)), _stream(stream)))
 
 
 def bitonic_sort_plan_i32(keys, ascending: bool = True, plan=None, stream=None) -> None:

@@ -79,7 +79,7 @@ struct Observer {
 
 // Enqueue (or, with count_only, just count) the launches for phases 1..K of
 // the network over keys[0, n).
-static int64_t enqueue_plain(int32_t* keys, uint32_t n, int K, int32_t flip, const Resolved& r,
+static int64_t enqueue_plain(int32_t* keys, uint32_t n, int K, Codec flip, const Resolved& r,
                              hipStream_t st, bool count_only, Observer* obs = nullptr) {
   const int k = ceil_log2(n);
   const uint32_t N = (k >= 32) ? 0u : (1u << k);
@@ -254,7 +254,7 @@ static int bind_device(Resolved* r) {
 // The launch sequence of one segmented sort (see kernels_segmented.hip) on
 // the given scratch buffer (seg_scratch_bytes(nseg) bytes).
 static void enqueue_segmented(int32_t* keys, const int64_t* offsets, int64_t nseg,
-                              int64_t max_seg_len, int32_t flip, void* scratch, int cus,
+                              int64_t max_seg_len, Codec flip, void* scratch, int cus,
                               hipStream_t st) {
   const SegScratch sc = seg_scratch_carve(scratch, nseg);
   launch_seg_prep(offsets, nseg, sc, st);
@@ -360,12 +360,30 @@ int bitonic_sort_plan_i32(int32_t* keys, int64_t n, int ascending, const bitonic
   rc = bind_device(&r);
   if (rc) return rc;
   (void)hipGetLastError();
-  enqueue_plain(keys, (uint32_t)n, 64, ascending ? 0 : -1, r, (hipStream_t)stream, false);
+  enqueue_plain(keys, (uint32_t)n, 64, make_codec(BITONIC_KEY_I32, ascending), r, (hipStream_t)stream, false);
   return finish_launches();
 }
 
 int bitonic_sort_i32(int32_t* keys, int64_t n, int ascending, void* stream) {
   return bitonic_sort_plan_i32(keys, n, ascending, nullptr, stream);
+}
+
+int bitonic_sort_keys(void* keys, int64_t n, int key_type, int ascending, void* stream) {
+  if (key_type < BITONIC_KEY_I32 || key_type > BITONIC_KEY_F32) return BITONIC_EINVAL;
+  int32_t* k = static_cast<int32_t*>(keys);
+  int rc = check_sort_args(k, n);
+  if (rc) return rc;
+  Resolved r;
+  rc = resolve(nullptr, &r);
+  if (rc) return rc;
+  if (n <= 1) return BITONIC_OK;
+  fit_alignment(k, &r);
+  rc = bind_device(&r);
+  if (rc) return rc;
+  (void)hipGetLastError();
+  enqueue_plain(k, (uint32_t)n, 64, make_codec(key_type, ascending != 0), r, (hipStream_t)stream,
+                false);
+  return finish_launches();
 }
 
 int bitonic_network_phases_i32(int32_t* keys, int64_t n, int ascending, int last_phase,
@@ -381,7 +399,7 @@ int bitonic_network_phases_i32(int32_t* keys, int64_t n, int ascending, int last
   rc = bind_device(&r);
   if (rc) return rc;
   (void)hipGetLastError();
-  enqueue_plain(keys, (uint32_t)n, last_phase, ascending ? 0 : -1, r, (hipStream_t)stream, false);
+  enqueue_plain(keys, (uint32_t)n, last_phase, make_codec(BITONIC_KEY_I32, ascending), r, (hipStream_t)stream, false);
   return finish_launches();
 }
 
@@ -390,7 +408,7 @@ int64_t bitonic_plan_passes(int64_t n, const bitonic_plan* plan) {
   Resolved r;
   if (resolve(plan, &r)) return -1;
   if (n <= 1) return 0;
-  return enqueue_plain(nullptr, (uint32_t)n, 64, 0, r, nullptr, true);
+  return enqueue_plain(nullptr, (uint32_t)n, 64, Codec{0, 0}, r, nullptr, true);
 }
 
 int64_t bitonic_plan_describe(int64_t n, const bitonic_plan* plan, int32_t* kinds,
@@ -403,7 +421,7 @@ int64_t bitonic_plan_describe(int64_t n, const bitonic_plan* plan, int32_t* kind
   obs.kinds = kinds;
   obs.fuse = fuse;
   obs.cap = cap;
-  return enqueue_plain(nullptr, (uint32_t)n, 64, 0, r, nullptr, true, &obs);
+  return enqueue_plain(nullptr, (uint32_t)n, 64, Codec{0, 0}, r, nullptr, true, &obs);
 }
 
 int bitonic_sort_plan_events_i32(int32_t* keys, int64_t n, int ascending,
@@ -423,7 +441,7 @@ int bitonic_sort_plan_events_i32(int32_t* keys, int64_t n, int ascending,
   obs.events = reinterpret_cast<hipEvent_t*>(events);
   obs.nevents = nevents;
   (void)hipGetLastError();
-  enqueue_plain(keys, (uint32_t)n, 64, ascending ? 0 : -1, r, (hipStream_t)stream, false, &obs);
+  enqueue_plain(keys, (uint32_t)n, 64, make_codec(BITONIC_KEY_I32, ascending), r, (hipStream_t)stream, false, &obs);
   return finish_launches();
 }
 
@@ -444,12 +462,20 @@ int bitonic_sort_plan_launches_i32(int32_t* keys, int64_t n, int ascending,
   obs.first = first;
   obs.count = count;
   (void)hipGetLastError();
-  enqueue_plain(keys, (uint32_t)n, 64, ascending ? 0 : -1, r, (hipStream_t)stream, false, &obs);
+  enqueue_plain(keys, (uint32_t)n, 64, make_codec(BITONIC_KEY_I32, ascending), r, (hipStream_t)stream, false, &obs);
   return finish_launches();
 }
 
 int bitonic_sort_segmented_bounded_i32(int32_t* keys, const int64_t* offsets, int64_t nseg,
                                        int64_t max_seg_len, int ascending, void* stream) {
+  return bitonic_sort_segmented_keys(keys, offsets, nseg, max_seg_len, BITONIC_KEY_I32, ascending,
+                                     stream);
+}
+
+int bitonic_sort_segmented_keys(void* keys_v, const int64_t* offsets, int64_t nseg,
+                                int64_t max_seg_len, int key_type, int ascending, void* stream) {
+  int32_t* keys = static_cast<int32_t*>(keys_v);
+  if (key_type < BITONIC_KEY_I32 || key_type > BITONIC_KEY_F32) return BITONIC_EINVAL;
   if (nseg < 0 || max_seg_len < 0) return BITONIC_EINVAL;
   if (nseg >= (int64_t(1) << 31)) return BITONIC_EUNSUPPORTED;
   if (max_seg_len > (int64_t(1) << 31)) return BITONIC_EUNSUPPORTED;
@@ -475,8 +501,8 @@ int bitonic_sort_segmented_bounded_i32(int32_t* keys, const int64_t* offsets, in
   rc = stream_scratch(dev, st, seg_scratch_bytes(nseg), &base);
   if (rc) return rc;
   (void)hipGetLastError();
-  enqueue_segmented(keys, offsets, nseg, max_seg_len, ascending ? 0 : -1, base, device_cus(dev),
-                    st);
+  enqueue_segmented(keys, offsets, nseg, max_seg_len, make_codec(key_type, ascending != 0), base,
+                    device_cus(dev), st);
   return finish_launches();
 }
 
@@ -548,7 +574,7 @@ int bitonic_graph_capture_sort_i32(bitonic_graph** out, int32_t* keys, int64_t n
   rc = bind_device(&r);
   if (rc) return rc;
   return capture_graph(out, nullptr, [&](hipStream_t cs) {
-    if (n > 1) enqueue_plain(keys, (uint32_t)n, 64, ascending ? 0 : -1, r, cs, false);
+    if (n > 1) enqueue_plain(keys, (uint32_t)n, 64, make_codec(BITONIC_KEY_I32, ascending), r, cs, false);
   });
 }
 
@@ -568,7 +594,7 @@ int bitonic_graph_capture_segmented_i32(bitonic_graph** out, int32_t* keys,
   const int cus = device_cus(dev);
   rc = capture_graph(out, scratch, [&](hipStream_t cs) {
     if (nseg > 0)
-      enqueue_segmented(keys, offsets, nseg, max_seg_len, ascending ? 0 : -1, scratch, cus, cs);
+      enqueue_segmented(keys, offsets, nseg, max_seg_len, make_codec(BITONIC_KEY_I32, ascending), scratch, cus, cs);
   });
   if (rc && scratch) (void)hipFree(scratch);
   return rc;

@@ -1,0 +1,41 @@
+// Key codec shared by the host planner and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace bitonic {
+
+// Key codec: enc maps a stored 32-bit key to the sorting domain, dec maps it
+// back.  enc(x) = g(x) ^ flip with g(x) = x ^ ((x >> 31) & fmask):
+//  - int32:   fmask = 0, flip = 0 (ascending) or -1 (descending: ~ reverses
+//             signed order);
+//  - uint32:  fmask = 0, flip = INT32_MIN (ascending) or INT32_MAX
+//             (descending): toggling the sign bit turns unsigned order into
+//             signed order;
+//  - float32: fmask = INT32_MAX, flip as for int32: g flips the magnitude bits
+//             of negative values, which turns IEEE-754 bit patterns into
+//             signed integers in totalOrder (-NaN < -inf < ... < -0 < +0 <
+//             ... < +inf < +NaN).  g is its own inverse.
+struct Codec {
+  int32_t flip;
+  int32_t fmask;
+  __host__ __device__ __forceinline__ int32_t enc(int32_t x) const {
+    return x ^ ((x >> 31) & fmask) ^ flip;
+  }
+  __host__ __device__ __forceinline__ int32_t dec(int32_t y) const {
+    const int32_t z = y ^ flip;
+    return z ^ ((z >> 31) & fmask);
+  }
+};
+
+// Key types of the C interface (enum bitonic_key_type in bitonic.h).
+inline Codec make_codec(int key_type, bool ascending) {
+  switch (key_type) {
+    case 1: return Codec{ascending ? INT32_MIN : INT32_MAX, 0};          // uint32
+    case 2: return Codec{ascending ? 0 : -1, INT32_MAX};                 // float32
+    default: return Codec{ascending ? 0 : -1, 0};                        // int32
+  }
+}
+
+}  // namespace bitonic

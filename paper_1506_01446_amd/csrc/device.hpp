@@ -6,13 +6,14 @@
 
 #include <type_traits>
 
+#include "codec.hpp"
 #include "program.hpp"
 
 namespace bitonic {
 
-// Sentinel in the sorting domain.  Keys are sorted ascending after an XOR
-// with `flip` (0 for ascending, -1 for descending: ~x reverses signed order),
-// so the absent padding keys are always INT32_MAX there.
+// Sentinel in the sorting domain.  Stored keys are mapped by a Codec to the
+// sorting domain, where they are sorted as signed int32 ascending, so the
+// absent padding keys are always INT32_MAX there.
 constexpr int32_t kPad = 0x7FFFFFFF;
 
 template <int B, int E, class F>
@@ -134,7 +135,7 @@ __device__ __forceinline__ uint32_t slot_index(uint32_t base) {
 // `valid` keys of the tile exist; the rest read as the sentinel.
 template <class PR, int G>
 __device__ __forceinline__ void load_tile(int32_t (&x)[PR::R], const int32_t* __restrict__ tile,
-                                          uint32_t valid, int32_t flip, uint32_t tid) {
+                                          uint32_t valid, Codec cd, uint32_t tid) {
   constexpr Group gr = PR::value.g[G];
   const uint32_t base = deposit<free_mask(gr, PR::L)>(tid);
   if (valid >= (uint32_t)PR::T) {
@@ -145,23 +146,23 @@ __device__ __forceinline__ void load_tile(int32_t (&x)[PR::R], const int32_t* __
         const int4 v = *reinterpret_cast<const int4*>(tile + (i & ~3u));
         const int32_t e[4] = {v.x, v.y, v.z, v.w};
         static_for<0, 4>([&](auto C) {
-          x[4 * Q + C] = e[(o ^ C) & 3u] ^ flip;
+          x[4 * Q + C] = cd.enc(e[(o ^ C) & 3u]);
         });
       });
     } else {
-      static_for<0, PR::R>([&](auto J) { x[J] = tile[slot_index<PR, G, J>(base)] ^ flip; });
+      static_for<0, PR::R>([&](auto J) { x[J] = cd.enc(tile[slot_index<PR, G, J>(base)]); });
     }
   } else {
     static_for<0, PR::R>([&](auto J) {
       const uint32_t i = slot_index<PR, G, J>(base);
-      x[J] = i < valid ? (tile[i] ^ flip) : kPad;
+      x[J] = i < valid ? cd.enc(tile[i]) : kPad;
     });
   }
 }
 
 template <class PR, int G>
 __device__ __forceinline__ void store_tile(const int32_t (&x)[PR::R], int32_t* __restrict__ tile,
-                                           uint32_t valid, int32_t flip, uint32_t tid) {
+                                           uint32_t valid, Codec cd, uint32_t tid) {
   constexpr Group gr = PR::value.g[G];
   const uint32_t base = deposit<free_mask(gr, PR::L)>(tid);
   if (valid >= (uint32_t)PR::T) {
@@ -170,16 +171,16 @@ __device__ __forceinline__ void store_tile(const int32_t (&x)[PR::R], int32_t* _
         constexpr uint32_t o = goff(gr, 4u * Q);
         const uint32_t i = slot_index<PR, G, 4u * Q>(base);
         int32_t e[4];
-        static_for<0, 4>([&](auto C) { e[(o ^ C) & 3u] = x[4 * Q + C] ^ flip; });
+        static_for<0, 4>([&](auto C) { e[(o ^ C) & 3u] = cd.dec(x[4 * Q + C]); });
         *reinterpret_cast<int4*>(tile + (i & ~3u)) = make_int4(e[0], e[1], e[2], e[3]);
       });
     } else {
-      static_for<0, PR::R>([&](auto J) { tile[slot_index<PR, G, J>(base)] = x[J] ^ flip; });
+      static_for<0, PR::R>([&](auto J) { tile[slot_index<PR, G, J>(base)] = cd.dec(x[J]); });
     }
   } else {
     static_for<0, PR::R>([&](auto J) {
       const uint32_t i = slot_index<PR, G, J>(base);
-      if (i < valid) tile[i] = x[J] ^ flip;
+      if (i < valid) tile[i] = cd.dec(x[J]);
     });
   }
 }
@@ -220,11 +221,11 @@ __device__ __forceinline__ void pass_steps(int32_t (&x)[4 << F]) {
 // `valid` real keys.  All threads of the block must call it.
 template <class PR>
 __device__ __forceinline__ void tile_program(int32_t* __restrict__ tile, uint32_t valid,
-                                             int32_t flip, int32_t* lds, uint32_t tid) {
+                                             Codec cd, int32_t* lds, uint32_t tid) {
   int32_t x[PR::R];
-  load_tile<PR, 0>(x, tile, valid, flip, tid);
+  load_tile<PR, 0>(x, tile, valid, cd, tid);
   run_from<PR, 0>(x, lds, tid);
-  store_tile<PR, PR::value.ngroups - 1>(x, tile, valid, flip, tid);
+  store_tile<PR, PR::value.ngroups - 1>(x, tile, valid, cd, tid);
 }
 
 }  // namespace bitonic

@@ -15,7 +15,7 @@
 //  step_kernel            one step, one compare-exchange per thread, in global
 //                         memory (the basic scheme of section 3.3)
 //
-// All kernels sort ascending in the XOR domain (key ^ flip) and treat indices
+// All kernels sort ascending in the codec domain (see Codec) and treat indices
 // >= n as absent INT32_MAX sentinels.
 #include "device.hpp"
 #include "launch.hpp"
@@ -25,13 +25,13 @@ namespace bitonic {
 // One tile per workgroup.
 template <int L, int RL, int KIND>
 __global__ __launch_bounds__(1 << (L - RL)) void tile_kernel(int32_t* __restrict__ keys,
-                                                             uint32_t n, int32_t flip) {
+                                                             uint32_t n, Codec cd) {
   using PR = Prog<L, RL, KIND>;
   __shared__ int32_t lds[PR::T];
   const uint32_t t0 = (uint32_t)blockIdx.x << L;
   const uint32_t left = n - t0;
   const uint32_t valid = left < (uint32_t)PR::T ? left : (uint32_t)PR::T;
-  tile_program<PR>(keys + t0, valid, flip, lds, threadIdx.x);
+  tile_program<PR>(keys + t0, valid, cd, lds, threadIdx.x);
 }
 
 // Tiles blockIdx.x, blockIdx.x + gridDim.x, ... of keys[0, n).  The keys of a
@@ -43,7 +43,7 @@ __global__ __launch_bounds__(1 << (L - RL)) void tile_kernel(int32_t* __restrict
 // all of them live in registers.
 template <int L, int RL, int KIND>
 __global__ __launch_bounds__(1 << (L - RL)) void tile_loop_kernel(int32_t* __restrict__ keys,
-                                                                  uint32_t n, int32_t flip) {
+                                                                  uint32_t n, Codec cd) {
   using PR = Prog<L, RL, KIND>;
   __shared__ int32_t lds[PR::T];
   const uint32_t ntiles = (uint32_t)(((uint64_t)n + PR::T - 1) >> L);
@@ -53,16 +53,16 @@ __global__ __launch_bounds__(1 << (L - RL)) void tile_loop_kernel(int32_t* __res
   };
   uint32_t tile = blockIdx.x;
   int32_t x[PR::R];
-  load_tile<PR, 0>(x, keys + ((size_t)tile << L), valid_of(tile), flip, threadIdx.x);
+  load_tile<PR, 0>(x, keys + ((size_t)tile << L), valid_of(tile), cd, threadIdx.x);
   for (;;) {
     uint32_t tid = threadIdx.x;
     asm volatile("" : "+v"(tid));
     const uint32_t next = tile + gridDim.x;
     const bool more = next < ntiles;
     int32_t y[PR::R];
-    if (more) load_tile<PR, 0>(y, keys + ((size_t)next << L), valid_of(next), flip, tid);
+    if (more) load_tile<PR, 0>(y, keys + ((size_t)next << L), valid_of(next), cd, tid);
     run_from<PR, 0>(x, lds, tid);
-    store_tile<PR, PR::value.ngroups - 1>(x, keys + ((size_t)tile << L), valid_of(tile), flip,
+    store_tile<PR, PR::value.ngroups - 1>(x, keys + ((size_t)tile << L), valid_of(tile), cd,
                                            tid);
     if (!more) break;
     static_for<0, PR::R>([&](auto J) { x[J] = y[J]; });
@@ -88,36 +88,36 @@ __device__ __forceinline__ uint32_t pass_row_index(uint32_t base, uint32_t span,
 // stored in reverse order, so their registers are reversed.
 template <int F, bool MIRROR, int RHO, bool VEC>
 __device__ __forceinline__ void pass_load_row(int32_t* x, const int32_t* __restrict__ keys,
-                                              uint32_t ri, uint32_t n, int32_t flip) {
+                                              uint32_t ri, uint32_t n, Codec cd) {
   constexpr bool rev = MIRROR && (RHO & ((1 << F) >> 1));
   if constexpr (VEC) {
     const int4 v = *reinterpret_cast<const int4*>(keys + (ri & ~3u));
-    x[4 * RHO + (rev ? 3 : 0)] = v.x ^ flip;
-    x[4 * RHO + (rev ? 2 : 1)] = v.y ^ flip;
-    x[4 * RHO + (rev ? 1 : 2)] = v.z ^ flip;
-    x[4 * RHO + (rev ? 0 : 3)] = v.w ^ flip;
+    x[4 * RHO + (rev ? 3 : 0)] = cd.enc(v.x);
+    x[4 * RHO + (rev ? 2 : 1)] = cd.enc(v.y);
+    x[4 * RHO + (rev ? 1 : 2)] = cd.enc(v.z);
+    x[4 * RHO + (rev ? 0 : 3)] = cd.enc(v.w);
   } else {
 #pragma unroll
     for (uint32_t c = 0; c < 4; ++c) {
       const uint32_t i = ri ^ c;
-      x[4 * RHO + c] = i < n ? (keys[i] ^ flip) : kPad;
+      x[4 * RHO + c] = i < n ? cd.enc(keys[i]) : kPad;
     }
   }
 }
 
 template <int F, bool MIRROR, int RHO, bool VEC>
 __device__ __forceinline__ void pass_store_row(const int32_t* x, int32_t* __restrict__ keys,
-                                               uint32_t ri, uint32_t n, int32_t flip) {
+                                               uint32_t ri, uint32_t n, Codec cd) {
   constexpr bool rev = MIRROR && (RHO & ((1 << F) >> 1));
   if constexpr (VEC) {
     *reinterpret_cast<int4*>(keys + (ri & ~3u)) =
-        make_int4(x[4 * RHO + (rev ? 3 : 0)] ^ flip, x[4 * RHO + (rev ? 2 : 1)] ^ flip,
-                  x[4 * RHO + (rev ? 1 : 2)] ^ flip, x[4 * RHO + (rev ? 0 : 3)] ^ flip);
+        make_int4(cd.dec(x[4 * RHO + (rev ? 3 : 0)]), cd.dec(x[4 * RHO + (rev ? 2 : 1)]),
+                  cd.dec(x[4 * RHO + (rev ? 1 : 2)]), cd.dec(x[4 * RHO + (rev ? 0 : 3)]));
   } else {
 #pragma unroll
     for (uint32_t c = 0; c < 4; ++c) {
       const uint32_t i = ri ^ c;
-      if (i < n) keys[i] = x[4 * RHO + c] ^ flip;
+      if (i < n) keys[i] = cd.dec(x[4 * RHO + c]);
     }
   }
 }
@@ -133,7 +133,7 @@ __device__ __forceinline__ void pass_store_row(const int32_t* x, int32_t* __rest
 // n goes key by key, rows at or past n are sentinels.
 template <int F, bool MIRROR, bool BOUNDED>
 __global__ __launch_bounds__(256) void global_pass_kernel(int32_t* __restrict__ keys, uint32_t n,
-                                                          int q, int32_t flip, uint32_t g0) {
+                                                          int q, Codec cd, uint32_t g0) {
   constexpr int ROWS = 1 << F;
   constexpr int TOP = ROWS >> 1;
   int32_t x[4 * ROWS];
@@ -153,10 +153,10 @@ __global__ __launch_bounds__(256) void global_pass_kernel(int32_t* __restrict__ 
     static_for<0, ROWS>([&](auto RHO) {
       constexpr bool rev = MIRROR && (RHO & TOP);
       const int4 v = *row_ptr(RHO);
-      x[4 * RHO + (rev ? 3 : 0)] = v.x ^ flip;
-      x[4 * RHO + (rev ? 2 : 1)] = v.y ^ flip;
-      x[4 * RHO + (rev ? 1 : 2)] = v.z ^ flip;
-      x[4 * RHO + (rev ? 0 : 3)] = v.w ^ flip;
+      x[4 * RHO + (rev ? 3 : 0)] = cd.enc(v.x);
+      x[4 * RHO + (rev ? 2 : 1)] = cd.enc(v.y);
+      x[4 * RHO + (rev ? 1 : 2)] = cd.enc(v.z);
+      x[4 * RHO + (rev ? 0 : 3)] = cd.enc(v.w);
     });
     // Scheduling fences keep the compiler from interleaving the steps with
     // the loads and stores, which would hold many more registers live.
@@ -165,8 +165,8 @@ __global__ __launch_bounds__(256) void global_pass_kernel(int32_t* __restrict__ 
     __builtin_amdgcn_sched_barrier(0);
     static_for<0, ROWS>([&](auto RHO) {
       constexpr bool rev = MIRROR && (RHO & TOP);
-      *row_ptr(RHO) = make_int4(x[4 * RHO + (rev ? 3 : 0)] ^ flip, x[4 * RHO + (rev ? 2 : 1)] ^ flip,
-                                x[4 * RHO + (rev ? 1 : 2)] ^ flip, x[4 * RHO + (rev ? 0 : 3)] ^ flip);
+      *row_ptr(RHO) = make_int4(cd.dec(x[4 * RHO + (rev ? 3 : 0)]), cd.dec(x[4 * RHO + (rev ? 2 : 1)]),
+                                cd.dec(x[4 * RHO + (rev ? 1 : 2)]), cd.dec(x[4 * RHO + (rev ? 0 : 3)]));
       __builtin_amdgcn_sched_barrier(0);
     });
   } else {
@@ -178,17 +178,17 @@ __global__ __launch_bounds__(256) void global_pass_kernel(int32_t* __restrict__ 
     static_for<0, ROWS>([&](auto RHO) {
       const uint32_t ri = pass_row_index<F, MIRROR, RHO>(base, span, q);
       if ((ri | 3u) < n)
-        pass_load_row<F, MIRROR, RHO, true>(x, keys, ri, n, flip);
+        pass_load_row<F, MIRROR, RHO, true>(x, keys, ri, n, cd);
       else
-        pass_load_row<F, MIRROR, RHO, false>(x, keys, ri, n, flip);
+        pass_load_row<F, MIRROR, RHO, false>(x, keys, ri, n, cd);
     });
     pass_steps<F, MIRROR>(x);
     static_for<0, ROWS>([&](auto RHO) {
       const uint32_t ri = pass_row_index<F, MIRROR, RHO>(base, span, q);
       if ((ri | 3u) < n)
-        pass_store_row<F, MIRROR, RHO, true>(x, keys, ri, n, flip);
+        pass_store_row<F, MIRROR, RHO, true>(x, keys, ri, n, cd);
       else
-        pass_store_row<F, MIRROR, RHO, false>(x, keys, ri, n, flip);
+        pass_store_row<F, MIRROR, RHO, false>(x, keys, ri, n, cd);
     });
   }
 }
@@ -210,14 +210,14 @@ __device__ __forceinline__ void lds_step(int32_t* s, uint32_t T, int sb, bool mi
 // (each a mirror step and half-cleaners); tail != 0: strides 2^(L-1)..1.
 __global__ __launch_bounds__(1024) void lds_network_kernel(int32_t* __restrict__ keys, uint32_t n,
                                                            int L, int p_first, int p_last,
-                                                           int tail, int32_t flip) {
+                                                           int tail, Codec cd) {
   extern __shared__ int32_t s[];
   const uint32_t T = 1u << L;
   const uint32_t t0 = (uint32_t)blockIdx.x << L;
   const uint32_t left = n - t0;
   const uint32_t valid = left < T ? left : T;
   for (uint32_t i = threadIdx.x; i < T; i += blockDim.x)
-    s[i] = i < valid ? (keys[t0 + i] ^ flip) : kPad;
+    s[i] = i < valid ? cd.enc(keys[t0 + i]) : kPad;
   __syncthreads();
   if (tail) {
     for (int sb = L - 1; sb >= 0; --sb) lds_step(s, T, sb, false);
@@ -227,22 +227,22 @@ __global__ __launch_bounds__(1024) void lds_network_kernel(int32_t* __restrict__
       for (int sb = p - 2; sb >= 0; --sb) lds_step(s, T, sb, false);
     }
   }
-  for (uint32_t i = threadIdx.x; i < valid; i += blockDim.x) keys[t0 + i] = s[i] ^ flip;
+  for (uint32_t i = threadIdx.x; i < valid; i += blockDim.x) keys[t0 + i] = cd.dec(s[i]);
 }
 
 // One step of the network in global memory, one comparator per thread.
 __global__ __launch_bounds__(256) void step_kernel(int32_t* __restrict__ keys, uint32_t n,
                                                    uint32_t half, int sb, int mirror,
-                                                   int32_t flip) {
+                                                   Codec cd) {
   const uint32_t c = blockIdx.x * 256u + threadIdx.x;
   if (c >= half) return;
   const uint32_t i = ((c >> sb) << (sb + 1)) | (c & ((1u << sb) - 1u));
   const uint32_t j = mirror ? (i ^ ((2u << sb) - 1u)) : (i | (1u << sb));
   if (j >= n) return;
-  const int32_t a = keys[i] ^ flip, b = keys[j] ^ flip;
+  const int32_t a = cd.enc(keys[i]), b = cd.enc(keys[j]);
   if (a > b) {
-    keys[i] = b ^ flip;
-    keys[j] = a ^ flip;
+    keys[i] = cd.dec(b);
+    keys[j] = cd.dec(a);
   }
 }
 
@@ -252,28 +252,28 @@ __global__ __launch_bounds__(256) void step_kernel(int32_t* __restrict__ keys, u
 constexpr int kTileRegLog = kTileRegLogPlain;
 
 template <int L>
-static void launch_tile_L(int kind, int32_t* keys, uint32_t n, int32_t flip, uint32_t max_blocks,
+static void launch_tile_L(int kind, int32_t* keys, uint32_t n, Codec cd, uint32_t max_blocks,
                           hipStream_t st) {
   const uint32_t ntiles = (uint32_t)(((uint64_t)n + (1u << L) - 1) >> L);
   constexpr int NT = 1 << (L - kTileRegLog);
   if (kind == 0) {
-    tile_kernel<L, kTileRegLog, 0><<<ntiles, NT, 0, st>>>(keys, n, flip);
+    tile_kernel<L, kTileRegLog, 0><<<ntiles, NT, 0, st>>>(keys, n, cd);
   } else if (max_blocks == 0 || max_blocks >= ntiles) {
-    tile_kernel<L, kTileRegLog, 1><<<ntiles, NT, 0, st>>>(keys, n, flip);
+    tile_kernel<L, kTileRegLog, 1><<<ntiles, NT, 0, st>>>(keys, n, cd);
   } else {
-    tile_loop_kernel<L, kTileRegLog, 1><<<max_blocks, NT, 0, st>>>(keys, n, flip);
+    tile_loop_kernel<L, kTileRegLog, 1><<<max_blocks, NT, 0, st>>>(keys, n, cd);
   }
 }
 
 bool tile_log2_supported(int L) { return L >= kTileMinLog2 && L <= kTileMaxLog2; }
 
-void launch_tile(int L, int kind, int32_t* keys, uint32_t n, int32_t flip, uint32_t max_blocks,
+void launch_tile(int L, int kind, int32_t* keys, uint32_t n, Codec cd, uint32_t max_blocks,
                  hipStream_t st) {
   switch (L) {
-    case 11: launch_tile_L<11>(kind, keys, n, flip, max_blocks, st); break;
-    case 12: launch_tile_L<12>(kind, keys, n, flip, max_blocks, st); break;
-    case 13: launch_tile_L<13>(kind, keys, n, flip, max_blocks, st); break;
-    case 14: launch_tile_L<14>(kind, keys, n, flip, max_blocks, st); break;
+    case 11: launch_tile_L<11>(kind, keys, n, cd, max_blocks, st); break;
+    case 12: launch_tile_L<12>(kind, keys, n, cd, max_blocks, st); break;
+    case 13: launch_tile_L<13>(kind, keys, n, cd, max_blocks, st); break;
+    case 14: launch_tile_L<14>(kind, keys, n, cd, max_blocks, st); break;
     default: break;
   }
 }
@@ -291,53 +291,53 @@ static void global_pass_threads(uint32_t n, int q, int f, uint32_t* full, uint32
 }
 
 template <int F, bool MIRROR>
-static void launch_global_FM(int32_t* keys, uint32_t n, int q, int32_t flip, hipStream_t st) {
+static void launch_global_FM(int32_t* keys, uint32_t n, int q, Codec cd, hipStream_t st) {
   uint32_t full = 0, total = 0;
   global_pass_threads(n, q, F, &full, &total);
   if (full > 0)  // full is a multiple of 2^(q-2) >= 256
-    global_pass_kernel<F, MIRROR, false><<<full / 256, 256, 0, st>>>(keys, n, q, flip, 0u);
+    global_pass_kernel<F, MIRROR, false><<<full / 256, 256, 0, st>>>(keys, n, q, cd, 0u);
   if (total > full)
     global_pass_kernel<F, MIRROR, true><<<(total - full + 255) / 256, 256, 0, st>>>(keys, n, q,
-                                                                                  flip, full);
+                                                                                  cd, full);
 }
 
 template <int F>
-static void launch_global_F(bool mirror, int32_t* keys, uint32_t n, int q, int32_t flip,
+static void launch_global_F(bool mirror, int32_t* keys, uint32_t n, int q, Codec cd,
                             hipStream_t st) {
   if (mirror)
-    launch_global_FM<F, true>(keys, n, q, flip, st);
+    launch_global_FM<F, true>(keys, n, q, cd, st);
   else
-    launch_global_FM<F, false>(keys, n, q, flip, st);
+    launch_global_FM<F, false>(keys, n, q, cd, st);
 }
 
-void launch_global_pass(int f, bool mirror, int32_t* keys, uint32_t n, int q, int32_t flip,
+void launch_global_pass(int f, bool mirror, int32_t* keys, uint32_t n, int q, Codec cd,
                         hipStream_t st) {
   switch (f) {
-    case 1: launch_global_F<1>(mirror, keys, n, q, flip, st); break;
-    case 2: launch_global_F<2>(mirror, keys, n, q, flip, st); break;
-    case 3: launch_global_F<3>(mirror, keys, n, q, flip, st); break;
-    case 4: launch_global_F<4>(mirror, keys, n, q, flip, st); break;
-    case 5: launch_global_F<5>(mirror, keys, n, q, flip, st); break;
+    case 1: launch_global_F<1>(mirror, keys, n, q, cd, st); break;
+    case 2: launch_global_F<2>(mirror, keys, n, q, cd, st); break;
+    case 3: launch_global_F<3>(mirror, keys, n, q, cd, st); break;
+    case 4: launch_global_F<4>(mirror, keys, n, q, cd, st); break;
+    case 5: launch_global_F<5>(mirror, keys, n, q, cd, st); break;
     default: break;
   }
 }
 
 void launch_lds_network(int L, int p_first, int p_last, bool tail, int32_t* keys, uint32_t n,
-                        int32_t flip, hipStream_t st) {
+                        Codec cd, hipStream_t st) {
   const uint32_t T = 1u << L;
   const uint32_t blocks = (uint32_t)(((uint64_t)n + T - 1) >> L);
   uint32_t threads = T / 2;
   if (threads > 1024) threads = 1024;
   if (threads < 64) threads = 64;
   lds_network_kernel<<<blocks, threads, T * sizeof(int32_t), st>>>(keys, n, L, p_first, p_last,
-                                                                   tail ? 1 : 0, flip);
+                                                                   tail ? 1 : 0, cd);
 }
 
-void launch_step(int sb, bool mirror, int32_t* keys, uint32_t n, uint32_t N, int32_t flip,
+void launch_step(int sb, bool mirror, int32_t* keys, uint32_t n, uint32_t N, Codec cd,
                  hipStream_t st) {
   const uint32_t half = N >> 1;
   const uint32_t blocks = (half + 255) / 256;
-  step_kernel<<<blocks, 256, 0, st>>>(keys, n, half, sb, mirror ? 1 : 0, flip);
+  step_kernel<<<blocks, 256, 0, st>>>(keys, n, half, sb, mirror ? 1 : 0, cd);
 }
 
 }  // namespace bitonic

@@ -155,7 +155,7 @@ template <int L>
 __device__ __attribute__((noinline)) void seg_small_item(int32_t* __restrict__ keys,
                                                const int64_t* __restrict__ offsets,
                                                const uint32_t* __restrict__ ids, uint32_t first,
-                                               uint32_t count, int32_t flip, int32_t* lds) {
+                                               uint32_t count, Codec cd, int32_t* lds) {
   using PR = Prog<L, kTileRegLogSeg, 2>;
   constexpr uint32_t NT = PR::NT;
   const uint32_t grp = threadIdx.x / NT;
@@ -168,12 +168,12 @@ __device__ __attribute__((noinline)) void seg_small_item(int32_t* __restrict__ k
     p = keys + off;
     len = (uint32_t)(offsets[s + 1] - off);
   }
-  tile_program<PR>(p, len, flip, lds + grp * PR::T, ltid);
+  tile_program<PR>(p, len, cd, lds + grp * PR::T, ltid);
 }
 
 __global__ __launch_bounds__(kSegThreads) void seg_small_kernel(
     int32_t* __restrict__ keys, const int64_t* __restrict__ offsets, SegMeta* __restrict__ meta,
-    const uint32_t* __restrict__ small_ids, int32_t flip) {
+    const uint32_t* __restrict__ small_ids, Codec cd) {
   __shared__ int32_t lds[kSegThreads << kTileRegLogSeg];
   __shared__ uint32_t item_s;
   const uint32_t total = meta->small_items;
@@ -192,15 +192,15 @@ __global__ __launch_bounds__(kSegThreads) void seg_small_kernel(
     const uint32_t left = meta->small_count[ci] - k * per;
     const uint32_t count = left < per ? left : per;
     switch (cls) {
-      case 13: seg_small_item<13>(keys, offsets, small_ids, first, count, flip, lds); break;
-      case 12: seg_small_item<12>(keys, offsets, small_ids, first, count, flip, lds); break;
-      case 11: seg_small_item<11>(keys, offsets, small_ids, first, count, flip, lds); break;
-      case 10: seg_small_item<10>(keys, offsets, small_ids, first, count, flip, lds); break;
-      case 9: seg_small_item<9>(keys, offsets, small_ids, first, count, flip, lds); break;
-      case 8: seg_small_item<8>(keys, offsets, small_ids, first, count, flip, lds); break;
-      case 7: seg_small_item<7>(keys, offsets, small_ids, first, count, flip, lds); break;
-      case 6: seg_small_item<6>(keys, offsets, small_ids, first, count, flip, lds); break;
-      default: seg_small_item<5>(keys, offsets, small_ids, first, count, flip, lds); break;
+      case 13: seg_small_item<13>(keys, offsets, small_ids, first, count, cd, lds); break;
+      case 12: seg_small_item<12>(keys, offsets, small_ids, first, count, cd, lds); break;
+      case 11: seg_small_item<11>(keys, offsets, small_ids, first, count, cd, lds); break;
+      case 10: seg_small_item<10>(keys, offsets, small_ids, first, count, cd, lds); break;
+      case 9: seg_small_item<9>(keys, offsets, small_ids, first, count, cd, lds); break;
+      case 8: seg_small_item<8>(keys, offsets, small_ids, first, count, cd, lds); break;
+      case 7: seg_small_item<7>(keys, offsets, small_ids, first, count, cd, lds); break;
+      case 6: seg_small_item<6>(keys, offsets, small_ids, first, count, cd, lds); break;
+      default: seg_small_item<5>(keys, offsets, small_ids, first, count, cd, lds); break;
     }
   }
 }
@@ -226,7 +226,7 @@ template <int KIND>
 __global__ __launch_bounds__(kSegThreads) void seg_tile_kernel(
     int32_t* __restrict__ keys, const int64_t* __restrict__ offsets,
     const SegMeta* __restrict__ meta, const uint32_t* __restrict__ big_ids,
-    const uint64_t* __restrict__ big_tiles, int cls_min, int32_t flip) {
+    const uint64_t* __restrict__ big_tiles, int cls_min, Codec cd) {
   using PR = Prog<kSegTileLog, kTileRegLogSeg, KIND>;
   static_assert(PR::NT == kSegThreads, "one tile per workgroup");
   __shared__ int32_t lds[PR::T];
@@ -244,7 +244,7 @@ __global__ __launch_bounds__(kSegThreads) void seg_tile_kernel(
     const uint64_t t0 = tile << kSegTileLog;
     const uint64_t left = len - t0;
     const uint32_t valid = left < (uint64_t)PR::T ? (uint32_t)left : (uint32_t)PR::T;
-    tile_program<PR>(keys + off + t0, valid, flip, lds, tid);
+    tile_program<PR>(keys + off + t0, valid, cd, lds, tid);
     __syncthreads();  // LDS reuse by the next tile
   }
 }
@@ -271,7 +271,7 @@ template <int F, bool MIRROR>
 __global__ __launch_bounds__(kSegThreads) void seg_pass_kernel(
     int32_t* __restrict__ keys, const int64_t* __restrict__ offsets,
     const SegMeta* __restrict__ meta, const uint32_t* __restrict__ big_ids,
-    const uint64_t* __restrict__ big_keys, int cls, int q, int32_t flip) {
+    const uint64_t* __restrict__ big_keys, int cls, int q, Codec cd) {
   constexpr int ROWS = 1 << F;
   constexpr int TOP = ROWS >> 1;
   constexpr int UNIT_LOG = 10 + F;  // keys per unit = 1024 columns x 2^F rows
@@ -295,14 +295,14 @@ __global__ __launch_bounds__(kSegThreads) void seg_pass_kernel(
     static_for<0, ROWS>([&](auto RHO) {
       static_for<0, 4>([&](auto J) {
         const uint32_t idx = seg_pass_index<F, MIRROR, RHO, J>(blk, c0, q);
-        x[4 * RHO + J] = idx < len ? (a[idx] ^ flip) : kPad;
+        x[4 * RHO + J] = idx < len ? cd.enc(a[idx]) : kPad;
       });
     });
     pass_steps<F, MIRROR>(x);
     static_for<0, ROWS>([&](auto RHO) {
       static_for<0, 4>([&](auto J) {
         const uint32_t idx = seg_pass_index<F, MIRROR, RHO, J>(blk, c0, q);
-        if (idx < len) a[idx] = x[4 * RHO + J] ^ flip;
+        if (idx < len) a[idx] = cd.dec(x[4 * RHO + J]);
       });
     });
   }
@@ -316,41 +316,41 @@ void launch_seg_prep(const int64_t* offsets, int64_t nseg, const SegScratch& sc,
                                       sc.big_keys, sc.big_tiles);
 }
 
-void launch_seg_small(int32_t* keys, const int64_t* offsets, const SegScratch& sc, int32_t flip,
+void launch_seg_small(int32_t* keys, const int64_t* offsets, const SegScratch& sc, Codec cd,
                       int grid, hipStream_t st) {
-  seg_small_kernel<<<grid, kSegThreads, 0, st>>>(keys, offsets, sc.meta, sc.small_ids, flip);
+  seg_small_kernel<<<grid, kSegThreads, 0, st>>>(keys, offsets, sc.meta, sc.small_ids, cd);
 }
 
 void launch_seg_tiles(bool merge, int32_t* keys, const int64_t* offsets, const SegScratch& sc,
-                      int cls_min, int32_t flip, int grid, hipStream_t st) {
+                      int cls_min, Codec cd, int grid, hipStream_t st) {
   if (merge)
     seg_tile_kernel<3><<<grid, kSegThreads, 0, st>>>(keys, offsets, sc.meta, sc.big_ids,
-                                                     sc.big_tiles, cls_min, flip);
+                                                     sc.big_tiles, cls_min, cd);
   else
     seg_tile_kernel<2><<<grid, kSegThreads, 0, st>>>(keys, offsets, sc.meta, sc.big_ids,
-                                                     sc.big_tiles, cls_min, flip);
+                                                     sc.big_tiles, cls_min, cd);
 }
 
 template <int F>
 static void launch_seg_pass_F(bool mirror, int32_t* keys, const int64_t* offsets,
-                              const SegScratch& sc, int cls, int q, int32_t flip, int grid,
+                              const SegScratch& sc, int cls, int q, Codec cd, int grid,
                               hipStream_t st) {
   if (mirror)
     seg_pass_kernel<F, true><<<grid, kSegThreads, 0, st>>>(keys, offsets, sc.meta, sc.big_ids,
-                                                           sc.big_keys, cls, q, flip);
+                                                           sc.big_keys, cls, q, cd);
   else
     seg_pass_kernel<F, false><<<grid, kSegThreads, 0, st>>>(keys, offsets, sc.meta, sc.big_ids,
-                                                            sc.big_keys, cls, q, flip);
+                                                            sc.big_keys, cls, q, cd);
 }
 
 void launch_seg_pass(int f, bool mirror, int32_t* keys, const int64_t* offsets,
-                     const SegScratch& sc, int cls, int q, int32_t flip, int grid,
+                     const SegScratch& sc, int cls, int q, Codec cd, int grid,
                      hipStream_t st) {
   switch (f) {
-    case 1: launch_seg_pass_F<1>(mirror, keys, offsets, sc, cls, q, flip, grid, st); break;
-    case 2: launch_seg_pass_F<2>(mirror, keys, offsets, sc, cls, q, flip, grid, st); break;
-    case 3: launch_seg_pass_F<3>(mirror, keys, offsets, sc, cls, q, flip, grid, st); break;
-    case 4: launch_seg_pass_F<4>(mirror, keys, offsets, sc, cls, q, flip, grid, st); break;
+    case 1: launch_seg_pass_F<1>(mirror, keys, offsets, sc, cls, q, cd, grid, st); break;
+    case 2: launch_seg_pass_F<2>(mirror, keys, offsets, sc, cls, q, cd, grid, st); break;
+    case 3: launch_seg_pass_F<3>(mirror, keys, offsets, sc, cls, q, cd, grid, st); break;
+    case 4: launch_seg_pass_F<4>(mirror, keys, offsets, sc, cls, q, cd, grid, st); break;
     default: break;
   }
 }

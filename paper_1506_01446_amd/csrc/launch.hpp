@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "codec.hpp"
+
 namespace bitonic {
 
 constexpr int kTileRegLogPlain = 5;  // 32 keys per thread in the tile kernels
@@ -17,20 +19,20 @@ bool tile_log2_supported(int L);
 // Tile sort (kind 0: phases 1..L) or tile merge (kind 1: strides
 // 2^(L-1)..1) over every 2^L tile of keys[0, n).  The merge runs at most
 // max_blocks workgroups (0 = one per tile), each looping over its tiles.
-void launch_tile(int L, int kind, int32_t* keys, uint32_t n, int32_t flip, uint32_t max_blocks,
+void launch_tile(int L, int kind, int32_t* keys, uint32_t n, Codec cd, uint32_t max_blocks,
                  hipStream_t st);
 
 // f fused steps on bits q+f-1 .. q (the first one the mirror step if
 // `mirror`).  Requires q >= 8, q + f <= 31, 1 <= f <= kFuseMax.
-void launch_global_pass(int f, bool mirror, int32_t* keys, uint32_t n, int q, int32_t flip,
+void launch_global_pass(int f, bool mirror, int32_t* keys, uint32_t n, int q, Codec cd,
                         hipStream_t st);
 
 // LDS network on 2^L tiles (L <= kLdsNetworkMaxLog2).
 void launch_lds_network(int L, int p_first, int p_last, bool tail, int32_t* keys, uint32_t n,
-                        int32_t flip, hipStream_t st);
+                        Codec cd, hipStream_t st);
 
 // One step (bit sb; mirror or half-cleaner) over keys[0, n) padded to N.
-void launch_step(int sb, bool mirror, int32_t* keys, uint32_t n, uint32_t N, int32_t flip,
+void launch_step(int sb, bool mirror, int32_t* keys, uint32_t n, uint32_t N, Codec cd,
                  hipStream_t st);
 
 // Input generator.

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "codec.hpp"
+
 namespace bitonic {
 
 constexpr int kTileRegLogSeg = 5;  // 32 keys per thread
@@ -53,14 +55,14 @@ inline SegScratch seg_scratch_carve(void* base, int64_t nseg) {
 }
 
 void launch_seg_prep(const int64_t* offsets, int64_t nseg, const SegScratch& sc, hipStream_t st);
-void launch_seg_small(int32_t* keys, const int64_t* offsets, const SegScratch& sc, int32_t flip,
+void launch_seg_small(int32_t* keys, const int64_t* offsets, const SegScratch& sc, Codec cd,
                       int grid, hipStream_t st);
 // Tile sort (merge == false) or tile merge of the big segments of class >= cls_min.
 void launch_seg_tiles(bool merge, int32_t* keys, const int64_t* offsets, const SegScratch& sc,
-                      int cls_min, int32_t flip, int grid, hipStream_t st);
+                      int cls_min, Codec cd, int grid, hipStream_t st);
 // f fused steps on bits q+f-1 .. q of the big segments of class >= cls.
 void launch_seg_pass(int f, bool mirror, int32_t* keys, const int64_t* offsets,
-                     const SegScratch& sc, int cls, int q, int32_t flip, int grid,
+                     const SegScratch& sc, int cls, int q, Codec cd, int grid,
                      hipStream_t st);
 
 }  // namespace bitonic

@@ -269,3 +269,42 @@ def test_maximum_size(n):
         assert below <= i < upto, i
     del src, t
     torch.cuda.empty_cache()
+
+
+# -- other 32-bit key types ---------------------------------------------------------
+
+TOTAL_ORDER_BITS = [0xFFC00001, 0xFFC00000, 0xFF800001, 0xFF800000, 0xC0000000, 0xBF800000,
+                    0x80000001, 0x80000000, 0x00000000, 0x00000001, 0x3F800000, 0x40000000,
+                    0x7F800000, 0x7F800001, 0x7FC00000, 0x7FC00001]
+
+
+@pytest.mark.parametrize("key_type", ["uint32", "float32"])
+def test_key_types(key_type):
+    """Random 32-bit patterns (for float32: NaNs, infinities, subnormals and
+    zeros of both signs included) and the totalOrder special values."""
+    kt = O.KEY_U32 if key_type == "uint32" else O.KEY_F32
+    dt = np.uint32 if key_type == "uint32" else np.float32
+    special = np.array(TOTAL_ORDER_BITS * 300, dtype=np.uint32)
+    for n in (3, 1000, 300001, (1 << 20) + 1):
+        bits = W.uniform_i32(n + 17, n).view(np.uint32).copy()
+        bits[: min(n, special.size)] = special[: min(n, special.size)]
+        keys = bits.view(dt)
+        for asc in (True, False):
+            t = torch.from_numpy(bits.view(np.int32).copy()).cuda()
+            B.bitonic_sort_keys(t, asc, key_type)
+            torch.cuda.synchronize()
+            want = O.sort_keys(keys, kt, asc).view(np.int32)
+            assert np.array_equal(t.cpu().numpy(), want), (key_type, n, asc)
+
+
+def test_key_types_segmented():
+    keys, off = W.batched_workload(nseg=400, seed=12, max_log2=15)
+    for key_type, kt in (("uint32", O.KEY_U32), ("float32", O.KEY_F32)):
+        dt = np.uint32 if kt == O.KEY_U32 else np.float32
+        for asc in (True, False):
+            t = torch.from_numpy(keys.copy()).cuda()
+            o = torch.from_numpy(off).cuda()
+            B.bitonic_sort_segmented_keys(t, o, asc, key_type)
+            torch.cuda.synchronize()
+            want = O.sort_segmented_keys(keys.view(dt), off, kt, asc).view(np.int32)
+            assert np.array_equal(t.cpu().numpy(), want), (key_type, asc)

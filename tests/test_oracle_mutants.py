@@ -63,7 +63,15 @@ def _pin_negative_padding(lib):
     return True
 
 
-PINS = (_pin_zero_one, _pin_signed_random, _pin_counts, _pin_negative_padding)
+def _pin_f32_total_order(lib):
+    from test_oracle_keytypes import TOTAL_ORDER
+    want = np.array(TOTAL_ORDER, dtype=np.uint32)
+    got = O.sort_keys(want[::-1].view(np.float32), O.KEY_F32, True, lib=lib).view(np.uint32)
+    return bool(np.array_equal(got, want))
+
+
+PINS = (_pin_zero_one, _pin_signed_random, _pin_counts, _pin_negative_padding,
+        _pin_f32_total_order)
 
 
 @pytest.fixture(scope="module")
