@@ -46,11 +46,6 @@ __device__ __forceinline__ uint32_t deposit(uint32_t t) {
   return out;
 }
 
-// LDS address swizzle: XOR bits 5..9 of the index into bits 0..4, so that
-// thread layouts whose lanes step through index bits 5..9 spread over the
-// banks.  A bijection on every aligned block of 1024 indices.
-__device__ __forceinline__ uint32_t swz(uint32_t i) { return i ^ ((i >> 5) & 31u); }
-
 // Program of a tile kernel, as a type.
 template <int L_, int R_LOG_, int KIND_>
 struct Prog {
@@ -59,6 +54,7 @@ struct Prog {
   static constexpr int R = 1 << R_LOG_;
   static constexpr int NT = 1 << (L_ - R_LOG_);
   static constexpr int T = 1 << L_;
+  static constexpr uint32_t LDSW = lds_words(L_);  // padded LDS words of a tile
   static constexpr bool VEC = KIND_ < 2;  // 16-byte vector global I/O allowed
   // Recompute each layout's thread base at its regroup (fewer registers,
   // more ALU); used by the segment kernels, which run several programs, and
@@ -88,29 +84,40 @@ __device__ __forceinline__ void group_steps(int32_t (&x)[PR::R]) {
   });
 }
 
+// LDS position of the thread part of a layout's slots: P(base), and for the
+// mirrored half of a virtual layout P(base ^ (mirror mask on thread bits)).
+template <class PR, int G>
+struct LdsBase {
+  uint32_t plain, mirrored;
+  __device__ __forceinline__ explicit LdsBase(uint32_t tid) {
+    constexpr Group gr = PR::value.g[G];
+    const uint32_t b = deposit<free_mask(gr, PR::L)>(tid);
+    plain = lds_pad(b);
+    if constexpr (gr.vmirror > 0)
+      mirrored = lds_pad(b ^ (mirror_mask(gr) & free_mask(gr, PR::L)));
+    else
+      mirrored = plain;
+  }
+  template <uint32_t J>
+  __device__ __forceinline__ uint32_t at() const {
+    constexpr Group gr = PR::value.g[G];
+    constexpr uint32_t o = lds_pad(real_off(gr, J));
+    return (slot_mirrored(gr, J) ? mirrored : plain) + o;
+  }
+};
+
 // Move the registers from the layout of group GA to that of group GB
-// through LDS.  Begins with a barrier so the LDS is free to overwrite.  The
-// swizzle is linear over XOR, so each address is the swizzled thread base
-// XOR a compile-time constant.  (The compiler computes the bases of all
-// layouts early and keeps them live; recomputing them per regroup would save
-// registers but costs more ALU time than it gains, measured.)
+// through LDS (each key to the padded position of its real index).  Begins
+// with a barrier so the LDS is free to overwrite.
 template <class PR, int GA, int GB>
 __device__ __forceinline__ void regroup(int32_t (&x)[PR::R], int32_t* lds, uint32_t tid) {
-  constexpr Group A = PR::value.g[GA];
-  constexpr Group B = PR::value.g[GB];
   if constexpr (PR::LEAN) asm volatile("" : "+v"(tid));
-  const uint32_t sa = swz(deposit<free_mask(A, PR::L)>(tid));
-  const uint32_t sb = swz(deposit<free_mask(B, PR::L)>(tid));
+  const LdsBase<PR, GA> a(tid);
+  const LdsBase<PR, GB> b(tid);
   __syncthreads();
-  static_for<0, PR::R>([&](auto J) {
-    constexpr uint32_t c = swz_const(goff(A, J));
-    lds[sa ^ c] = x[J];
-  });
+  static_for<0, PR::R>([&](auto J) { lds[a.template at<J>()] = x[J]; });
   __syncthreads();
-  static_for<0, PR::R>([&](auto J) {
-    constexpr uint32_t c = swz_const(goff(B, J));
-    x[J] = lds[sb ^ c];
-  });
+  static_for<0, PR::R>([&](auto J) { x[J] = lds[b.template at<J>()]; });
 }
 
 template <class PR, int G>
@@ -122,13 +129,13 @@ __device__ __forceinline__ void run_from(int32_t (&x)[PR::R], int32_t* lds, uint
   }
 }
 
-// Index of register slot J of a thread whose base index is `base`.
+// Index of register slot J of a thread whose base index is `base` (layouts
+// used for global I/O are never virtual).
 template <class PR, int G, uint32_t J>
 __device__ __forceinline__ uint32_t slot_index(uint32_t base) {
   constexpr Group gr = PR::value.g[G];
-  constexpr uint32_t o = goff(gr, J);
-  if constexpr (layout_is_unit(gr)) return base + o;  // disjoint bits
-  else return base ^ o;
+  static_assert(gr.vmirror == 0, "global I/O from a virtual layout");
+  return base + goff(gr, J);
 }
 
 // Load the thread's keys of a tile in the layout of group G.

@@ -27,7 +27,7 @@ template <int L, int RL, int KIND>
 __global__ __launch_bounds__(1 << (L - RL)) void tile_kernel(int32_t* __restrict__ keys,
                                                              uint32_t n, Codec cd) {
   using PR = Prog<L, RL, KIND>;
-  __shared__ int32_t lds[PR::T];
+  __shared__ int32_t lds[PR::LDSW];
   const uint32_t t0 = (uint32_t)blockIdx.x << L;
   const uint32_t left = n - t0;
   const uint32_t valid = left < (uint32_t)PR::T ? left : (uint32_t)PR::T;
@@ -45,7 +45,7 @@ template <int L, int RL, int KIND>
 __global__ __launch_bounds__(1 << (L - RL)) void tile_loop_kernel(int32_t* __restrict__ keys,
                                                                   uint32_t n, Codec cd) {
   using PR = Prog<L, RL, KIND>;
-  __shared__ int32_t lds[PR::T];
+  __shared__ int32_t lds[PR::LDSW];
   const uint32_t ntiles = (uint32_t)(((uint64_t)n + PR::T - 1) >> L);
   auto valid_of = [&](uint32_t tile) {
     const uint32_t left = n - (tile << L);

@@ -149,6 +149,8 @@ __global__ __launch_bounds__(1024) void seg_prep_kernel(const int64_t* __restric
 // ---------------------------------------------------------------------------
 // small segments
 
+constexpr uint32_t kSmallLdsWords = (kSegThreads << kTileRegLogSeg) / 32 * 33;
+
 // Not inlined: each class's program keeps its own register allocation
 // instead of the kernel carrying the union of all of them.
 template <int L>
@@ -158,6 +160,7 @@ __device__ __attribute__((noinline)) void seg_small_item(int32_t* __restrict__ k
                                                uint32_t count, Codec cd, int32_t* lds) {
   using PR = Prog<L, kTileRegLogSeg, 2>;
   constexpr uint32_t NT = PR::NT;
+  static_assert((kSegThreads / NT) * PR::LDSW <= kSmallLdsWords, "padded tiles exceed LDS");
   const uint32_t grp = threadIdx.x / NT;
   const uint32_t ltid = threadIdx.x % NT;
   int32_t* p = keys;
@@ -168,13 +171,14 @@ __device__ __attribute__((noinline)) void seg_small_item(int32_t* __restrict__ k
     p = keys + off;
     len = (uint32_t)(offsets[s + 1] - off);
   }
-  tile_program<PR>(p, len, cd, lds + grp * PR::T, ltid);
+  tile_program<PR>(p, len, cd, lds + grp * PR::LDSW, ltid);
 }
 
 __global__ __launch_bounds__(kSegThreads) void seg_small_kernel(
     int32_t* __restrict__ keys, const int64_t* __restrict__ offsets, SegMeta* __restrict__ meta,
     const uint32_t* __restrict__ small_ids, Codec cd) {
-  __shared__ int32_t lds[kSegThreads << kTileRegLogSeg];
+  // room for 256 / 2^(m-5) padded tiles of 2^m keys, for every class m
+  __shared__ int32_t lds[kSmallLdsWords];
   __shared__ uint32_t item_s;
   const uint32_t total = meta->small_items;
   for (;;) {
@@ -229,7 +233,7 @@ __global__ __launch_bounds__(kSegThreads) void seg_tile_kernel(
     const uint64_t* __restrict__ big_tiles, int cls_min, Codec cd) {
   using PR = Prog<kSegTileLog, kTileRegLogSeg, KIND>;
   static_assert(PR::NT == kSegThreads, "one tile per workgroup");
-  __shared__ int32_t lds[PR::T];
+  __shared__ int32_t lds[PR::LDSW];
   const uint32_t cnt = meta->big_ge[cls_min];
   const uint64_t total = big_tiles[cnt];
   for (uint64_t u = blockIdx.x; u < total; u += gridDim.x) {

@@ -1,20 +1,32 @@
 // Compile-time description of how a tile of 2^L keys moves through registers.
 //
 // A workgroup of 2^(L-r) threads holds a tile of 2^L keys, R = 2^r keys per
-// thread.  Which keys a thread holds is given by a "layout": r basis vectors
-// v[0..r) over GF(2) (tile indices read as bit vectors).  Thread t holds the
-// keys at indices  base(t) XOR off(j)  for register slots j in [0, R), where
-// off(j) is the XOR of the v[m] whose bit m is set in j and base(t) spreads
-// the bits of t over the index bits that are not the leading bit of any
-// v[m].  A basis vector is either a single index bit 2^b or the mirror
-// vector 2^p - 1, which pairs a key with its mirror image inside its 2^p
-// block (the first step of phase p in the flip arrangement of the network).
+// thread.  Which keys a thread holds is given by a "layout": r distinct index
+// bits b[0..r) (the basis vectors v[m] = 2^b[m]).  Thread t holds register
+// slots j in [0, R); slot j sits at tile index base(t) + off(j), where off(j)
+// is the sum of the v[m] whose bit m is set in j and base(t) spreads the bits
+// of t over the index bits that are not basis bits.  base and off share no
+// bit, so base + off == base | off.
 //
-// A compare-exchange step is a register mask D: slot j meets slot j XOR D,
-// and the key that sits at the lower tile index takes the minimum.  Which
-// slot that is only depends on j and the layout (the leading bit of
-// off(D) is zero in base(t)), so it is decided at compile time and the step
+// The first step of phase p compares each key with its mirror image inside
+// its 2^p block (index i XOR (2^p - 1)).  A layout that starts phase p is
+// "virtual": its keys are read so that the upper half of every 2^p block is
+// mirrored -- virtual index v holds the key of real index m(v), where
+// m(v) = v XOR (2^(p-1) - 1) if bit p-1 of v is set and m(v) = v otherwise
+// (m is its own inverse).  In virtual indices the mirror step pairs v with
+// v XOR 2^(p-1), a single bit, and the later steps of the phase keep their
+// strides but run in the opposite direction in the mirrored half.
+//
+// A compare-exchange step is a register mask D: slot j meets slot j XOR D, and
+// the key at the lower real index takes the minimum.  Which slot that is only
+// depends on j and the layout, so it is decided at compile time and the step
 // compiles to straight v_min_i32 / v_max_i32 pairs.
+//
+// LDS holds a tile at padded positions P(i) = i + floor(i / 32) (one unused
+// word after every 32), which spreads strided accesses over the banks.  P is
+// additive over bit-disjoint parts, so the LDS address of a slot is a
+// per-thread base P(base) plus a compile-time offset P(off(j)) that fits the
+// offset field of the LDS instruction: no address arithmetic per key.
 //
 // A program is a list of groups (layout + steps).  Keys are loaded from
 // global memory in the first group's layout, move between groups through
@@ -31,9 +43,10 @@ constexpr int kMaxGroups = 40;
 
 struct Group {
   int r = 0;
-  uint32_t v[kMaxRegBits] = {};
+  uint32_t v[kMaxRegBits] = {};  // single index bits
   int nsteps = 0;
   uint32_t d[kMaxSteps] = {};
+  int vmirror = 0;  // p > 0: virtual indices for phase p (see above)
 };
 
 struct Program {
@@ -52,30 +65,57 @@ constexpr int highbit(uint32_t x) {
   return h;
 }
 
-// Offset of register slot j inside the thread's key set.
+// Offset of register slot j inside the thread's key set (virtual index).
 constexpr uint32_t goff(const Group& G, uint32_t j) {
   uint32_t o = 0;
   for (int m = 0; m < G.r; ++m)
-    if ((j >> m) & 1u) o ^= G.v[m];
+    if ((j >> m) & 1u) o |= G.v[m];
   return o;
 }
 
-// Index bits that carry the thread id: all tile bits except leading bits.
-constexpr uint32_t free_mask(const Group& G, int L) {
-  uint32_t lead = 0;
-  for (int m = 0; m < G.r; ++m) lead |= 1u << highbit(G.v[m]);
-  return ((L >= 32) ? 0xFFFFFFFFu : ((1u << L) - 1u)) & ~lead;
+constexpr uint32_t reg_mask(const Group& G) {
+  uint32_t s = 0;
+  for (int m = 0; m < G.r; ++m) s |= G.v[m];
+  return s;
 }
 
-// True if slot j holds the lower tile index of the pair (j, j ^ D).
+// Index bits that carry the thread id: all tile bits except basis bits.
+constexpr uint32_t free_mask(const Group& G, int L) {
+  return ((L >= 32) ? 0xFFFFFFFFu : ((1u << L) - 1u)) & ~reg_mask(G);
+}
+
+// Mask applied to the lower bits in the mirrored half of a virtual layout.
+constexpr uint32_t mirror_mask(const Group& G) {
+  return G.vmirror > 0 ? ((1u << (G.vmirror - 1)) - 1u) : 0u;
+}
+
+// Is slot j in the mirrored half (bit p-1 of its virtual index set)?  For a
+// virtual layout bit p-1 is always a basis bit, so this is known per slot.
+constexpr bool slot_mirrored(const Group& G, uint32_t j) {
+  return G.vmirror > 0 && ((goff(G, j) >> (G.vmirror - 1)) & 1u);
+}
+
+// Register part of slot j's real index (the thread part is base, or
+// base ^ (mirror_mask & free_mask) for mirrored slots).
+constexpr uint32_t real_off(const Group& G, uint32_t j) {
+  return slot_mirrored(G, j) ? (goff(G, j) ^ (mirror_mask(G) & reg_mask(G))) : goff(G, j);
+}
+
+// True if slot j holds the lower real index of the pair (j, j ^ D).
 constexpr bool slot_is_lower(const Group& G, uint32_t j, uint32_t D) {
   const int h = highbit(goff(G, D));
-  return ((goff(G, j) >> h) & 1u) == 0;
+  return ((real_off(G, j) >> h) & 1u) == 0;
 }
 
-// Layout for global loads and stores: each thread holds 4 consecutive keys
-// (index bits 0, 1) of r - 2 rows (the top tile bits), so a wave moves 64
-// consecutive 16-byte pieces per instruction.
+// Padded LDS position of tile index i.
+constexpr uint32_t lds_pad(uint32_t i) { return i + (i >> 5); }
+
+// Words of LDS a padded tile of 2^L keys occupies.
+constexpr uint32_t lds_words(int L) { return lds_pad((1u << L) - 1u) + 1u; }
+
+// Layout for 16-byte global loads and stores: each thread holds 4
+// consecutive keys (index bits 0, 1) of r - 2 rows (the top tile bits), so a
+// wave moves 64 consecutive 16-byte pieces per instruction.
 constexpr Group io_group(int L, int r) {
   Group G{};
   G.r = r;
@@ -103,14 +143,15 @@ constexpr Group blocked_group(int r) {
 }
 
 // Bits top..0 of one merge, in groups of r bits from the top.  If `mirror`,
-// the first step is the phase's mirror step (bit top pairs mirror images).
+// the first step is the mirror step of phase top + 1: the first group is a
+// virtual layout whose first step pairs bit `top`.
 constexpr void add_merge_bits(Program& P, int top, bool mirror) {
   const int r = P.r;
   while (top >= r) {
     Group G{};
     G.r = r;
     for (int m = 0; m < r; ++m) G.v[m] = 1u << (top - m);
-    if (mirror) G.v[0] = (2u << top) - 1u;
+    if (mirror) G.vmirror = top + 1;
     for (int m = 0; m < r; ++m) G.d[G.nsteps++] = 1u << m;
     mirror = false;
     P.g[P.ngroups++] = G;
@@ -118,7 +159,7 @@ constexpr void add_merge_bits(Program& P, int top, bool mirror) {
   }
   if (top >= 0) {
     Group G = blocked_group(r);
-    if (mirror) {
+    if (mirror) {  // the whole 2^(top+1) block is in registers: mirror pairs
       G.d[G.nsteps++] = (2u << top) - 1u;
       --top;
     }
@@ -129,12 +170,13 @@ constexpr void add_merge_bits(Program& P, int top, bool mirror) {
 
 // Phases 1..L of the flip network on one tile: afterwards the tile is
 // ascending.  Phases 1..r run in the blocked layout (thread holds R
-// consecutive keys).
-constexpr Program make_tile_sort(int L, int r) {
+// consecutive keys, where the mirror step is a register-index mask).  A tile
+// of L == r bits is one thread's registers: one group and no LDS.
+constexpr Program make_tile_sort(int L, int r, bool vector_io) {
   Program P{};
   P.L = L;
   P.r = r;
-  P.g[P.ngroups++] = io_group(L, r);
+  if (L > r) P.g[P.ngroups++] = vector_io ? io_group(L, r) : io_scalar_group(L, r);
   Group g0 = blocked_group(r);
   const int pin = L < r ? L : r;
   for (int p = 1; p <= pin; ++p) {
@@ -143,84 +185,41 @@ constexpr Program make_tile_sort(int L, int r) {
   }
   P.g[P.ngroups++] = g0;
   for (int p = r + 1; p <= L; ++p) add_merge_bits(P, p - 1, true);
-  P.g[P.ngroups++] = io_group(L, r);
+  if (L > r) P.g[P.ngroups++] = vector_io ? io_group(L, r) : io_scalar_group(L, r);
   return P;
 }
 
 // The last L steps of a phase longer than the tile: strides 2^(L-1) .. 1,
-// smaller key to the lower index, on each tile.  The first layout also holds
-// index bits 0 and 1, so every thread loads 4 consecutive keys at a time.
-constexpr Program make_tile_merge(int L, int r) {
+// smaller key to the lower index, on each tile.  With vector I/O the first
+// layout also holds index bits 0 and 1, so every thread loads 4 consecutive
+// keys at a time; with scalar I/O the first merge layout (the top r bits in
+// registers) is already the I/O layout.
+constexpr Program make_tile_merge(int L, int r, bool vector_io) {
   Program P{};
   P.L = L;
   P.r = r;
-  Group G{};
-  G.r = r;
-  G.v[0] = 1u;
-  G.v[1] = 2u;
-  for (int m = 2; m < r; ++m) {
-    G.v[m] = 1u << (L - 1 - (m - 2));
-    G.d[G.nsteps++] = 1u << m;
+  if (vector_io) {
+    Group G = io_group(L, r);
+    for (int m = 2; m < r; ++m) G.d[G.nsteps++] = 1u << m;
+    P.g[P.ngroups++] = G;
+    add_merge_bits(P, L - 1 - (r - 2), false);
+    P.g[P.ngroups++] = io_group(L, r);
+  } else {
+    add_merge_bits(P, L - 1, false);
+    P.g[P.ngroups++] = io_scalar_group(L, r);
   }
-  P.g[P.ngroups++] = G;
-  add_merge_bits(P, L - 1 - (r - 2), false);
-  P.g[P.ngroups++] = io_group(L, r);
-  return P;
-}
-
-// Phases 1..L with scalar I/O.  A tile of L == r bits is one thread's
-// registers: a single blocked group and no LDS.
-constexpr Program make_tile_sort_scalar(int L, int r) {
-  Program P{};
-  P.L = L;
-  P.r = r;
-  if (L > r) P.g[P.ngroups++] = io_scalar_group(L, r);
-  Group g0 = blocked_group(r);
-  const int pin = L < r ? L : r;
-  for (int p = 1; p <= pin; ++p) {
-    g0.d[g0.nsteps++] = (1u << p) - 1u;
-    for (int b = p - 2; b >= 0; --b) g0.d[g0.nsteps++] = 1u << b;
-  }
-  P.g[P.ngroups++] = g0;
-  for (int p = r + 1; p <= L; ++p) add_merge_bits(P, p - 1, true);
-  if (L > r) P.g[P.ngroups++] = io_scalar_group(L, r);
-  return P;
-}
-
-// Strides 2^(L-1) .. 1 with scalar I/O: the first merge group's layout (the
-// top r bits in registers) is already the scalar I/O layout.
-constexpr Program make_tile_merge_scalar(int L, int r) {
-  Program P{};
-  P.L = L;
-  P.r = r;
-  add_merge_bits(P, L - 1, false);
-  P.g[P.ngroups++] = io_scalar_group(L, r);
   return P;
 }
 
 // Program kinds: 0 sort, 1 merge (16-byte vector I/O); 2 sort, 3 merge
 // (scalar I/O).
 constexpr Program make_program(int L, int r, int kind) {
-  return kind == 0   ? make_tile_sort(L, r)
-         : kind == 1 ? make_tile_merge(L, r)
-         : kind == 2 ? make_tile_sort_scalar(L, r)
-                     : make_tile_merge_scalar(L, r);
+  return (kind & 1) ? make_tile_merge(L, r, kind < 2) : make_tile_sort(L, r, kind < 2);
 }
 
 constexpr bool layout_is_vector4(const Group& G) {
-  return G.r >= 2 && G.v[0] == 1u && G.v[1] == 2u;
+  return G.r >= 2 && G.v[0] == 1u && G.v[1] == 2u && G.vmirror == 0;
 }
-
-// Every basis vector a single index bit: then base(t) and off(j) have no bit
-// in common and base ^ off == base + off.
-constexpr bool layout_is_unit(const Group& G) {
-  for (int m = 0; m < G.r; ++m)
-    if ((G.v[m] & (G.v[m] - 1u)) != 0) return false;
-  return true;
-}
-
-// The LDS swizzle of device.hpp, which is linear over XOR.
-constexpr uint32_t swz_const(uint32_t i) { return i ^ ((i >> 5) & 31u); }
 
 // Total compare-exchange steps a program performs (for checks).
 constexpr int program_steps(const Program& P) {

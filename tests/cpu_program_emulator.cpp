@@ -23,7 +23,20 @@ static uint32_t deposit_rt(uint32_t mask, uint32_t t) {
   return out;
 }
 
-static uint32_t swz(uint32_t i) { return i ^ ((i >> 5) & 31u); }
+// LDS position of slot j of thread t in layout G: the padded position of the
+// slot's real index (virtual layouts mirror the upper half of each block).
+static uint32_t lds_addr(const Group& G, int L, uint32_t t, uint32_t j) {
+  uint32_t base = deposit_rt(free_mask(G, L), t);
+  if (slot_mirrored(G, j)) base ^= mirror_mask(G) & free_mask(G, L);
+  return lds_pad(base) + lds_pad(real_off(G, j));
+}
+
+// Real tile index of slot j of thread t (checks the additive address form).
+static uint32_t real_index(const Group& G, int L, uint32_t t, uint32_t j) {
+  const uint32_t v = deposit_rt(free_mask(G, L), t) | goff(G, j);
+  if (G.vmirror > 0 && ((v >> (G.vmirror - 1)) & 1u)) return v ^ mirror_mask(G);
+  return v;
+}
 
 static Program make(int L, int r, int kind) {
   return make_program(L, r, kind);
@@ -50,28 +63,33 @@ int emulate_tile(int L, int r, int kind, int32_t* tile, uint32_t valid) {
     }
   }
   int steps = 0;
-  std::vector<int32_t> lds(T);
-  std::vector<int> hit(T);
+  std::vector<int32_t> lds(lds_words(L));
+  std::vector<int> hit(lds_words(L));
   for (int g = 0; g < P.ngroups; ++g) {
     const Group& G = P.g[g];
     if (g > 0) {
       const Group& A = P.g[g - 1];
       std::fill(hit.begin(), hit.end(), 0);
       for (uint32_t t = 0; t < NT; ++t) {
-        const uint32_t ba = deposit_rt(free_mask(A, L), t);
         for (uint32_t j = 0; j < R; ++j) {
-          const uint32_t a = swz(ba ^ goff(A, j));
-          if (a >= T) return -1;
+          const uint32_t a = lds_addr(A, L, t, j);
+          if (a >= lds_words(L) || a != lds_pad(real_index(A, L, t, j))) return -1;
           lds[a] = x[t * R + j];
           hit[a]++;
         }
       }
-      for (uint32_t a = 0; a < T; ++a)
-        if (hit[a] != 1) return -1;
-      for (uint32_t t = 0; t < NT; ++t) {
-        const uint32_t bb = deposit_rt(free_mask(G, L), t);
-        for (uint32_t j = 0; j < R; ++j) x[t * R + j] = lds[swz(bb ^ goff(G, j))];
+      uint32_t filled = 0;
+      for (uint32_t a = 0; a < lds_words(L); ++a) {
+        if (hit[a] > 1) return -1;
+        filled += hit[a];
       }
+      if (filled != T) return -1;
+      for (uint32_t t = 0; t < NT; ++t)
+        for (uint32_t j = 0; j < R; ++j) {
+          const uint32_t a = lds_addr(G, L, t, j);
+          if (a != lds_pad(real_index(G, L, t, j))) return -1;
+          x[t * R + j] = lds[a];
+        }
     }
     for (int s = 0; s < G.nsteps; ++s) {
       const uint32_t D = G.d[s];
@@ -114,7 +132,7 @@ int worst_bank_conflict(int L, int r, int kind, int banks) {
         for (uint32_t j = 0; j < R; ++j) {
           std::vector<int> cnt(banks, 0);
           for (uint32_t t = w0; t < w0 + 32 && t < NT; ++t) {
-            const uint32_t a = swz(deposit_rt(free_mask(G, L), t) ^ goff(G, j));
+            const uint32_t a = lds_addr(G, L, t, j);
             worst = std::max(worst, ++cnt[a % banks]);
           }
         }
