@@ -49,6 +49,8 @@ def parse():
     ap.add_argument("--fuse", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the n = 10^7 run (profiles of the n-key sort alone)")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--out", default="")
     ap.add_argument("--ablation", action="store_true",
@@ -140,8 +142,17 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-KERNEL_CLASS = {f"tile_kernel<{t}, 5, {k}>": ("tile_merge" if k else "tile_sort")
-                for t in (11, 12, 13, 14) for k in (0, 1)}
+def kernel_class(name: str):
+    """Kernel class of a (demangled, shortened) kernel name: tile_sort,
+    tile_merge, global_pass_f<F> for the unbounded pass kernels, else None."""
+    for pre in ("tile_kernel<", "tile_loop_kernel<"):
+        if name.startswith(pre):
+            args = name[len(pre):name.index(">")].split(", ")
+            return "tile_merge" if args[2] == "1" else "tile_sort"
+    if name.startswith("global_pass_kernel<"):
+        f_, _, bounded = name[len("global_pass_kernel<"):name.index(">")].split(", ")
+        return f"global_pass_f{f_}" if bounded == "false" else None
+    return None
 
 
 def committed_traffic(kernel: str, n: int):
@@ -164,11 +175,7 @@ def committed_traffic(kernel: str, n: int):
     vals = []
     for r in rows:
         name = r[0]
-        cls = KERNEL_CLASS.get(name)
-        if cls is None and name.startswith("global_pass_kernel<"):
-            f_, _, bounded = name[len("global_pass_kernel<"):-1].split(", ")
-            cls = f"global_pass_f{f_}" if bounded == "false" else None
-        if cls == kernel:
+        if kernel_class(name) == kernel:
             vals.append(float(r[3]))
     return round(sum(vals) / len(vals)) if vals else None
 
@@ -357,13 +364,14 @@ def main():
                                    "this_over_paper": round(gkeys * 1e3 / PAPER_K10_MKEYS_2_24,
                                                             1)}}
     del src
-    n2 = 10_000_000
-    src2 = torch.from_numpy(W.uniform_i32(W.SEED_BASE + 3, n2)).cuda()
-    ms2, _, ok2 = time_sorts(torch, B, src2, max(5, args.steps // 2), 2, plan)
-    extra["n10M"] = {"n": n2, "ms": round(ms2, 3), "gkeys_s": round(n2 / (ms2 * 1e-3) / 1e9, 3),
-                     "sorted_check": ok2}
-    log(f"[bench] n=10M: {ms2:.3f} ms, {extra['n10M']['gkeys_s']} Gkeys/s")
-    del src2
+    if not args.no_extra:
+        n2 = 10_000_000
+        src2 = torch.from_numpy(W.uniform_i32(W.SEED_BASE + 3, n2)).cuda()
+        ms2, _, ok2 = time_sorts(torch, B, src2, max(5, args.steps // 2), 2, plan)
+        extra["n10M"] = {"n": n2, "ms": round(ms2, 3),
+                         "gkeys_s": round(n2 / (ms2 * 1e-3) / 1e9, 3), "sorted_check": ok2}
+        log(f"[bench] n=10M: {ms2:.3f} ms, {extra['n10M']['gkeys_s']} Gkeys/s")
+        del src2
     if not args.no_batched:
         extra["batched"] = batched_vs_looped(torch, B, W)
         log(f"[bench] batched: {json.dumps(extra['batched'])}")

@@ -157,7 +157,7 @@ enum bitonic_plan_kind {
 
 typedef struct bitonic_plan {
   int kind;                /* enum bitonic_plan_kind */
-  int tile_log2;           /* keys per on-chip tile = 2^tile_log2, 11..14 for
+  int tile_log2;           /* keys per on-chip tile = 2^tile_log2, 11..15 for
                               the optimized plan, 1..13 for semi (0 = library
                               choice) */
   int fuse;                /* max long-stride steps per HBM pass, 1..5
@@ -165,7 +165,7 @@ typedef struct bitonic_plan {
   int merge_blocks_per_cu; /* tile-merge workgroups per compute unit, 1..16,
                               each looping over its tiles with the next
                               tile's loads in flight; -1 = one tile per
-                              workgroup (0 = library choice) */
+                              workgroup (0 = library choice, 2) */
 } bitonic_plan;
 
 /*
@@ -227,7 +227,10 @@ int bitonic_sort_plan_events_i32(int32_t* keys, int64_t n, int ascending,
 /*
  * Enqueue only launches [first, first + count) of the plan for n keys (the
  * order of bitonic_plan_describe).  Running a subset leaves the keys in an
- * intermediate state; it exists to time single kernels on the device.
+ * intermediate state; it exists to time single kernels on the device.  In
+ * the optimized plan the first kernel maps the keys into the sorting domain
+ * and the last maps them back (the identity for ascending int32), so an
+ * intermediate state holds mapped keys.
  */
 int bitonic_sort_plan_launches_i32(int32_t* keys, int64_t n, int ascending,
                                    const bitonic_plan* plan, int64_t first,

@@ -25,7 +25,7 @@ namespace bitonic {
 
 static std::atomic<int> g_tile_log2{14};
 static std::atomic<int> g_fuse{5};
-static std::atomic<int> g_merge_bpc{0};  // 0: one tile per workgroup
+static std::atomic<int> g_merge_bpc{2};  // 0: one tile per workgroup
 static std::atomic<int> g_seg_bpc{4};    // small-segment workgroups per compute unit
 
 struct Resolved {
@@ -129,11 +129,13 @@ static int64_t enqueue_plain(int32_t* keys, uint32_t n, int K, Codec flip, const
       emit(BITONIC_LAUNCH_LDS_NETWORK, 0,
            [&] { launch_lds_network(K, 1, K, false, keys, n, flip, st); });
     else
-      emit(BITONIC_LAUNCH_TILE_SORT, 0, [&] { launch_tile(K, 0, keys, n, flip, 0, st); });
+      emit(BITONIC_LAUNCH_TILE_SORT, 0, [&] { launch_tile(K, 0, keys, n, flip, CX_BOTH, 0, st); });
     return launches;
   }
+  // The tile sort encodes the keys and the last merge decodes them; the
+  // passes and merges in between work on encoded keys.
   const int L = r.tile;
-  emit(BITONIC_LAUNCH_TILE_SORT, 0, [&] { launch_tile(L, 0, keys, n, flip, 0, st); });
+  emit(BITONIC_LAUNCH_TILE_SORT, 0, [&] { launch_tile(L, 0, keys, n, flip, CX_ENC, 0, st); });
   for (int p = L + 1; p <= K; ++p) {
     const int nb = p - L;                          // long-stride steps
     const int npass = (nb + r.fuse - 1) / r.fuse;  // fused HBM passes
@@ -144,10 +146,12 @@ static int64_t enqueue_plain(int32_t* keys, uint32_t n, int K, Codec flip, const
       const int f = (left + passes_left - 1) / passes_left;
       const int q = top - f + 1;
       emit(BITONIC_LAUNCH_GLOBAL_PASS, f,
-           [&] { launch_global_pass(f, i == 0, keys, n, q, flip, st); });
+           [&] { launch_global_pass(f, i == 0, keys, n, q, st); });
       top = q - 1;
     }
-    emit(BITONIC_LAUNCH_TILE_MERGE, 0, [&] { launch_tile(L, 1, keys, n, flip, r.merge_blocks, st); });
+    const int cx = p == K ? CX_DEC : CX_NONE;
+    emit(BITONIC_LAUNCH_TILE_MERGE, 0,
+         [&] { launch_tile(L, 1, keys, n, flip, cx, r.merge_blocks, st); });
   }
   return launches;
 }

@@ -29,6 +29,28 @@ struct Codec {
   }
 };
 
+inline bool codec_is_identity(Codec c) { return c.flip == 0 && c.fmask == 0; }
+
+// Which global accesses of a kernel apply the codec.  A sort made of several
+// kernels encodes at its first kernel's loads and decodes at its last
+// kernel's stores; the kernels in between move keys of the sorting domain
+// unchanged, with no codec arithmetic.  CX_BOTH is a kernel that is the whole
+// sort; an identity codec always takes CX_NONE.
+enum : int { CX_NONE = 0, CX_ENC = 1, CX_DEC = 2, CX_BOTH = 3 };
+
+template <int CX>
+struct KeyIO {
+  Codec c;
+  __device__ __forceinline__ int32_t enc(int32_t x) const {
+    if constexpr ((CX & CX_ENC) != 0) return c.enc(x);
+    return x;
+  }
+  __device__ __forceinline__ int32_t dec(int32_t y) const {
+    if constexpr ((CX & CX_DEC) != 0) return c.dec(y);
+    return y;
+  }
+};
+
 // Key types of the C interface (enum bitonic_key_type in bitonic.h).
 inline Codec make_codec(int key_type, bool ascending) {
   switch (key_type) {

@@ -140,9 +140,9 @@ __device__ __forceinline__ uint32_t slot_index(uint32_t base) {
 
 // Load the thread's keys of a tile in the layout of group G.
 // `valid` keys of the tile exist; the rest read as the sentinel.
-template <class PR, int G>
+template <class PR, int G, class CD>
 __device__ __forceinline__ void load_tile(int32_t (&x)[PR::R], const int32_t* __restrict__ tile,
-                                          uint32_t valid, Codec cd, uint32_t tid) {
+                                          uint32_t valid, CD cd, uint32_t tid) {
   constexpr Group gr = PR::value.g[G];
   const uint32_t base = deposit<free_mask(gr, PR::L)>(tid);
   if (valid >= (uint32_t)PR::T) {
@@ -167,9 +167,34 @@ __device__ __forceinline__ void load_tile(int32_t (&x)[PR::R], const int32_t* __
   }
 }
 
-template <class PR, int G>
+// Buffer resource over the 2^L keys of a tile starting at `tile`, or an empty
+// one (`full` false).  Buffer loads outside the range return zeros and read no
+// memory, so a load of "no tile" issues the same instructions as a real one.
+// The last word is the gfx9-family resource format for raw 32-bit data.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t tile_rsrc(const int32_t* tile, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<int32_t*>(tile), 0, (int)bytes, 0x00020000);
+}
+
+// A full tile in the 16-byte layout of group G through a buffer resource.
+template <class PR, int G, class CD>
+__device__ __forceinline__ void load_tile_rsrc(int32_t (&x)[PR::R], __amdgpu_buffer_rsrc_t rs,
+                                               CD cd, uint32_t tid) {
+  constexpr Group gr = PR::value.g[G];
+  static_assert(PR::VEC && layout_is_vector4(gr), "buffer tile loads need the 16-byte layout");
+  const uint32_t base = deposit<free_mask(gr, PR::L)>(tid);
+  static_for<0, PR::R / 4>([&](auto Q) {
+    constexpr uint32_t o = goff(gr, 4u * Q);
+    const uint32_t i = slot_index<PR, G, 4u * Q>(base);
+    const int4 v = __builtin_bit_cast(
+        int4, __builtin_amdgcn_raw_buffer_load_b128(rs, (i & ~3u) * 4u, 0, 0));
+    const int32_t e[4] = {v.x, v.y, v.z, v.w};
+    static_for<0, 4>([&](auto C) { x[4 * Q + C] = cd.enc(e[(o ^ C) & 3u]); });
+  });
+}
+
+template <class PR, int G, class CD>
 __device__ __forceinline__ void store_tile(const int32_t (&x)[PR::R], int32_t* __restrict__ tile,
-                                           uint32_t valid, Codec cd, uint32_t tid) {
+                                           uint32_t valid, CD cd, uint32_t tid) {
   constexpr Group gr = PR::value.g[G];
   const uint32_t base = deposit<free_mask(gr, PR::L)>(tid);
   if (valid >= (uint32_t)PR::T) {
@@ -225,10 +250,11 @@ __device__ __forceinline__ void pass_steps(int32_t (&x)[4 << F]) {
 }
 
 // Sort (KIND 0) or merge (KIND 1) one tile that starts at `tile` and holds
-// `valid` real keys.  All threads of the block must call it.
-template <class PR>
+// `valid` real keys.  All threads of the block must call it.  `cd` is a Codec
+// or a KeyIO.
+template <class PR, class CD>
 __device__ __forceinline__ void tile_program(int32_t* __restrict__ tile, uint32_t valid,
-                                             Codec cd, int32_t* lds, uint32_t tid) {
+                                             CD cd, int32_t* lds, uint32_t tid) {
   int32_t x[PR::R];
   load_tile<PR, 0>(x, tile, valid, cd, tid);
   run_from<PR, 0>(x, lds, tid);

@@ -10,7 +10,7 @@ namespace bitonic {
 
 constexpr int kTileRegLogPlain = 5;  // 32 keys per thread in the tile kernels
 constexpr int kTileMinLog2 = 11;
-constexpr int kTileMaxLog2 = 14;
+constexpr int kTileMaxLog2 = 15;
 constexpr int kFuseMax = 5;
 constexpr int kLdsNetworkMaxLog2 = 13;
 
@@ -19,13 +19,15 @@ bool tile_log2_supported(int L);
 // Tile sort (kind 0: phases 1..L) or tile merge (kind 1: strides
 // 2^(L-1)..1) over every 2^L tile of keys[0, n).  The merge runs at most
 // max_blocks workgroups (0 = one per tile), each looping over its tiles.
-void launch_tile(int L, int kind, int32_t* keys, uint32_t n, Codec cd, uint32_t max_blocks,
-                 hipStream_t st);
+// cx (CX_*): whether loads encode and stores decode; a tile sort takes
+// CX_ENC or CX_BOTH, a merge CX_NONE or CX_DEC.
+void launch_tile(int L, int kind, int32_t* keys, uint32_t n, Codec cd, int cx,
+                 uint32_t max_blocks, hipStream_t st);
 
 // f fused steps on bits q+f-1 .. q (the first one the mirror step if
-// `mirror`).  Requires q >= 8, q + f <= 31, 1 <= f <= kFuseMax.
-void launch_global_pass(int f, bool mirror, int32_t* keys, uint32_t n, int q, Codec cd,
-                        hipStream_t st);
+// `mirror`) on keys already in the sorting domain.  Requires q >= 8,
+// q + f <= 31, 1 <= f <= kFuseMax.
+void launch_global_pass(int f, bool mirror, int32_t* keys, uint32_t n, int q, hipStream_t st);
 
 // LDS network on 2^L tiles (L <= kLdsNetworkMaxLog2).
 void launch_lds_network(int L, int p_first, int p_last, bool tail, int32_t* keys, uint32_t n,

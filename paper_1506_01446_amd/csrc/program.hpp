@@ -190,10 +190,11 @@ constexpr Program make_tile_sort(int L, int r, bool vector_io) {
 }
 
 // The last L steps of a phase longer than the tile: strides 2^(L-1) .. 1,
-// smaller key to the lower index, on each tile.  With vector I/O the first
-// layout also holds index bits 0 and 1, so every thread loads 4 consecutive
-// keys at a time; with scalar I/O the first merge layout (the top r bits in
-// registers) is already the I/O layout.
+// smaller key to the lower index, on each tile.  With vector I/O the load and
+// store layouts hold index bits 0 and 1, so every thread moves 4 consecutive
+// keys at a time, and the store layout performs the last two steps; with
+// scalar I/O the first merge layout (the top r bits in registers) is already
+// the I/O layout.
 constexpr Program make_tile_merge(int L, int r, bool vector_io) {
   Program P{};
   P.L = L;
@@ -202,8 +203,23 @@ constexpr Program make_tile_merge(int L, int r, bool vector_io) {
     Group G = io_group(L, r);
     for (int m = 2; m < r; ++m) G.d[G.nsteps++] = 1u << m;
     P.g[P.ngroups++] = G;
-    add_merge_bits(P, L - 1 - (r - 2), false);
-    P.g[P.ngroups++] = io_group(L, r);
+    // bits L-r+1 .. 2 in windows of r consecutive bits (the last window may
+    // step fewer than r of them); bits 1 and 0 are register bits of the
+    // store layout, which performs those two steps itself.
+    int top = L - 1 - (r - 2);
+    while (top >= 2) {
+      const int hi = top > r - 1 ? top : r - 1;  // window hi .. hi-r+1
+      Group M{};
+      M.r = r;
+      for (int m = 0; m < r; ++m) M.v[m] = 1u << (hi - m);
+      for (int b = top; b >= 2 && b > hi - r; --b) M.d[M.nsteps++] = 1u << (hi - b);
+      P.g[P.ngroups++] = M;
+      top = hi - r;
+    }
+    Group S = io_group(L, r);
+    S.d[S.nsteps++] = 2u;
+    S.d[S.nsteps++] = 1u;
+    P.g[P.ngroups++] = S;
   } else {
     add_merge_bits(P, L - 1, false);
     P.g[P.ngroups++] = io_scalar_group(L, r);

@@ -42,12 +42,30 @@ static Program make(int L, int r, int kind) {
   return make_program(L, r, kind);
 }
 
+// Every layout's basis: r distinct single index bits below L; every step a
+// nonzero register mask.
+static bool layouts_valid(const Program& P, int L) {
+  for (int g = 0; g < P.ngroups; ++g) {
+    const Group& G = P.g[g];
+    uint32_t seen = 0;
+    for (int m = 0; m < G.r; ++m) {
+      const uint32_t v = G.v[m];
+      if (v == 0 || (v & (v - 1)) || v >= (1u << L) || (seen & v)) return false;
+      seen |= v;
+    }
+    for (int s = 0; s < G.nsteps; ++s)
+      if (G.d[s] == 0 || G.d[s] >= (1u << G.r)) return false;
+  }
+  return true;
+}
+
 extern "C" {
 
 // Returns the number of compare-exchange steps performed, or -1 on error
 // (e.g. an LDS regrouping that is not a permutation).
 int emulate_tile(int L, int r, int kind, int32_t* tile, uint32_t valid) {
   const Program P = make(L, r, kind);
+  if (!layouts_valid(P, L)) return -1;
   const uint32_t T = 1u << L, NT = 1u << (L - r), R = 1u << r;
   const int32_t PAD = 0x7FFFFFFF;
   std::vector<int32_t> x(size_t(NT) * R);
@@ -123,6 +141,7 @@ int emulate_tile(int L, int r, int kind, int32_t* tile, uint32_t valid) {
 // bank (of `banks`) in any 32-bit access of any regrouping of the program.
 int worst_bank_conflict(int L, int r, int kind, int banks) {
   const Program P = make(L, r, kind);
+  if (!layouts_valid(P, L)) return -1;
   const uint32_t NT = 1u << (L - r), R = 1u << r;
   int worst = 0;
   for (int g = 1; g < P.ngroups; ++g) {

@@ -63,7 +63,7 @@ def _closed_form_optimized(k, t, f):
     return 1 + sum(-(-(p - t) // f) + 1 for p in range(t + 1, k + 1))
 
 
-@pytest.mark.parametrize("t", [11, 12, 13, 14])
+@pytest.mark.parametrize("t", [11, 12, 13, 14, 15])
 @pytest.mark.parametrize("f", [1, 2, 3, 4, 5])
 def test_optimized_pass_count(lib, t, f):
     for k in range(1, 32):

@@ -19,8 +19,8 @@ SIZES = [0, 1, 2, 3, 4, 5, 7, 8, 9, 15, 16, 17, 31, 33, 63, 64, 65, 127, 129, 25
          257, 1000, 1023, 1024, 1025, 2047, 2048, 2049, 4095, 4096, 4097, 8191, 8192, 8193,
          16383, 16385, 32768, 65535, 65536, 65537, 100003, 131075, 262144, 300001]
 PLANS = [("basic",), ("semi", 8), ("semi", 12)] + \
-        [("optimized", t, f) for t in (11, 12, 13, 14) for f in (1, 2, 3, 4, 5)] + \
-        [("optimized", 13, 5, 4), ("optimized", 14, 5, 2)]
+        [("optimized", t, f) for t in (11, 12, 13, 14, 15) for f in (1, 2, 3, 4, 5)] + \
+        [("optimized", 13, 5, 4), ("optimized", 14, 5, 2), ("optimized", 15, 5, 1)]
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -80,8 +80,45 @@ def test_signed_extremes():
             assert np.array_equal(gpu_sort(keys, asc, plan), O.sort_i32(keys, asc))
 
 
+@pytest.mark.parametrize("plan", [("optimized", 11, 2, 1), ("optimized", 12, 5, 2),
+                                  ("optimized", 14, 5, 1), ("optimized", 15, 5, 1)],
+                         ids=lambda p: "-".join(map(str, p)))
+def test_merge_loop_kernel(plan):
+    """Merges on fewer workgroups than tiles: each block loops over several
+    full tiles with its next tile prefetched (an empty prefetch on its last
+    iteration) and one block also merges the partial last tile."""
+    L, grid = plan[1], torch.cuda.get_device_properties(0).multi_processor_count * plan[3]
+    cases = ((grid + 1, 0), (2 * grid, 777), (3 * grid - 5, 1)) if L < 14 else ((grid + 3, 4097),)
+    for tiles, tail in cases:
+        n = (tiles << L) + tail
+        keys = W.uniform_i32(W.SEED_BASE + 31 + n, n)
+        for asc in (True, False):
+            print(f"[case] plan={plan} n={n} asc={asc}", flush=True)
+            assert np.array_equal(gpu_sort(keys, asc, plan), O.sort_i32(keys, asc)), (plan, n, asc)
+
+
+def test_merge_loop_kernel_float_keys():
+    """The last merge decodes float32 keys in the looping kernel."""
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    n = ((2 * cus) << 14) + 999
+    bits = W.uniform_i32(W.SEED_BASE + 32, n).view(np.uint32).copy()
+    bits[: len(TOTAL_ORDER_BITS)] = TOTAL_ORDER_BITS
+    old = B.bitonic_get_tuning_value("merge_blocks_per_cu")
+    B.bitonic_set_tuning_value("merge_blocks_per_cu", 1)
+    try:
+        for asc in (True, False):
+            t = torch.from_numpy(bits.view(np.int32).copy()).cuda()
+            B.bitonic_sort_keys(t, asc, "float32")
+            torch.cuda.synchronize()
+            want = O.sort_keys(bits.view(np.float32), O.KEY_F32, asc).view(np.int32)
+            assert np.array_equal(t.cpu().numpy(), want), asc
+    finally:
+        B.bitonic_set_tuning_value("merge_blocks_per_cu", old)
+
+
 @pytest.mark.parametrize("plan", [("optimized", 11, 2), ("optimized", 13, 4),
-                                  ("optimized", 14, 5), ("semi", 9), ("basic",)],
+                                  ("optimized", 14, 5), ("optimized", 15, 3), ("semi", 9),
+                                  ("basic",)],
                          ids=lambda p: "-".join(map(str, p)))
 def test_per_phase_states(plan):
     """After phase p the GPU state equals the oracle network's state after

@@ -41,7 +41,7 @@ def _run(emu, L, r, kind, tile, valid):
     return x, steps
 
 
-@pytest.mark.parametrize("L", [11, 12, 13, 14])
+@pytest.mark.parametrize("L", [11, 12, 13, 14, 15])
 def test_tile_sort_program(emu, L):
     T = 1 << L
     for seed in range(3):
@@ -65,7 +65,7 @@ def test_tile_sort_partial(emu, L):
         assert (out[valid:] == keys[valid:]).all()
 
 
-@pytest.mark.parametrize("L", [11, 12, 13, 14])
+@pytest.mark.parametrize("L", [11, 12, 13, 14, 15])
 def test_tile_merge_program(emu, L):
     """The merge tail sorts any tile whose halves at every level were left
     in the state a long-stride pass leaves: here, a bitonic tile (ascending
@@ -80,7 +80,7 @@ def test_tile_merge_program(emu, L):
         assert (out == np.sort(keys)).all()
 
 
-@pytest.mark.parametrize("L", [11, 12, 13, 14])
+@pytest.mark.parametrize("L", [11, 12, 13, 14, 15])
 @pytest.mark.parametrize("kind", [0, 1])
 def test_lds_bank_conflicts(emu, L, kind):
     # no half-wave access of any regrouping puts two lanes on one bank
