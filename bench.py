@@ -180,6 +180,63 @@ def committed_traffic(kernel: str, n: int):
     return round(sum(vals) / len(vals)) if vals else None
 
 
+def rep_protocol(torch, B, W, plan, sizes=(1 << 24, 1 << 26), reps=30, warmup=5):
+    """Per-repetition timing: before each rep the keys are restored by a
+    device-to-device copy (untimed), then one sort is timed with HIP events.
+    Warm reps run back to back; cold reps first write a 1 GiB buffer
+    (untimed) so that neither the L2 caches nor the 256 MB Infinity Cache
+    hold the keys.  Reports median and p90 in ms and the median's Gkeys/s;
+    at n = 2^26 the 256 MiB array does not fit the Infinity Cache, so that
+    is the HBM-bound figure."""
+    ev = B.HipEvents(2)
+    rt = ev.rt
+    rt.hipEventRecord.argtypes = [B.ctypes.c_void_p, B.ctypes.c_void_p]
+    stream = torch.cuda.current_stream().cuda_stream
+    flush = torch.empty(1 << 28, dtype=torch.int32, device="cuda")
+    out = {}
+    for n in sizes:
+        src = torch.from_numpy(W.uniform_i32(W.SEED_BASE + 2, n)).cuda()
+        buf = torch.empty_like(src)
+        res = {}
+        for mode in ("warm", "cold"):
+            times = []
+            for r in range(warmup + reps):
+                buf.copy_(src)
+                if mode == "cold":
+                    flush.fill_(r)
+                rt.hipEventRecord(ev.ev[0], stream)
+                B.bitonic_sort_plan_i32(buf, True, plan)
+                rt.hipEventRecord(ev.ev[1], stream)
+                torch.cuda.synchronize()
+                if r >= warmup:
+                    times.append(ev.elapsed_ms(0, 1))
+            times.sort()
+            med = times[len(times) // 2]
+            p90 = times[min(len(times) - 1, int(0.9 * len(times)))]
+            res[mode] = {"median_ms": round(med, 4), "p90_ms": round(p90, 4),
+                         "gkeys_s_at_median": round(n / (med * 1e-3) / 1e9, 3)}
+        ok = bool((buf[1:] >= buf[:-1]).all().item())
+        out[f"n{n}"] = dict(res, reps=reps, warmup=warmup, sorted_check=ok)
+        del src, buf
+    del flush
+    ev.close()
+    return out
+
+
+def cpu_network_context(n=1 << 20):
+    """The oracle's scalar flip network (one thread) at a bounded size: the
+    analogue of the paper's CPU bitonic-sort column, as context only."""
+    from oracle import oracle as O
+    from paper_1506_01446_amd import workloads as W
+    keys = W.uniform_i32(W.SEED_BASE + 2, n)
+    t0 = time.perf_counter()
+    O.bitonic_i32(keys, True, O.FLIP_VIRTUAL)
+    dt = time.perf_counter() - t0
+    return {"value": round(n / dt / 1e9, 5), "unit": "Gkeys/s", "cores": 1,
+            "kind": "oracle scalar network", "sample": f"one sort of n={n} uniform int32, "
+                                                        f"{dt:.2f} s"}
+
+
 def cpu_baseline(n):
     """The CPU oracle as it stands (std::sort, one thread) on a bounded
     sample of the same workload."""
@@ -379,7 +436,12 @@ def main():
         from paper_1506_01446_amd import serving
         extra["serving"] = serving.run_gpu(duration_s=args.serve_seconds)
         log(f"[bench] serving: {json.dumps(extra['serving'])}")
+    if not args.no_extra:
+        extra["protocol"] = rep_protocol(torch, B, W, plan)
+        log(f"[bench] protocol: {json.dumps(extra['protocol'])}")
     cpu = None if args.no_cpu else cpu_baseline(n)
+    if cpu is not None:
+        extra["cpu_network"] = cpu_network_context()
 
     line = {"metric": "Gkeys/s int32 at n=2^24 (%HBM peak); batched vs looped Gkeys/s; p99 ms",
             "value": round(gkeys, 3), "unit": "Gkeys/s", "n_gpus": 1, "steps": args.steps,

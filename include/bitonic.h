@@ -71,19 +71,24 @@ const char* bitonic_status_string(int status);
 int bitonic_sort_i32(int32_t* keys, int64_t n, int ascending, void* stream);
 
 /*
- * Key types.  All are 32-bit and sorted with the same network; a key type
- * only changes the order-preserving map applied as keys are loaded and
- * stored (the paper's future work, section 6, names other key types):
+ * Key types.  Every type is sorted with the same network; a key type only
+ * changes the order-preserving map applied as keys are loaded and stored
+ * (the paper's future work, section 6, names other key types):
  *   BITONIC_KEY_I32  signed two's-complement integers
  *   BITONIC_KEY_U32  unsigned integers
  *   BITONIC_KEY_F32  IEEE-754 binary32, in the totalOrder of IEEE 754-2008
  *                    (-NaN < -inf < ... < -0 < +0 < ... < +inf < +NaN; NaNs
  *                    ordered by their payload bits)
+ *   BITONIC_KEY_I64, BITONIC_KEY_U64, BITONIC_KEY_F64  the same on 8 bytes
+ *                    (binary64 for F64)
  */
 enum bitonic_key_type {
   BITONIC_KEY_I32 = 0,
   BITONIC_KEY_U32 = 1,
-  BITONIC_KEY_F32 = 2
+  BITONIC_KEY_F32 = 2,
+  BITONIC_KEY_I64 = 3,
+  BITONIC_KEY_U64 = 4,
+  BITONIC_KEY_F64 = 5
 };
 
 /*
@@ -92,6 +97,34 @@ enum bitonic_key_type {
  * bitonic_sort_i32.
  */
 int bitonic_sort_keys(void* keys, int64_t n, int key_type, int ascending, void* stream);
+
+/*
+ * Sort n 8-byte keys in place: the network of sections 3.1-3.3 with the
+ * tile sort and fused passes of sections 4.1-4.2 on 8-byte elements.
+ *   keys       device pointer to n keys of key_type (BITONIC_KEY_I64, U64
+ *              or F64), 8-byte aligned (may be NULL when n <= 1)
+ *   n, ascending, stream  as for bitonic_sort_i32
+ * Returns BITONIC_EINVAL for another key_type, a misaligned pointer, keys
+ * NULL with n > 1 or n < 0; else as bitonic_sort_i32.
+ */
+int bitonic_sort_keys64(void* keys, int64_t n, int key_type, int ascending, void* stream);
+
+/*
+ * Sort (key, value) pairs in place by key, ties by value: a key-value
+ * variant of the same network, each pair moving through it as one 8-byte
+ * element (key word, then value word).  The result is the unique order of
+ * the pairs by key in the requested direction (key_type BITONIC_KEY_I32,
+ * U32 or F32, as for bitonic_sort_keys) and, among equal keys, by value
+ * ascending as int32.  With values 0 .. n-1 on input, the values come out as
+ * the permutation of a stable sort (an argsort).
+ *   keys       device pointer to n 4-byte keys, 4-byte aligned
+ *   values     device pointer to n int32 values, 4-byte aligned (both may
+ *              be NULL when n <= 1; the arrays must not overlap)
+ *   n, ascending, stream  as for bitonic_sort_i32
+ * Returns as bitonic_sort_keys64.
+ */
+int bitonic_sort_pairs(void* keys, int32_t* values, int64_t n, int key_type, int ascending,
+                       void* stream);
 
 /*
  * Sort every segment of a CSR table independently, in one batched launch
@@ -169,6 +202,21 @@ typedef struct bitonic_plan {
 } bitonic_plan;
 
 /*
+ * The 8-byte sorts with an explicit plan: an 8-byte key_type (I64, U64,
+ * F64) sorts keys (bitonic_sort_keys64; values must be NULL), a 4-byte one
+ * sorts pairs (bitonic_sort_pairs).  The plan's kind
+ * must be BITONIC_PLAN_AUTO or BITONIC_PLAN_OPTIMIZED, its tile_log2 11..13
+ * (elements per tile), its fuse 1..5; merge_blocks_per_cu is ignored (one
+ * tile per workgroup).  Library choices (0): tile_log2 13, fuse 4 (tuning
+ * values "wide_tile_log2" and "wide_fuse").
+ */
+int bitonic_sort_wide_plan(void* keys, int32_t* values, int64_t n, int key_type, int ascending,
+                           const bitonic_plan* plan, void* stream);
+
+/* Launches of an 8-byte sort of n elements under `plan` (-1: bad plan or n). */
+int64_t bitonic_wide_plan_passes(int64_t n, const bitonic_plan* plan);
+
+/*
  * bitonic_sort_i32 with an explicit plan (used for the section 5 ablation
  * and by the autotuner).  plan == NULL means BITONIC_PLAN_AUTO.
  * Returns BITONIC_EINVAL for a plan the library does not implement.
@@ -241,8 +289,10 @@ int bitonic_sort_plan_launches_i32(int32_t* keys, int64_t n, int ascending,
  * the library's default plan for BITONIC_PLAN_AUTO (values as in
  * bitonic_plan; 0 keeps the current value).  bitonic_set_tuning_value sets
  * one value by name: "tile_log2", "fuse", "merge_blocks_per_cu" (as in
- * bitonic_plan) or "seg_blocks_per_cu" (1..16, workgroups per compute unit of
- * the persistent small-segment kernel); bitonic_get_tuning_value reads one.
+ * bitonic_plan), "seg_blocks_per_cu" (1..16, workgroups per compute unit of
+ * the persistent small-segment kernel), "wide_tile_log2" (11..13) or
+ * "wide_fuse" (1..5) (the 8-byte sorts' plan); bitonic_get_tuning_value
+ * reads one.
  * bitonic_load_tuning reads "<name> <value>" lines (the autotuner's output
  * file).  All return BITONIC_OK or BITONIC_EINVAL; they are not thread-safe
  * with concurrent sorts.

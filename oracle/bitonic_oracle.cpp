@@ -44,6 +44,11 @@
 //     index; the virtual one then treats the absent sentinels as INT32_MIN,
 //     which keeps them at the back and the answer at x[0 .. n).
 //
+//  3. oracle_sort_keys64 / oracle_sort_pairs -- the plain definitions for
+//     8-byte keys and for (key, value) pairs (the paper's future work names
+//     other key types; the pair order is a definition of this library: by
+//     key, then by value).
+//
 // Readings of the paper taken here:
 //  * "alternating descending and ascending" is read with the first block
 //    ascending (block ascending iff bit r of the index is 0); either reading
@@ -156,6 +161,78 @@ int oracle_sort_segmented_keys(uint32_t* keys, const int64_t* offsets, int64_t n
                                    : oracle_sort_f32_bits(k, len, ascending);
     if (rc) return rc;
   }
+  return 0;
+}
+
+// totalOrder on binary64 bit patterns, the same rule as for binary32.
+static bool f64_total_less(uint64_t a, uint64_t b) {
+  const bool na = (a >> 63) != 0, nb = (b >> 63) != 0;
+  if (na != nb) return na;
+  const uint64_t ma = a & 0x7FFFFFFFFFFFFFFFull, mb = b & 0x7FFFFFFFFFFFFFFFull;
+#if ORACLE_MUTANT == 10
+  // planted mistake: negatives ordered by increasing magnitude
+  return ma < mb;
+#else
+  return na ? (ma > mb) : (ma < mb);
+#endif
+}
+
+// Plain definition for 8-byte keys (bit patterns in and out): key_type 3
+// int64, 4 uint64, 5 float64 in totalOrder.  Descending is the ascending
+// result read backwards.
+int oracle_sort_keys64(uint64_t* keys, int64_t n, int key_type, int ascending) {
+  if (n < 0 || (n > 0 && keys == nullptr) || key_type < 3 || key_type > 5) return -1;
+  if (key_type == 3) {
+    int64_t* k = reinterpret_cast<int64_t*>(keys);
+#if ORACLE_MUTANT == 9
+    // planted mistake: only the low 32 bits of each key are compared
+    std::stable_sort(k, k + n, [](int64_t a, int64_t b) { return (uint32_t)a < (uint32_t)b; });
+#else
+    std::sort(k, k + n);
+#endif
+  } else if (key_type == 4) {
+    std::sort(keys, keys + n);
+  } else {
+    std::sort(keys, keys + n, f64_total_less);
+  }
+  if (!ascending) std::reverse(keys, keys + n);
+  return 0;
+}
+
+// Plain definition of the key-value sort: pairs (keys[i], values[i]) in the
+// order of their keys (key_type 0 int32, 1 uint32, 2 float32 totalOrder; in
+// the requested direction), pairs with equal keys in ascending order of
+// their int32 values.  That order is unique: pairs that compare equal are
+// identical.  Keys as bit patterns; both arrays rewritten in that order.
+int oracle_sort_pairs(uint32_t* keys, int32_t* values, int64_t n, int key_type, int ascending) {
+  if (n < 0 || (n > 0 && (keys == nullptr || values == nullptr)) || key_type < 0 ||
+      key_type > 2)
+    return -1;
+  auto key_less = [key_type](uint32_t a, uint32_t b) {
+    if (key_type == 0) return (int32_t)a < (int32_t)b;
+    if (key_type == 1) return a < b;
+    return f32_total_less(a, b);
+  };
+  std::vector<int64_t> idx(n);
+  for (int64_t i = 0; i < n; ++i) idx[i] = i;
+  std::sort(idx.begin(), idx.end(), [&](int64_t i, int64_t j) {
+    const uint32_t a = keys[i], b = keys[j];
+    if (key_less(a, b)) return ascending != 0;
+    if (key_less(b, a)) return ascending == 0;
+#if ORACLE_MUTANT == 8
+    return values[i] > values[j];  // planted mistake: ties by value descending
+#else
+    return values[i] < values[j];
+#endif
+  });
+  std::vector<uint32_t> k2(n);
+  std::vector<int32_t> v2(n);
+  for (int64_t i = 0; i < n; ++i) {
+    k2[i] = keys[idx[i]];
+    v2[i] = values[idx[i]];
+  }
+  std::copy(k2.begin(), k2.end(), keys);
+  std::copy(v2.begin(), v2.end(), values);
   return 0;
 }
 

@@ -22,6 +22,9 @@ MUTANTS = {
     5: "last step of every phase dropped",
     6: "padding with zeros instead of INT32_MAX",
     7: "float32 negatives ordered by increasing magnitude",
+    8: "pairs with equal keys ordered by value descending",
+    9: "int64 keys compared on their low 32 bits only",
+    10: "float64 negatives ordered by increasing magnitude",
 }
 
 

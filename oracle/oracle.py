@@ -11,6 +11,8 @@ CPU-baseline leg may import this module.  It loads ``liboracle.so`` (built by
   the paper's phase/step order, with step and compare-exchange counters and a
   per-step hook.  ``variant`` is one of :data:`STANDARD`, :data:`FLIP`,
   :data:`FLIP_VIRTUAL` (see the C source for their definitions).
+* :func:`sort_keys`, :func:`sort_keys64`, :func:`sort_pairs` -- the plain
+  definitions for the other key types and for (key, value) pairs.
 * :func:`bitonic_merge_i32` -- the bitonic merge of section 3.1 alone.
 * :func:`step_pairs` -- the comparators of one step.
 """
@@ -60,6 +62,11 @@ def _bind(lib: ctypes.CDLL) -> ctypes.CDLL:
     lib.oracle_sort_f32_bits.restype = ctypes.c_int
     lib.oracle_sort_segmented_keys.argtypes = [pu, p64, ctypes.c_int64, ctypes.c_int, ctypes.c_int]
     lib.oracle_sort_segmented_keys.restype = ctypes.c_int
+    lib.oracle_sort_keys64.argtypes = [ctypes.POINTER(ctypes.c_uint64), ctypes.c_int64,
+                                       ctypes.c_int, ctypes.c_int]
+    lib.oracle_sort_keys64.restype = ctypes.c_int
+    lib.oracle_sort_pairs.argtypes = [pu, p32, ctypes.c_int64, ctypes.c_int, ctypes.c_int]
+    lib.oracle_sort_pairs.restype = ctypes.c_int
     lib.oracle_mutant_id.argtypes = []
     lib.oracle_mutant_id.restype = ctypes.c_int
     return lib
@@ -116,6 +123,37 @@ def sort_keys(keys, key_type: int, ascending: bool = True, lib=None) -> np.ndarr
     if fn(bits.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)), x.size, int(bool(ascending))):
         raise ValueError("oracle rejected its arguments")
     return x
+
+
+KEY_I64, KEY_U64, KEY_F64 = 3, 4, 5
+_KEY64_DTYPES = {KEY_I64: np.int64, KEY_U64: np.uint64, KEY_F64: np.float64}
+
+
+def sort_keys64(keys, key_type: int, ascending: bool = True, lib=None) -> np.ndarray:
+    """Plain definition for int64 / uint64 / float64 keys (float64 in IEEE
+    totalOrder).  Returns an array of the key type (bit-exact)."""
+    lib = lib or load()
+    x = np.ascontiguousarray(np.asarray(keys, dtype=_KEY64_DTYPES[key_type])).copy()
+    bits = x.view(np.uint64)
+    if lib.oracle_sort_keys64(bits.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), x.size,
+                              int(key_type), int(bool(ascending))):
+        raise ValueError("oracle rejected its arguments")
+    return x
+
+
+def sort_pairs(keys, values, key_type: int = KEY_I32, ascending: bool = True, lib=None):
+    """Plain definition of the key-value sort: by key (key_type 0..2, in the
+    requested direction), equal keys by int32 value ascending.  Returns
+    (keys, values) as new arrays."""
+    lib = lib or load()
+    k = np.ascontiguousarray(np.asarray(keys, dtype=_KEY_DTYPES[key_type])).copy()
+    v = np.ascontiguousarray(np.asarray(values, dtype=np.int32)).copy()
+    if k.size != v.size:
+        raise ValueError("keys and values differ in length")
+    if lib.oracle_sort_pairs(k.view(np.uint32).ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
+                             _p32(v), k.size, int(key_type), int(bool(ascending))):
+        raise ValueError("oracle rejected its arguments")
+    return k, v
 
 
 def sort_segmented_keys(keys, offsets, key_type: int, ascending: bool = True, lib=None):

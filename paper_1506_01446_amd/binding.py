@@ -75,6 +75,14 @@ def load() -> ctypes.CDLL:
         "bitonic_keygen_i32": ([vp, ctypes.c_int64, ctypes.c_uint64, ctypes.c_int64, vp],
                                ctypes.c_int),
         "bitonic_sort_keys": ([vp, ctypes.c_int64, ctypes.c_int, ctypes.c_int, vp], ctypes.c_int),
+        "bitonic_sort_keys64": ([vp, ctypes.c_int64, ctypes.c_int, ctypes.c_int, vp],
+                                ctypes.c_int),
+        "bitonic_sort_pairs": ([vp, vp, ctypes.c_int64, ctypes.c_int, ctypes.c_int, vp],
+                               ctypes.c_int),
+        "bitonic_sort_wide_plan": ([vp, vp, ctypes.c_int64, ctypes.c_int, ctypes.c_int,
+                                    ctypes.POINTER(bitonic_plan), vp], ctypes.c_int),
+        "bitonic_wide_plan_passes": ([ctypes.c_int64, ctypes.POINTER(bitonic_plan)],
+                                     ctypes.c_int64),
         "bitonic_sort_segmented_keys": ([vp, vp, ctypes.c_int64, ctypes.c_int64, ctypes.c_int,
                                          ctypes.c_int, vp], ctypes.c_int),
         "bitonic_plan_describe": ([ctypes.c_int64, ctypes.POINTER(bitonic_plan), vp, vp,
@@ -128,7 +136,7 @@ def _keys_ptr(keys, dtype_name: str = "int32"):
     return keys.data_ptr() if keys.numel() else None
 
 
-KEY_TYPES = {"int32": 0, "uint32": 1, "float32": 2}
+KEY_TYPES = {"int32": 0, "uint32": 1, "float32": 2, "int64": 3, "uint64": 4, "float64": 5}
 
 
 def _key_type(keys, key_type) -> int:
@@ -194,6 +202,77 @@ def bitonic_sort_keys(keys, ascending: bool = True, key_type=None, stream=None) 
     _check("bitonic_sort_keys",
            load().bitonic_sort_keys(ptr, keys.numel(), _key_type(keys, key_type),
                                     int(bool(ascending)), _stream(stream)))
+
+
+def _key_type64(keys, key_type) -> int:
+    import torch
+    if key_type is not None:
+        return KEY_TYPES[key_type] if isinstance(key_type, str) else int(key_type)
+    by_dtype = {torch.int64: 3, torch.float64: 5}
+    if hasattr(torch, "uint64"):
+        by_dtype[torch.uint64] = 4
+    if keys.dtype not in by_dtype:
+        raise ValueError(f"no 64-bit key type for dtype {keys.dtype}")
+    return by_dtype[keys.dtype]
+
+
+def _any64_ptr(keys):
+    import torch
+    if not isinstance(keys, torch.Tensor):
+        raise TypeError("expected a torch tensor on the GPU")
+    if keys.element_size() != 8 or not keys.is_cuda or not keys.is_contiguous():
+        raise ValueError("expected a contiguous tensor of 8-byte keys on the GPU")
+    return keys.data_ptr() if keys.numel() else None
+
+
+def bitonic_sort_keys64(keys, ascending: bool = True, key_type=None, stream=None) -> None:
+    """Sort 8-byte keys in place: int64, uint64 or float64 (IEEE totalOrder),
+    from the tensor's dtype or key_type ("int64", "uint64", "float64"; an
+    int64 tensor may hold the bit patterns of another type)."""
+    ptr = _any64_ptr(keys)
+    _check("bitonic_sort_keys64",
+           load().bitonic_sort_keys64(ptr, keys.numel(), _key_type64(keys, key_type),
+                                      int(bool(ascending)), _stream(stream)))
+
+
+def _pair_ptrs(keys, values):
+    import torch
+    kp = _any32_ptr(keys)
+    if not isinstance(values, torch.Tensor) or values.dtype != torch.int32 or \
+            not values.is_cuda or not values.is_contiguous():
+        raise ValueError("values must be a contiguous int32 tensor on the GPU")
+    if values.numel() != keys.numel():
+        raise ValueError("keys and values differ in length")
+    return kp, (values.data_ptr() if values.numel() else None)
+
+
+def bitonic_sort_pairs(keys, values, ascending: bool = True, key_type=None, stream=None) -> None:
+    """Sort (key, value) pairs in place by key, equal keys by value ascending
+    (with values 0..n-1: a stable argsort).  keys: 4-byte keys (int32,
+    uint32 or float32, from the dtype or key_type); values: int32."""
+    kp, vp_ = _pair_ptrs(keys, values)
+    _check("bitonic_sort_pairs",
+           load().bitonic_sort_pairs(kp, vp_, keys.numel(), _key_type(keys, key_type),
+                                     int(bool(ascending)), _stream(stream)))
+
+
+def bitonic_sort_wide_plan(keys, values=None, ascending: bool = True, key_type=None,
+                           plan=None, stream=None) -> None:
+    """An 8-byte sort (values None: 8-byte keys; else pairs) with an explicit
+    plan ("optimized", tile_log2 11..13, fuse 1..5)."""
+    p = _plan(plan)
+    if values is None:
+        ptr, vptr, kt = _any64_ptr(keys), None, _key_type64(keys, key_type)
+    else:
+        (ptr, vptr), kt = _pair_ptrs(keys, values), _key_type(keys, key_type)
+    _check("bitonic_sort_wide_plan",
+           load().bitonic_sort_wide_plan(ptr, vptr, keys.numel(), kt, int(bool(ascending)),
+                                         _plan_ref(p), _stream(stream)))
+
+
+def bitonic_wide_plan_passes(n: int, plan=None) -> int:
+    p = _plan(plan)
+    return int(load().bitonic_wide_plan_passes(int(n), _plan_ref(p)))
 
 
 def bitonic_sort_segmented_keys(keys, offsets, ascending: bool = True, key_type=None,

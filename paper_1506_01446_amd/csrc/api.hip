@@ -26,6 +26,8 @@ namespace bitonic {
 static std::atomic<int> g_tile_log2{14};
 static std::atomic<int> g_fuse{5};
 static std::atomic<int> g_merge_bpc{2};  // 0: one tile per workgroup
+static std::atomic<int> g_wide_tile_log2{13};  // 8-byte sorts
+static std::atomic<int> g_wide_fuse{4};
 static std::atomic<int> g_seg_bpc{4};    // small-segment workgroups per compute unit
 
 struct Resolved {
@@ -336,6 +338,87 @@ static int capture_graph(bitonic_graph** out, void* scratch, F&& enqueue) {
   return BITONIC_OK;
 }
 
+// The plan of the 8-byte sorts: tile sort, then for every phase p > L its
+// long strides in passes of at most F steps and its last L strides in a tile
+// merge -- the optimized plan of the 4-byte sort on 8-byte elements.  Returns
+// the number of launches (enqueued unless count_only).
+static int64_t enqueue_wide(int64_t* k64, int32_t* k32, int32_t* vals, uint32_t n, Codec64 cd,
+                            int L, int F, hipStream_t st, bool count_only) {
+  const int K = ceil_log2(n);
+  if (K <= 0) return 0;
+  int64_t launches = 0;
+  auto emit = [&](auto&& launch) {
+    if (!count_only) launch();
+    ++launches;
+  };
+  if (K <= L) {
+    const int Lt = K < kWideTileMinLog2 ? kWideTileMinLog2 : K;
+    emit([&] { launch_wide_tile(Lt, 0, k64, k32, vals, n, cd, CX_BOTH, st); });
+    return launches;
+  }
+  emit([&] { launch_wide_tile(L, 0, k64, k32, vals, n, cd, CX_ENC, st); });
+  for (int p = L + 1; p <= K; ++p) {
+    const int nb = p - L;
+    const int npass = (nb + F - 1) / F;
+    int top = p - 1;
+    for (int i = 0; i < npass; ++i) {
+      const int left = top - L + 1;
+      const int passes_left = npass - i;
+      const int f = (left + passes_left - 1) / passes_left;
+      const int q = top - f + 1;
+      emit([&] { launch_wide_pass(f, i == 0, k64, k32, vals, n, q, st); });
+      top = q - 1;
+    }
+    const int cx = p == K ? CX_DEC : CX_NONE;
+    emit([&] { launch_wide_tile(L, 1, k64, k32, vals, n, cd, cx, st); });
+  }
+  return launches;
+}
+
+static int resolve_wide(const bitonic_plan* plan, int* L, int* F) {
+  *L = g_wide_tile_log2.load();
+  *F = g_wide_fuse.load();
+  if (plan) {
+    if (plan->kind != BITONIC_PLAN_AUTO && plan->kind != BITONIC_PLAN_OPTIMIZED)
+      return BITONIC_EINVAL;
+    if (plan->tile_log2) *L = plan->tile_log2;
+    if (plan->fuse) *F = plan->fuse;
+  }
+  if (*L < kWideTileMinLog2 || *L > kWideTileMaxLog2) return BITONIC_EINVAL;
+  if (*F < 1 || *F > kWideFuseMax) return BITONIC_EINVAL;
+  return BITONIC_OK;
+}
+
+// Arguments of an 8-byte sort, by key_type: 8-byte keys (3..5) at keys with
+// values == nullptr, or pairs of 4-byte keys (0..2) at keys and int32 values.
+static int sort_wide(void* keys, int32_t* values, int64_t n, int key_type, int ascending,
+                     const bitonic_plan* plan, void* stream) {
+  if (key_type < BITONIC_KEY_I32 || key_type > BITONIC_KEY_F64) return BITONIC_EINVAL;
+  const bool pairs = key_type <= BITONIC_KEY_F32;
+  if (!pairs && values != nullptr) return BITONIC_EINVAL;
+  if (n < 0) return BITONIC_EINVAL;
+  if (n > (int64_t(1) << 31)) return BITONIC_EUNSUPPORTED;
+  if (n > 1 && (keys == nullptr || (pairs && values == nullptr))) return BITONIC_EINVAL;
+  const uintptr_t align = pairs ? 3u : 7u;
+  if ((reinterpret_cast<uintptr_t>(keys) & align) != 0 ||
+      (reinterpret_cast<uintptr_t>(values) & 3u) != 0)
+    return BITONIC_EINVAL;
+  int L = 0, F = 0;
+  const int rc = resolve_wide(plan, &L, &F);
+  if (rc) return rc;
+  if (n <= 1) return BITONIC_OK;
+  const Codec64 cd = pairs ? make_pair_codec(key_type, ascending != 0)
+                           : make_codec64(key_type, ascending != 0);
+  (void)hipGetLastError();
+  if (pairs)
+    enqueue_wide(nullptr, static_cast<int32_t*>(keys), values, (uint32_t)n, cd, L, F,
+                 (hipStream_t)stream, false);
+  else
+    enqueue_wide(static_cast<int64_t*>(keys), nullptr, nullptr, (uint32_t)n, cd, L, F,
+                 (hipStream_t)stream, false);
+  return finish_launches();
+}
+
 extern "C" {
 
 const char* bitonic_status_string(int status) {
@@ -405,6 +488,30 @@ int bitonic_network_phases_i32(int32_t* keys, int64_t n, int ascending, int last
   (void)hipGetLastError();
   enqueue_plain(keys, (uint32_t)n, last_phase, make_codec(BITONIC_KEY_I32, ascending), r, (hipStream_t)stream, false);
   return finish_launches();
+}
+
+int bitonic_sort_keys64(void* keys, int64_t n, int key_type, int ascending, void* stream) {
+  if (key_type < BITONIC_KEY_I64 || key_type > BITONIC_KEY_F64) return BITONIC_EINVAL;
+  return sort_wide(keys, nullptr, n, key_type, ascending, nullptr, stream);
+}
+
+int bitonic_sort_pairs(void* keys, int32_t* values, int64_t n, int key_type, int ascending,
+                       void* stream) {
+  if (key_type < BITONIC_KEY_I32 || key_type > BITONIC_KEY_F32) return BITONIC_EINVAL;
+  return sort_wide(keys, values, n, key_type, ascending, nullptr, stream);
+}
+
+int bitonic_sort_wide_plan(void* keys, int32_t* values, int64_t n, int key_type, int ascending,
+                           const bitonic_plan* plan, void* stream) {
+  return sort_wide(keys, values, n, key_type, ascending, plan, stream);
+}
+
+int64_t bitonic_wide_plan_passes(int64_t n, const bitonic_plan* plan) {
+  if (n < 0 || n > (int64_t(1) << 31)) return -1;
+  int L = 0, F = 0;
+  if (resolve_wide(plan, &L, &F)) return -1;
+  if (n <= 1) return 0;
+  return enqueue_wide(nullptr, nullptr, nullptr, (uint32_t)n, Codec64{0, 0}, L, F, nullptr, true);
 }
 
 int64_t bitonic_plan_passes(int64_t n, const bitonic_plan* plan) {
@@ -537,6 +644,16 @@ int bitonic_set_tuning_value(const char* key, int value) {
     g_seg_bpc.store(value);
     return BITONIC_OK;
   }
+  if (!std::strcmp(key, "wide_tile_log2")) {
+    if (value < kWideTileMinLog2 || value > kWideTileMaxLog2) return BITONIC_EINVAL;
+    g_wide_tile_log2.store(value);
+    return BITONIC_OK;
+  }
+  if (!std::strcmp(key, "wide_fuse")) {
+    if (value < 1 || value > kWideFuseMax) return BITONIC_EINVAL;
+    g_wide_fuse.store(value);
+    return BITONIC_OK;
+  }
   return BITONIC_EINVAL;
 }
 
@@ -546,6 +663,8 @@ int bitonic_get_tuning_value(const char* key, int* value) {
   else if (!std::strcmp(key, "fuse")) *value = g_fuse.load();
   else if (!std::strcmp(key, "merge_blocks_per_cu")) *value = g_merge_bpc.load() ? g_merge_bpc.load() : -1;
   else if (!std::strcmp(key, "seg_blocks_per_cu")) *value = g_seg_bpc.load();
+  else if (!std::strcmp(key, "wide_tile_log2")) *value = g_wide_tile_log2.load();
+  else if (!std::strcmp(key, "wide_fuse")) *value = g_wide_fuse.load();
   else return BITONIC_EINVAL;
   return BITONIC_OK;
 }

@@ -24,10 +24,21 @@ __device__ __forceinline__ void static_for(F&& f) {
   }
 }
 
+// Sentinel of the 8-byte sorting domain (int64 keys and packed pairs).
+constexpr int64_t kPad64 = 0x7FFFFFFFFFFFFFFFll;
+
 // Compare-exchange: a takes the minimum, b the maximum.
 __device__ __forceinline__ void cmpx(int32_t& a, int32_t& b) {
   const int32_t lo = min(a, b);
   const int32_t hi = max(a, b);
+  a = lo;
+  b = hi;
+}
+
+__device__ __forceinline__ void cmpx(int64_t& a, int64_t& b) {
+  const bool sw = b < a;
+  const int64_t lo = sw ? b : a;
+  const int64_t hi = sw ? a : b;
   a = lo;
   b = hi;
 }
@@ -65,8 +76,8 @@ struct Prog {
 };
 
 // All compare-exchange steps of group G on the registers.
-template <class PR, int G>
-__device__ __forceinline__ void group_steps(int32_t (&x)[PR::R]) {
+template <class PR, int G, class E>
+__device__ __forceinline__ void group_steps(E (&x)[PR::R]) {
   constexpr Group gr = PR::value.g[G];
   static_for<0, gr.nsteps>([&](auto S) {
     constexpr uint32_t D = gr.d[S];
@@ -109,8 +120,8 @@ struct LdsBase {
 // Move the registers from the layout of group GA to that of group GB
 // through LDS (each key to the padded position of its real index).  Begins
 // with a barrier so the LDS is free to overwrite.
-template <class PR, int GA, int GB>
-__device__ __forceinline__ void regroup(int32_t (&x)[PR::R], int32_t* lds, uint32_t tid) {
+template <class PR, int GA, int GB, class E>
+__device__ __forceinline__ void regroup(E (&x)[PR::R], E* lds, uint32_t tid) {
   if constexpr (PR::LEAN) asm volatile("" : "+v"(tid));
   const LdsBase<PR, GA> a(tid);
   const LdsBase<PR, GB> b(tid);
@@ -120,8 +131,8 @@ __device__ __forceinline__ void regroup(int32_t (&x)[PR::R], int32_t* lds, uint3
   static_for<0, PR::R>([&](auto J) { x[J] = lds[b.template at<J>()]; });
 }
 
-template <class PR, int G>
-__device__ __forceinline__ void run_from(int32_t (&x)[PR::R], int32_t* lds, uint32_t tid) {
+template <class PR, int G, class E>
+__device__ __forceinline__ void run_from(E (&x)[PR::R], E* lds, uint32_t tid) {
   group_steps<PR, G>(x);
   if constexpr (G + 1 < PR::value.ngroups) {
     regroup<PR, G, G + 1>(x, lds, tid);
@@ -217,15 +228,18 @@ __device__ __forceinline__ void store_tile(const int32_t (&x)[PR::R], int32_t* _
   }
 }
 
-// Fused long-stride steps on 4 columns x 2^F rows of registers x[4 rho + c]: the mirror step (if MIRROR) on the top row
-// bit, then half-cleaners on the remaining row bits, highest first.
-template <int F, bool MIRROR>
-__device__ __forceinline__ void pass_steps(int32_t (&x)[4 << F]) {
+// Fused long-stride steps on COLS columns x 2^F rows of registers
+// x[COLS rho + c]: the mirror step (if MIRROR) on the top row bit, then
+// half-cleaners on the remaining row bits, highest first.  Rows of the upper
+// half are held mirrored when MIRROR (row rho + 2^(F-1) is the mirror image
+// of row rho), so there the lower index of a pair is the row with the bit set.
+template <int F, bool MIRROR, int COLS = 4, class E>
+__device__ __forceinline__ void pass_steps(E (&x)[COLS << F]) {
   constexpr int ROWS = 1 << F;
   constexpr int TOP = ROWS >> 1;
   if constexpr (MIRROR) {
     static_for<0, TOP>([&](auto RHO) {
-      static_for<0, 4>([&](auto C) { cmpx(x[4 * RHO + C], x[4 * (RHO + TOP) + C]); });
+      static_for<0, COLS>([&](auto C) { cmpx(x[COLS * RHO + C], x[COLS * (RHO + TOP) + C]); });
     });
   }
   constexpr int NB = MIRROR ? F - 1 : F;
@@ -235,13 +249,12 @@ __device__ __forceinline__ void pass_steps(int32_t (&x)[4 << F]) {
       constexpr int rho = RHO;
       constexpr int partner = rho ^ (1 << b);
       if constexpr (rho < partner) {
-        // rho has bit b clear; in a mirrored upper half the order is reversed
         constexpr bool low = !(MIRROR && (rho & TOP));
-        static_for<0, 4>([&](auto C) {
+        static_for<0, COLS>([&](auto C) {
           if constexpr (low) {
-            cmpx(x[4 * rho + C], x[4 * partner + C]);
+            cmpx(x[COLS * rho + C], x[COLS * partner + C]);
           } else {
-            cmpx(x[4 * partner + C], x[4 * rho + C]);
+            cmpx(x[COLS * partner + C], x[COLS * rho + C]);
           }
         });
       }

@@ -37,6 +37,25 @@ void launch_lds_network(int L, int p_first, int p_last, bool tail, int32_t* keys
 void launch_step(int sb, bool mirror, int32_t* keys, uint32_t n, uint32_t N, Codec cd,
                  hipStream_t st);
 
+// Sort of 8-byte elements (kernels_wide.hip): 2^kWideRegLog elements per
+// thread in the tile kernels, tiles of 2^kWideTileMinLog2 .. 2^kWideTileMaxLog2
+// elements, up to kWideFuseMax steps per pass.
+constexpr int kWideRegLog = 5;
+constexpr int kWideTileMinLog2 = 11;
+constexpr int kWideTileMaxLog2 = 13;
+constexpr int kWideFuseMax = 5;
+
+// Tile sort (kind 0) or merge (kind 1) over the 2^L-element tiles of an
+// 8-byte sort: int64 keys at keys64 (values == nullptr), or pairs of 4-byte
+// keys at keys32 and int32 values.  cx as for launch_tile.
+void launch_wide_tile(int L, int kind, int64_t* keys64, int32_t* keys32, int32_t* values,
+                      uint32_t n, Codec64 cd, int cx, hipStream_t st);
+
+// f fused steps on bits q+f-1 .. q of an 8-byte sort, on mapped elements.
+// Requires q + f <= 31, 1 <= f <= kWideFuseMax.
+void launch_wide_pass(int f, bool mirror, int64_t* keys64, int32_t* keys32, int32_t* values,
+                      uint32_t n, int q, hipStream_t st);
+
 // Input generator.
 void launch_keygen(int32_t* out, uint64_t n, uint64_t seed, uint64_t start, hipStream_t st);
 

@@ -59,6 +59,11 @@ def uniform_i32(seed: int, n: int, start: int = 0) -> np.ndarray:
     return (w >> np.uint64(32)).astype(np.uint32).view(np.int32)
 
 
+def uniform_i64(seed: int, n: int, start: int = 0) -> np.ndarray:
+    """Keys uniform over the full signed int64 range (the whole 64-bit word)."""
+    return splitmix64(seed, start, n).view(np.int64)
+
+
 def unit_doubles(seed: int, n: int, start: int = 0) -> np.ndarray:
     """Uniform doubles in [0, 1) from the top 53 bits of each word."""
     w = splitmix64(seed, start, n)
@@ -132,7 +137,7 @@ def serving_requests(duration_s: float, rate_per_s: float, seed: int,
 
 
 __all__ = [
-    "GAMMA", "SEED_BASE", "KINDS", "splitmix64", "splitmix64_scalar",
+    "GAMMA", "SEED_BASE", "KINDS", "splitmix64", "splitmix64_scalar", "uniform_i64",
     "uniform_i32", "unit_doubles", "make_keys", "segment_lengths",
     "offsets_from_lengths", "batched_workload", "serving_requests",
 ]

@@ -55,6 +55,33 @@ def test_argument_errors_are_synchronous(lib):
     assert lib.bitonic_load_tuning(b"/nonexistent/tuning.txt") == -1
 
 
+def test_wide_argument_errors_are_synchronous(lib):
+    """8-byte keys and pairs: bad key types, sizes, pointers and plans are
+    rejected before anything is enqueued (no pointer here is dereferenced)."""
+    I64, F64, I32, F32 = 3, 5, 0, 2
+    assert lib.bitonic_sort_keys64(None, -1, I64, 1, None) == -1
+    assert lib.bitonic_sort_keys64(None, 5, I64, 1, None) == -1
+    assert lib.bitonic_sort_keys64(None, 2**31 + 1, I64, 1, None) == -4
+    assert lib.bitonic_sort_keys64(None, 0, I64, 1, None) == 0
+    assert lib.bitonic_sort_keys64(None, 1, F64, 0, None) == 0
+    assert lib.bitonic_sort_keys64(None, 0, I32, 1, None) == -1     # 4-byte type
+    assert lib.bitonic_sort_keys64(None, 0, 6, 1, None) == -1
+    assert lib.bitonic_sort_keys64(4, 8, I64, 1, None) == -1        # not 8-byte aligned
+    assert lib.bitonic_sort_pairs(None, None, 0, I32, 1, None) == 0
+    assert lib.bitonic_sort_pairs(None, None, 1, F32, 1, None) == 0
+    assert lib.bitonic_sort_pairs(None, None, 2, I32, 1, None) == -1
+    assert lib.bitonic_sort_pairs(None, None, -1, I32, 1, None) == -1
+    assert lib.bitonic_sort_pairs(None, None, 0, I64, 1, None) == -1  # 8-byte type
+    assert lib.bitonic_sort_pairs(4, 6, 8, I32, 1, None) == -1        # values misaligned
+    assert lib.bitonic_sort_pairs(2, 8, 8, I32, 1, None) == -1        # keys misaligned
+    for bad in (B.bitonic_plan(1, 0, 0, 0), B.bitonic_plan(3, 14, 0, 0),
+                B.bitonic_plan(3, 10, 0, 0), B.bitonic_plan(3, 12, 6, 0)):
+        assert lib.bitonic_sort_wide_plan(None, None, 0, I64, 1, ctypes.byref(bad), None) == -1
+        assert lib.bitonic_wide_plan_passes(2**20, ctypes.byref(bad)) == -1
+    assert lib.bitonic_set_tuning_value(b"wide_tile_log2", 14) == -1
+    assert lib.bitonic_set_tuning_value(b"wide_fuse", 0) == -1
+
+
 def _closed_form_optimized(k, t, f):
     if k <= 1:
         return k
@@ -73,6 +100,18 @@ def test_optimized_pass_count(lib, t, f):
         # a non-power-of-two n makes the launches of its padded size
         if k >= 2:
             assert B.bitonic_plan_passes(n - 1, ("optimized", t, f)) == got
+
+
+@pytest.mark.parametrize("t", [11, 12, 13])
+@pytest.mark.parametrize("f", [1, 2, 3, 4, 5])
+def test_wide_pass_count(lib, t, f):
+    """The 8-byte sorts run the optimized plan's schedule (section 4: one
+    tile sort, then per phase beyond the tile its fused passes and a merge)."""
+    for k in range(1, 32):
+        got = B.bitonic_wide_plan_passes(2**k, ("optimized", t, f))
+        assert got == _closed_form_optimized(k, t, f), (k, t, f)
+        if k >= 2:
+            assert B.bitonic_wide_plan_passes(2**k - 1, ("optimized", t, f)) == got
 
 
 def test_basic_plan_is_one_launch_per_round(lib):

@@ -1,0 +1,235 @@
+"""GPU parity of the 8-byte sorts: int64 / uint64 / float64 keys and (key,
+value) pairs, against the CPU oracle, bit for bit.
+
+Sizes span one to several tiles with ragged tails at every plan shape
+(tile 2^11..2^13 elements, 1..5 fused steps); full-size cases check the
+whole array against the oracle; the maximum size is checked by properties
+that hold at any size (order, an exact permutation check, sampled order
+statistics counted in the input).
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_1506_01446_amd import binding as B
+from paper_1506_01446_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+SIZES = [0, 1, 2, 3, 5, 8, 31, 33, 100, 1023, 2047, 2048, 2049, 4097, 8191, 8192, 8193,
+         16383, 16385, 65537, 100003, 262144, 300001]
+PLANS = [None] + [("optimized", t, f) for t in (11, 12, 13) for f in (1, 3, 5)]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    B.load()
+
+
+def _i64(seed, n):
+    keys = W.uniform_i64(seed, n)
+    if n >= 6:
+        keys[:6] = [2**63 - 1, -2**63, -1, 0, 2**63 - 1, -2**63]
+    return keys
+
+
+def _sort64(keys, asc, key_type, plan=None):
+    t = torch.from_numpy(np.ascontiguousarray(keys).view(np.int64).copy()).cuda()
+    if plan is None:
+        B.bitonic_sort_keys64(t, asc, key_type)
+    else:
+        B.bitonic_sort_wide_plan(t, None, asc, key_type, plan)
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def _sort_pairs(keys, values, asc, key_type="int32", plan=None):
+    k = torch.from_numpy(np.ascontiguousarray(keys).view(np.int32).copy()).cuda()
+    v = torch.from_numpy(np.ascontiguousarray(values, dtype=np.int32).copy()).cuda()
+    if plan is None:
+        B.bitonic_sort_pairs(k, v, asc, key_type)
+    else:
+        B.bitonic_sort_wide_plan(k, v, asc, key_type, plan)
+    torch.cuda.synchronize()
+    return k.cpu().numpy(), v.cpu().numpy()
+
+
+@pytest.mark.parametrize("plan", PLANS, ids=lambda p: "default" if p is None else
+                         "-".join(map(str, p)))
+def test_int64_sizes_and_plans(plan):
+    for n in SIZES:
+        keys = _i64(W.SEED_BASE + 50 + n, n)
+        for asc in (True, False):
+            print(f"[case] int64 plan={plan} n={n} asc={asc}", flush=True)
+            want = O.sort_keys64(keys, O.KEY_I64, asc)
+            assert np.array_equal(_sort64(keys, asc, "int64", plan), want), (plan, n, asc)
+
+
+@pytest.mark.parametrize("plan", PLANS, ids=lambda p: "default" if p is None else
+                         "-".join(map(str, p)))
+def test_pairs_sizes_and_plans(plan):
+    for n in SIZES:
+        # few distinct keys: most comparisons are decided by the value word
+        keys = (W.uniform_i32(W.SEED_BASE + 60 + n, n).astype(np.int64) % 97 - 48).astype(np.int32)
+        values = W.uniform_i32(W.SEED_BASE + 61 + n, n)
+        if n >= 4:
+            keys[:4] = [2**31 - 1, -2**31, 2**31 - 1, -2**31]
+            values[:4] = [2**31 - 1, -2**31, -2**31, 2**31 - 1]
+        for asc in (True, False):
+            print(f"[case] pairs plan={plan} n={n} asc={asc}", flush=True)
+            wk, wv = O.sort_pairs(keys, values, O.KEY_I32, asc)
+            gk, gv = _sort_pairs(keys, values, asc, "int32", plan)
+            assert np.array_equal(gk, wk) and np.array_equal(gv, wv), (plan, n, asc)
+
+
+TOTAL_ORDER64 = [0xFFF8000000000001, 0xFFF8000000000000, 0xFFF0000000000001,
+                 0xFFF0000000000000, 0xFFEFFFFFFFFFFFFF, 0xBFF0000000000000,
+                 0x8010000000000000, 0x800FFFFFFFFFFFFF, 0x8000000000000001,
+                 0x8000000000000000, 0x0000000000000000, 0x0000000000000001,
+                 0x000FFFFFFFFFFFFF, 0x0010000000000000, 0x3FF0000000000000,
+                 0x7FEFFFFFFFFFFFFF, 0x7FF0000000000000, 0x7FF0000000000001,
+                 0x7FF8000000000000, 0x7FF8000000000001]
+
+
+@pytest.mark.parametrize("key_type", ["uint64", "float64"])
+def test_other_8_byte_key_types(key_type):
+    """Random 64-bit patterns (for float64: NaNs, infinities, subnormals and
+    zeros of both signs included) and the totalOrder special values."""
+    kt = O.KEY_U64 if key_type == "uint64" else O.KEY_F64
+    dt = np.uint64 if key_type == "uint64" else np.float64
+    special = np.array(TOTAL_ORDER64 * 200, dtype=np.uint64)
+    for n in (3, 1000, 300001, (1 << 20) + 1):
+        bits = W.uniform_i64(n + 71, n).view(np.uint64).copy()
+        bits[: min(n, special.size)] = special[: min(n, special.size)]
+        for asc in (True, False):
+            want = O.sort_keys64(bits.view(dt), kt, asc).view(np.uint64)
+            got = _sort64(bits, asc, key_type).view(np.uint64)
+            assert np.array_equal(got, want), (key_type, n, asc)
+
+
+@pytest.mark.parametrize("key_type", ["uint32", "float32"])
+def test_pairs_other_key_types(key_type):
+    kt = O.KEY_U32 if key_type == "uint32" else O.KEY_F32
+    for n in (7, 5000, 300001):
+        bits = (W.uniform_i32(n + 81, n).astype(np.int64) % 1000).astype(np.uint32)
+        bits[::3] = W.uniform_i32(n + 82, n)[::3].view(np.uint32)   # some NaNs etc.
+        values = W.uniform_i32(n + 83, n)
+        dt = np.uint32 if key_type == "uint32" else np.float32
+        for asc in (True, False):
+            wk, wv = O.sort_pairs(bits.view(dt), values, kt, asc)
+            gk, gv = _sort_pairs(bits, values, asc, key_type)
+            assert np.array_equal(gk.view(np.uint32), wk.view(np.uint32)), (key_type, n, asc)
+            assert np.array_equal(gv, wv), (key_type, n, asc)
+
+
+def test_pairs_argsort_is_stable():
+    n = (1 << 20) + 12345
+    keys = (W.uniform_i32(W.SEED_BASE + 90, n).astype(np.int64) % 5000).astype(np.int32)
+    idx = np.arange(n, dtype=np.int32)
+    for asc in (True, False):
+        _, gv = _sort_pairs(keys, idx, asc)
+        want = np.argsort(keys if asc else -keys.astype(np.int64), kind="stable")
+        assert np.array_equal(gv, want), asc
+
+
+@pytest.mark.parametrize("n", [1 << 24, 10_000_000])
+def test_full_size(n):
+    """Whole-array parity at the headline sizes (default plans)."""
+    keys = W.uniform_i64(W.SEED_BASE + 2, n)
+    for asc in (True, False):
+        print(f"[case] int64 full n={n} asc={asc}", flush=True)
+        assert np.array_equal(_sort64(keys, asc, "int64"), O.sort_keys64(keys, O.KEY_I64, asc))
+    k32 = W.uniform_i32(W.SEED_BASE + 2, n)
+    vals = np.arange(n, dtype=np.int32)
+    print(f"[case] pairs full n={n}", flush=True)
+    wk, wv = O.sort_pairs(k32, vals, O.KEY_I32, True)
+    gk, gv = _sort_pairs(k32, vals, True)
+    assert np.array_equal(gk, wk) and np.array_equal(gv, wv)
+
+
+def _i64_on_device(n, seed, chunk=1 << 28):
+    hi = torch.empty(n, dtype=torch.int32, device="cuda")
+    lo = torch.empty(n, dtype=torch.int32, device="cuda")
+    B.bitonic_keygen_i32(hi, seed)
+    B.bitonic_keygen_i32(lo, seed + 1)
+    t = torch.empty(n, dtype=torch.int64, device="cuda")
+    for a in range(0, n, chunk):
+        t[a:a + chunk] = (hi[a:a + chunk].to(torch.int64) << 32) | \
+            (lo[a:a + chunk].to(torch.int64) & 0xFFFFFFFF)
+    del hi, lo
+    return t
+
+
+def _sorted64(t, chunk=1 << 28):
+    ok = True
+    for a in range(0, t.numel() - 1, chunk):
+        b = min(a + chunk + 1, t.numel())
+        ok = ok and bool((t[a + 1:b] >= t[a:b - 1]).all().item())
+    return ok
+
+
+def _hash64(t, chunk=1 << 28):
+    s1 = torch.zeros((), dtype=torch.int64, device="cuda")
+    s2 = torch.zeros((), dtype=torch.int64, device="cuda")
+    for a in range(0, t.numel(), chunk):
+        c = t[a:a + chunk]
+        s1 += c.sum()
+        # odd multiplier 0x9E3779B97F4A7C15 as int64; products wrap mod 2^64
+        s2 += ((c ^ (c >> 29)) * -7046029254386353131).sum()
+    return int(s1.item()), int(s2.item())
+
+
+def test_int64_maximum_size():
+    """n = 2^31 - 1 int64 keys: sorted order, the multiset (two hashes),
+    extremes and sampled order statistics counted in the input."""
+    n = (1 << 31) - 1
+    print(f"[case] int64 maximum size n={n}", flush=True)
+    t = _i64_on_device(n, W.SEED_BASE + 97)
+    h0 = _hash64(t)
+    lo, hi = int(t.min().item()), int(t.max().item())
+    src = t.clone()
+    B.bitonic_sort_keys64(t, True)
+    torch.cuda.synchronize()
+    assert _sorted64(t)
+    assert _hash64(t) == h0
+    assert int(t[0].item()) == lo and int(t[-1].item()) == hi
+    for i in (0, 1, n // 3, n // 2, n - 2, n - 1):
+        v = int(t[i].item())
+        below = int((src < v).sum().item())
+        upto = int((src <= v).sum().item())
+        assert below <= i < upto, i
+    del src, t
+    torch.cuda.empty_cache()
+
+
+def test_pairs_maximum_size():
+    """n = 2^31 - 1 pairs with values 0..n-1: every output pair is an input
+    pair (key == input key at the value's index), the values are a
+    permutation (each index hit exactly once), and the pairs are strictly
+    increasing by (key, value)."""
+    n = (1 << 31) - 1
+    print(f"[case] pairs maximum size n={n}", flush=True)
+    k = torch.empty(n, dtype=torch.int32, device="cuda")
+    B.bitonic_keygen_i32(k, W.SEED_BASE + 98)
+    src = k.clone()
+    v = torch.arange(n, dtype=torch.int32, device="cuda")
+    B.bitonic_sort_pairs(k, v, True)
+    torch.cuda.synchronize()
+    chunk = 1 << 28
+    hit = torch.zeros(n, dtype=torch.uint8, device="cuda")
+    for a in range(0, n, chunk):
+        vv = v[a:a + chunk].to(torch.int64)
+        assert bool((k[a:a + chunk] == src[vv]).all().item()), a
+        hit[vv] = 1
+    assert bool((hit == 1).all().item())
+    del hit, src
+    for a in range(0, n - 1, chunk):
+        b = min(a + chunk + 1, n)
+        k0, k1 = k[a:b - 1], k[a + 1:b]
+        v0, v1 = v[a:b - 1], v[a + 1:b]
+        assert bool(((k1 > k0) | ((k1 == k0) & (v1 > v0))).all().item()), a
+    del k, v
+    torch.cuda.empty_cache()

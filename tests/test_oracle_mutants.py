@@ -70,8 +70,29 @@ def _pin_f32_total_order(lib):
     return bool(np.array_equal(got, want))
 
 
+def _pin_keys64(lib):
+    keys = W.uniform_i64(8, 3001)
+    keys[:2] = [2**63 - 1, -2**63]
+    return bool(np.array_equal(O.sort_keys64(keys, O.KEY_I64, True, lib=lib), np.sort(keys)))
+
+
+def _pin_f64_total_order(lib):
+    from test_oracle_wide import TOTAL_ORDER64
+    want = np.array(TOTAL_ORDER64, dtype=np.uint64)
+    got = O.sort_keys64(want[::-1].view(np.float64), O.KEY_F64, True, lib=lib).view(np.uint64)
+    return bool(np.array_equal(got, want))
+
+
+def _pin_pairs(lib):
+    keys = (W.uniform_i32(9, 2000).astype(np.int64) % 17).astype(np.int32)
+    values = W.uniform_i32(10, 2000)
+    k, v = O.sort_pairs(keys, values, O.KEY_I32, True, lib=lib)
+    order = np.lexsort((values, keys))
+    return bool(np.array_equal(k, keys[order]) and np.array_equal(v, values[order]))
+
+
 PINS = (_pin_zero_one, _pin_signed_random, _pin_counts, _pin_negative_padding,
-        _pin_f32_total_order)
+        _pin_f32_total_order, _pin_keys64, _pin_f64_total_order, _pin_pairs)
 
 
 @pytest.fixture(scope="module")
