@@ -223,6 +223,47 @@ def rep_protocol(torch, B, W, plan, sizes=(1 << 24, 1 << 26), reps=30, warmup=5)
     return out
 
 
+def wide_sorts(torch, B, W, n=1 << 24, reps=10):
+    """The 8-byte sorts at n = 2^24 (default plan): int64 keys and (int32
+    key, int32 value) pairs with values 0..n-1 (an argsort).  Each moves 16
+    bytes per element per pass."""
+    out = {}
+    ev = B.HipEvents(2)
+    rt = ev.rt
+    rt.hipEventRecord.argtypes = [B.ctypes.c_void_p, B.ctypes.c_void_p]
+    stream = torch.cuda.current_stream().cuda_stream
+    passes = B.bitonic_wide_plan_passes(n)
+    k64 = torch.from_numpy(W.uniform_i64(W.SEED_BASE + 2, n)).cuda()
+    k32 = torch.from_numpy(W.uniform_i32(W.SEED_BASE + 2, n)).cuda()
+    iota = torch.arange(n, dtype=torch.int32, device="cuda")
+    for kind in ("int64", "pairs"):
+        if kind == "int64":
+            bufs = [k64.clone() for _ in range(reps + 2)]
+            run = lambda i: B.bitonic_sort_keys64(bufs[i], True, "int64")  # noqa: E731
+        else:
+            bufs = [(k32.clone(), iota.clone()) for _ in range(reps + 2)]
+            run = lambda i: B.bitonic_sort_pairs(bufs[i][0], bufs[i][1], True)  # noqa: E731
+        run(0)
+        run(1)
+        torch.cuda.synchronize()
+        rt.hipEventRecord(ev.ev[0], stream)
+        for i in range(2, reps + 2):
+            run(i)
+        rt.hipEventRecord(ev.ev[1], stream)
+        torch.cuda.synchronize()
+        ms = ev.elapsed_ms(0, 1) / reps
+        last = bufs[-1] if kind == "int64" else bufs[-1][0]
+        ok = bool((last[1:] >= last[:-1]).all().item())
+        out[kind] = {"n": n, "ms": round(ms, 4), "gkeys_s": round(n / (ms * 1e-3) / 1e9, 3),
+                     "launches": passes,
+                     "algorithmic_GBps_per_launch": round(16.0 * n * passes / (ms * 1e-3) / 1e9, 1),
+                     "sorted_check": ok}
+        del bufs
+    ev.close()
+    del k64, k32, iota
+    return out
+
+
 def cpu_network_context(n=1 << 20):
     """The oracle's scalar flip network (one thread) at a bounded size: the
     analogue of the paper's CPU bitonic-sort column, as context only."""
@@ -437,6 +478,8 @@ def main():
         extra["serving"] = serving.run_gpu(duration_s=args.serve_seconds)
         log(f"[bench] serving: {json.dumps(extra['serving'])}")
     if not args.no_extra:
+        extra["wide"] = wide_sorts(torch, B, W)
+        log(f"[bench] 8-byte sorts: {json.dumps(extra['wide'])}")
         extra["protocol"] = rep_protocol(torch, B, W, plan)
         log(f"[bench] protocol: {json.dumps(extra['protocol'])}")
     cpu = None if args.no_cpu else cpu_baseline(n)
