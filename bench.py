@@ -152,6 +152,9 @@ def kernel_class(name: str):
     if name.startswith("global_pass_kernel<"):
         f_, _, bounded = name[len("global_pass_kernel<"):name.index(">")].split(", ")
         return f"global_pass_f{f_}" if bounded == "false" else None
+    if name.startswith("column_pass_kernel<") and "Keys32" in name:
+        f_, _, bounded = name[len("column_pass_kernel<"):name.index(">")].split(", ")[:3]
+        return f"global_pass_f{f_}" if bounded == "false" else None
     return None
 
 

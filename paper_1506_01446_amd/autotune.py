@@ -3,8 +3,8 @@
 python -m paper_1506_01446_amd.autotune [--n 16777216] [--out tuning.txt]
 
 Searches, on the GPU, the plan parameters that do not change the result:
-  tile_log2            keys per on-chip tile (2^11 .. 2^13)
-  fuse                 long-stride steps fused per HBM pass (3 .. 5)
+  tile_log2            keys per on-chip tile (2^12 .. 2^15)
+  fuse                 long-stride steps fused per HBM pass (4 .. 7)
   merge_blocks_per_cu  tile-merge workgroups per compute unit (-1: one tile each)
 for the single-array sort of n keys, and
   seg_blocks_per_cu    workgroups per compute unit of the persistent
@@ -73,9 +73,9 @@ def tune(n: int = 1 << 24, reps: int = 5, quick: bool = False, log=print) -> dic
     import torch
     B.load()
     src = torch.from_numpy(W.uniform_i32(W.SEED_BASE + 2, n)).cuda()
-    tiles = (13,) if quick else (11, 12, 13)
-    fuses = (4, 5) if quick else (3, 4, 5)
-    merges = (-1,) if quick else (-1, 4)
+    tiles = (14,) if quick else (12, 13, 14, 15)
+    fuses = (5, 7) if quick else (4, 5, 6, 7)
+    merges = (2,) if quick else (-1, 1, 2, 4)
     results = []
     for t, f, m in itertools.product(tiles, fuses, merges):
         ms = _time_plain(torch, src, ("optimized", t, f, m), reps)

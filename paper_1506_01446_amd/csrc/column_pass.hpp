@@ -1,0 +1,147 @@
+// One-column fused passes over global memory, shared by the sorts of 4-byte
+// keys (for 6 or 7 fused steps) and of 8-byte elements (any number), and the
+// storage types they read and write.
+//
+// A storage type names where the elements of a sort live: Keys32 (an array
+// of 4-byte keys), Keys64 (an array of 8-byte keys) or Pairs (an array of
+// 4-byte keys and an array of int32 values, moving as one 8-byte element:
+// key word high, value word low).  E is the element type in registers and
+// kPadE the sentinel of the sorting domain for indices >= n.
+#pragma once
+
+#include "device.hpp"
+
+namespace bitonic {
+
+// get/put take an element index; getb/putb take the index times kUnit as a
+// 32-bit byte offset, so a uniform base plus a lane offset maps onto the
+// scalar-base + vector-offset global addressing form.
+struct Keys32 {
+  using E = int32_t;
+  static constexpr E kPadE = kPad;
+  static constexpr uint32_t kUnit = 4;
+  int32_t* k;
+  __device__ __forceinline__ int32_t get(uint32_t i) const { return k[i]; }
+  __device__ __forceinline__ void put(uint32_t i, int32_t x) const { k[i] = x; }
+  __device__ __forceinline__ Keys32 at(size_t i) const { return Keys32{k + i}; }
+  __device__ __forceinline__ int32_t getb(uint32_t b) const {
+    return *reinterpret_cast<const int32_t*>(reinterpret_cast<const char*>(k) + b);
+  }
+  __device__ __forceinline__ void putb(uint32_t b, int32_t x) const {
+    *reinterpret_cast<int32_t*>(reinterpret_cast<char*>(k) + b) = x;
+  }
+};
+
+struct Keys64 {
+  using E = int64_t;
+  static constexpr E kPadE = kPad64;
+  static constexpr uint32_t kUnit = 8;
+  int64_t* k;
+  __device__ __forceinline__ int64_t get(uint32_t i) const { return k[i]; }
+  __device__ __forceinline__ void put(uint32_t i, int64_t x) const { k[i] = x; }
+  __device__ __forceinline__ Keys64 at(size_t i) const { return Keys64{k + i}; }
+  __device__ __forceinline__ int64_t getb(uint32_t b) const {
+    return *reinterpret_cast<const int64_t*>(reinterpret_cast<const char*>(k) + b);
+  }
+  __device__ __forceinline__ void putb(uint32_t b, int64_t x) const {
+    *reinterpret_cast<int64_t*>(reinterpret_cast<char*>(k) + b) = x;
+  }
+};
+
+struct Pairs {
+  using E = int64_t;
+  static constexpr E kPadE = kPad64;
+  int32_t* k;
+  int32_t* v;
+  __device__ __forceinline__ int64_t get(uint32_t i) const {
+    return (int64_t)(((uint64_t)(uint32_t)k[i] << 32) | (uint32_t)v[i]);
+  }
+  __device__ __forceinline__ void put(uint32_t i, int64_t x) const {
+    k[i] = (int32_t)((uint64_t)x >> 32);
+    v[i] = (int32_t)(uint32_t)(uint64_t)x;
+  }
+  __device__ __forceinline__ Pairs at(size_t i) const { return Pairs{k + i, v + i}; }
+  static constexpr uint32_t kUnit = 4;
+  __device__ __forceinline__ int64_t getb(uint32_t b) const {
+    const uint32_t hi = *reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(k) + b);
+    const uint32_t lo = *reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(v) + b);
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+  }
+  __device__ __forceinline__ void putb(uint32_t b, int64_t x) const {
+    *reinterpret_cast<int32_t*>(reinterpret_cast<char*>(k) + b) = (int32_t)((uint64_t)x >> 32);
+    *reinterpret_cast<int32_t*>(reinterpret_cast<char*>(v) + b) = (int32_t)(uint32_t)(uint64_t)x;
+  }
+};
+
+// F consecutive steps on index bits q+F-1 .. q (the first the mirror step of
+// the phase if MIRROR).  Thread g = g0 + blockIdx.x * 256 + threadIdx.x owns
+// column c = g mod 2^q of block b = g / 2^q of 2^(q+F) elements: rows
+// rho = 0 .. 2^F-1 at c + rho 2^q within the block, the upper half mirrored
+// when MIRROR (row rho holds index (2^F-1-(rho mod 2^(F-1))) 2^q + 2^q-1-c).
+// Consecutive threads own consecutive columns, so every row access is
+// coalesced.  Since 256 divides 2^q a workgroup stays inside one block, so a
+// row's address is a workgroup-uniform row start plus the lane's column (or
+// its mirror image) as a 32-bit byte offset, which keeps few vector
+// registers live.  BOUNDED == false: the whole block lies below n and nothing
+// is checked.  BOUNDED == true: indices >= n read as sentinels and are not
+// stored.
+template <int F, bool MIRROR, bool BOUNDED, class ST>
+__global__ __launch_bounds__(256) void column_pass_kernel(ST st, uint32_t n, int q, uint32_t g0) {
+  using E = typename ST::E;
+  constexpr int ROWS = 1 << F;
+  constexpr int TOP = ROWS >> 1;
+  E x[ROWS];
+  const uint32_t gw = g0 + blockIdx.x * 256u;                // uniform
+  const uint32_t bs = (gw >> q) << (q + F);                   // uniform block start
+  const uint32_t col = (gw + threadIdx.x) & ((1u << q) - 1u);
+  const uint32_t mcol = ((1u << q) - 1u) - col;
+  // the thread's lowest index is bs + col; its mirrored rows lie higher
+  if (BOUNDED && bs + col >= n) return;
+  const uint32_t off = col * ST::kUnit;                       // byte offsets, < 2^(q+3)
+  const uint32_t moff = mcol * ST::kUnit;
+  auto row_of = [&](int rho) -> uint32_t {                    // uniform row
+    return (MIRROR && (rho & TOP)) ? (uint32_t)(ROWS - 1 - (rho & (TOP - 1))) : (uint32_t)rho;
+  };
+  static_for<0, ROWS>([&](auto RHO) {
+    constexpr bool mir = MIRROR && (RHO & TOP);
+    const uint32_t r0 = bs + (row_of(RHO) << q);              // uniform
+    if constexpr (BOUNDED) {
+      x[RHO] = r0 + (mir ? mcol : col) < n ? st.at(r0).getb(mir ? moff : off) : ST::kPadE;
+    } else {
+      x[RHO] = st.at(r0).getb(mir ? moff : off);
+    }
+  });
+  __builtin_amdgcn_sched_barrier(0);
+  pass_steps<F, MIRROR, 1>(x);
+  __builtin_amdgcn_sched_barrier(0);
+  static_for<0, ROWS>([&](auto RHO) {
+    constexpr bool mir = MIRROR && (RHO & TOP);
+    const uint32_t r0 = bs + (row_of(RHO) << q);
+    if (!BOUNDED || r0 + (mir ? mcol : col) < n) st.at(r0).putb(mir ? moff : off, x[RHO]);
+    __builtin_amdgcn_sched_barrier(0);
+  });
+}
+
+template <int F, bool MIRROR, class ST>
+static void launch_column_pass_FM(ST st, uint32_t n, int q, hipStream_t s) {
+  // 2^q threads per 2^(q+F) block: blocks wholly below n take the unchecked
+  // kernel, the block that straddles n (if any) the checked one
+  const uint64_t full = ((uint64_t)n >> (q + F)) << q;   // a multiple of 256 (q >= 8)
+  const uint64_t blocks = ((uint64_t)n + (1ull << (q + F)) - 1) >> (q + F);
+  const uint64_t total = blocks << q;
+  if (full > 0)
+    column_pass_kernel<F, MIRROR, false, ST><<<(uint32_t)(full / 256), 256, 0, s>>>(st, n, q, 0u);
+  if (total > full)
+    column_pass_kernel<F, MIRROR, true, ST><<<(uint32_t)((total - full + 255) / 256), 256, 0, s>>>(
+        st, n, q, (uint32_t)full);
+}
+
+template <int F, class ST>
+static void launch_column_pass_F(bool mirror, ST st, uint32_t n, int q, hipStream_t s) {
+  if (mirror)
+    launch_column_pass_FM<F, true>(st, n, q, s);
+  else
+    launch_column_pass_FM<F, false>(st, n, q, s);
+}
+
+}  // namespace bitonic

@@ -9,7 +9,8 @@
 //  global_pass_kernel<F>  F consecutive steps with strides >= 2^q in one pass
 //                         over HBM: each thread holds 4 columns x 2^F rows of
 //                         keys in registers (section 4.2, generalised from
-//                         2 steps to F)
+//                         2 steps to F); for F = 6, 7 the one-column kernel of
+//                         column_pass.hpp
 //  lds_network_kernel     the same network steps with one compare-exchange per
 //                         thread per step in LDS (section 4.1 as written)
 //  step_kernel            one step, one compare-exchange per thread, in global
@@ -19,6 +20,7 @@
 // >= n as absent INT32_MAX sentinels.  The tile and pass kernels of a sort
 // apply the codec only where the sort's data enters and leaves them (CX, see
 // KeyIO); the LDS-network and step kernels apply it at every access.
+#include "column_pass.hpp"
 #include "device.hpp"
 #include "launch.hpp"
 
@@ -349,6 +351,10 @@ void launch_global_pass(int f, bool mirror, int32_t* keys, uint32_t n, int q, hi
     case 3: launch_global_F<3>(mirror, keys, n, q, st); break;
     case 4: launch_global_F<4>(mirror, keys, n, q, st); break;
     case 5: launch_global_F<5>(mirror, keys, n, q, st); break;
+    // wider fusion: one column of 2^f keys per thread (the same 128 keys at
+    // f = 7 as four columns at f = 5), 256 B per wave access
+    case 6: launch_column_pass_F<6>(mirror, Keys32{keys}, n, q, st); break;
+    case 7: launch_column_pass_F<7>(mirror, Keys32{keys}, n, q, st); break;
     default: break;
   }
 }
