@@ -193,8 +193,8 @@ typedef struct bitonic_plan {
   int tile_log2;           /* keys per on-chip tile = 2^tile_log2, 11..15 for
                               the optimized plan, 1..13 for semi (0 = library
                               choice) */
-  int fuse;                /* max long-stride steps per HBM pass, 1..7
-                              (0 = library choice, 7) */
+  int fuse;                /* max long-stride steps per HBM pass, 1..8
+                              (0 = library choice, 8) */
   int merge_blocks_per_cu; /* tile-merge workgroups per compute unit, 1..16,
                               each looping over its tiles with the next
                               tile's loads in flight; -1 = one tile per

@@ -4,7 +4,7 @@ python -m paper_1506_01446_amd.autotune [--n 16777216] [--out tuning.txt]
 
 Searches, on the GPU, the plan parameters that do not change the result:
   tile_log2            keys per on-chip tile (2^12 .. 2^15)
-  fuse                 long-stride steps fused per HBM pass (4 .. 7)
+  fuse                 long-stride steps fused per HBM pass (5 .. 8)
   merge_blocks_per_cu  tile-merge workgroups per compute unit (-1: one tile each)
 for the single-array sort of n keys, and
   seg_blocks_per_cu    workgroups per compute unit of the persistent
@@ -74,7 +74,7 @@ def tune(n: int = 1 << 24, reps: int = 5, quick: bool = False, log=print) -> dic
     B.load()
     src = torch.from_numpy(W.uniform_i32(W.SEED_BASE + 2, n)).cuda()
     tiles = (14,) if quick else (12, 13, 14, 15)
-    fuses = (5, 7) if quick else (4, 5, 6, 7)
+    fuses = (7, 8) if quick else (5, 6, 7, 8)
     merges = (2,) if quick else (-1, 1, 2, 4)
     results = []
     for t, f, m in itertools.product(tiles, fuses, merges):

@@ -24,7 +24,7 @@
 namespace bitonic {
 
 static std::atomic<int> g_tile_log2{14};
-static std::atomic<int> g_fuse{7};
+static std::atomic<int> g_fuse{8};
 static std::atomic<int> g_merge_bpc{2};  // 0: one tile per workgroup
 static std::atomic<int> g_wide_tile_log2{12};  // 8-byte sorts
 static std::atomic<int> g_wide_fuse{5};

@@ -1,5 +1,5 @@
 // One-column fused passes over global memory, shared by the sorts of 4-byte
-// keys (for 6 or 7 fused steps) and of 8-byte elements (any number), and the
+// keys (for 6 to 8 fused steps) and of 8-byte elements (any number), and the
 // storage types they read and write.
 //
 // A storage type names where the elements of a sort live: Keys32 (an array

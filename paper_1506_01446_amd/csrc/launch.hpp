@@ -11,7 +11,7 @@ namespace bitonic {
 constexpr int kTileRegLogPlain = 5;  // 32 keys per thread in the tile kernels
 constexpr int kTileMinLog2 = 11;
 constexpr int kTileMaxLog2 = 15;
-constexpr int kFuseMax = 7;
+constexpr int kFuseMax = 8;
 constexpr int kLdsNetworkMaxLog2 = 13;
 
 bool tile_log2_supported(int L);
@@ -26,9 +26,12 @@ void launch_tile(int L, int kind, int32_t* keys, uint32_t n, Codec cd, int cx,
 
 // f fused steps on bits q+f-1 .. q (the first one the mirror step if
 // `mirror`) on keys already in the sorting domain.  Requires q >= 8,
-// q + f <= 31, 1 <= f <= kFuseMax (f <= 5: four columns per thread; 6, 7:
+// q + f <= 31, 1 <= f <= kFuseMax (f <= 5: four columns per thread; 6..8:
 // one column).
 void launch_global_pass(int f, bool mirror, int32_t* keys, uint32_t n, int q, hipStream_t st);
+
+// The one-column passes behind launch_global_pass for f = 6 .. kFuseMax.
+void launch_column_pass_i32(int f, bool mirror, int32_t* keys, uint32_t n, int q, hipStream_t st);
 
 // LDS network on 2^L tiles (L <= kLdsNetworkMaxLog2).
 void launch_lds_network(int L, int p_first, int p_last, bool tail, int32_t* keys, uint32_t n,

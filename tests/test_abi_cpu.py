@@ -49,7 +49,7 @@ def test_argument_errors_are_synchronous(lib):
     assert lib.bitonic_sort_segmented_bounded_i32(None, None, 3, -1, 1, None) == -1
     assert lib.bitonic_keygen_i32(None, -1, 0, 0, None) == -1
     assert lib.bitonic_set_tuning(99, 0, 0) == -1
-    assert lib.bitonic_set_tuning(0, 8, 0) == -1
+    assert lib.bitonic_set_tuning(0, 9, 0) == -1
     assert lib.bitonic_set_tuning(0, 0, 99) == -1
     assert lib.bitonic_set_tuning(0, 0, -2) == -1
     assert lib.bitonic_load_tuning(b"/nonexistent/tuning.txt") == -1
@@ -91,7 +91,7 @@ def _closed_form_optimized(k, t, f):
 
 
 @pytest.mark.parametrize("t", [11, 12, 13, 14, 15])
-@pytest.mark.parametrize("f", [1, 2, 3, 4, 5, 6, 7])
+@pytest.mark.parametrize("f", [1, 2, 3, 4, 5, 6, 7, 8])
 def test_optimized_pass_count(lib, t, f):
     for k in range(1, 32):
         n = 2**k
@@ -131,7 +131,7 @@ def test_semi_plan_counts(lib):
 def test_headline_pass_count(lib):
     # n = 2^24 with 2^13-key tiles and up to 4 fused steps per HBM pass
     assert B.bitonic_plan_passes(2**24, ("optimized", 13, 4)) == 33
-    assert B.bitonic_plan_passes(2**24) == 24  # default: 2^14 tiles, 7 fused steps
+    assert B.bitonic_plan_passes(2**24) == 23  # default: 2^14 tiles, 8 fused steps
     assert B.bitonic_plan_passes(0) == 0 and B.bitonic_plan_passes(1) == 0
     assert B.bitonic_plan_passes(-1) == -1
 

@@ -19,9 +19,9 @@ SIZES = [0, 1, 2, 3, 4, 5, 7, 8, 9, 15, 16, 17, 31, 33, 63, 64, 65, 127, 129, 25
          257, 1000, 1023, 1024, 1025, 2047, 2048, 2049, 4095, 4096, 4097, 8191, 8192, 8193,
          16383, 16385, 32768, 65535, 65536, 65537, 100003, 131075, 262144, 300001]
 PLANS = [("basic",), ("semi", 8), ("semi", 12)] + \
-        [("optimized", t, f) for t in (11, 12, 13, 14, 15) for f in (1, 2, 3, 4, 5, 6, 7)] + \
+        [("optimized", t, f) for t in (11, 12, 13, 14, 15) for f in (1, 2, 3, 4, 5, 6, 7, 8)] + \
         [("optimized", 13, 5, 4), ("optimized", 14, 5, 2), ("optimized", 15, 5, 1),
-         ("optimized", 14, 7, 2)]
+         ("optimized", 14, 7, 2), ("optimized", 14, 8, 2)]
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -176,10 +176,11 @@ def test_config_2_full_size():
         _full_check(keys, False, want)
 
 
-@pytest.mark.parametrize("plan", [("optimized", 14, 7, 2), ("optimized", 13, 6)],
+@pytest.mark.parametrize("plan", [("optimized", 14, 8, 2), ("optimized", 14, 7, 2),
+                                  ("optimized", 13, 6)],
                          ids=lambda p: "-".join(map(str, p)))
 def test_wide_fusion_full_size(plan):
-    """Six and seven fused steps (one-column passes) at strides up to 2^23."""
+    """Six to eight fused steps (one-column passes) at strides up to 2^23."""
     for n, seed in ((1 << 24, W.SEED_BASE + 2), (10_000_007, W.SEED_BASE + 3)):
         keys = W.uniform_i32(seed, n)
         want = O.sort_i32(keys, True)
