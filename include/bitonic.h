@@ -194,7 +194,8 @@ typedef struct bitonic_plan {
                               the optimized plan, 1..13 for semi (0 = library
                               choice) */
   int fuse;                /* max long-stride steps per HBM pass, 1..8
-                              (0 = library choice, 8) */
+                              (0 = library choice, 8); at most 7 are used
+                              when n is not a power of two */
   int merge_blocks_per_cu; /* tile-merge workgroups per compute unit, 1..16,
                               each looping over its tiles with the next
                               tile's loads in flight; -1 = one tile per

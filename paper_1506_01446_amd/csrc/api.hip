@@ -137,10 +137,14 @@ static int64_t enqueue_plain(int32_t* keys, uint32_t n, int K, Codec flip, const
   // The tile sort encodes the keys and the last merge decodes them; the
   // passes and merges in between work on encoded keys.
   const int L = r.tile;
+  // Eight fused steps only when n is a power of two: otherwise the block of
+  // a pass that straddles n takes the bounds-checked eight-step kernel, which
+  // runs out of registers, so such sorts use at most seven.
+  const int fuse = (r.fuse > kFuseMaxRagged && (n & (n - 1)) != 0) ? kFuseMaxRagged : r.fuse;
   emit(BITONIC_LAUNCH_TILE_SORT, 0, [&] { launch_tile(L, 0, keys, n, flip, CX_ENC, 0, st); });
   for (int p = L + 1; p <= K; ++p) {
     const int nb = p - L;                          // long-stride steps
-    const int npass = (nb + r.fuse - 1) / r.fuse;  // fused HBM passes
+    const int npass = (nb + fuse - 1) / fuse;      // fused HBM passes
     int top = p - 1;
     // Each pass takes as many steps as it may, the last one what is left:
     // the phase's first pass, the one with the mirror step, is then always
@@ -149,7 +153,7 @@ static int64_t enqueue_plain(int32_t* keys, uint32_t n, int K, Codec flip, const
     for (int i = 0; i < npass; ++i) {
       const int left = top - L + 1;                // bits still to do
       const int passes_left = npass - i;
-      const int f = r.fuse < left - (passes_left - 1) ? r.fuse : left - (passes_left - 1);
+      const int f = fuse < left - (passes_left - 1) ? fuse : left - (passes_left - 1);
       const int q = top - f + 1;
       emit(BITONIC_LAUNCH_GLOBAL_PASS, f,
            [&] { launch_global_pass(f, i == 0, keys, n, q, st); });

@@ -12,6 +12,7 @@ constexpr int kTileRegLogPlain = 5;  // 32 keys per thread in the tile kernels
 constexpr int kTileMinLog2 = 11;
 constexpr int kTileMaxLog2 = 15;
 constexpr int kFuseMax = 8;
+constexpr int kFuseMaxRagged = 7;  // n not a power of two (see enqueue_plain)
 constexpr int kLdsNetworkMaxLog2 = 13;
 
 bool tile_log2_supported(int L);
