@@ -207,8 +207,8 @@ typedef struct bitonic_plan {
  * F64) sorts keys (bitonic_sort_keys64; values must be NULL), a 4-byte one
  * sorts pairs (bitonic_sort_pairs).  The plan's kind
  * must be BITONIC_PLAN_AUTO or BITONIC_PLAN_OPTIMIZED, its tile_log2 11..13
- * (elements per tile), its fuse 1..5; merge_blocks_per_cu is ignored (one
- * tile per workgroup).  Library choices (0): tile_log2 12, fuse 5 (tuning
+ * (elements per tile), its fuse 1..6; merge_blocks_per_cu is ignored (one
+ * tile per workgroup).  Library choices (0): tile_log2 12, fuse 6 (tuning
  * values "wide_tile_log2" and "wide_fuse").
  */
 int bitonic_sort_wide_plan(void* keys, int32_t* values, int64_t n, int key_type, int ascending,
@@ -292,7 +292,7 @@ int bitonic_sort_plan_launches_i32(int32_t* keys, int64_t n, int ascending,
  * one value by name: "tile_log2", "fuse", "merge_blocks_per_cu" (as in
  * bitonic_plan), "seg_blocks_per_cu" (1..16, workgroups per compute unit of
  * the persistent small-segment kernel), "wide_tile_log2" (11..13) or
- * "wide_fuse" (1..5) (the 8-byte sorts' plan); bitonic_get_tuning_value
+ * "wide_fuse" (1..6) (the 8-byte sorts' plan); bitonic_get_tuning_value
  * reads one.
  * bitonic_load_tuning reads "<name> <value>" lines (the autotuner's output
  * file).  All return BITONIC_OK or BITONIC_EINVAL; they are not thread-safe

@@ -259,7 +259,7 @@ def bitonic_sort_pairs(keys, values, ascending: bool = True, key_type=None, stre
 def bitonic_sort_wide_plan(keys, values=None, ascending: bool = True, key_type=None,
                            plan=None, stream=None) -> None:
     """An 8-byte sort (values None: 8-byte keys; else pairs) with an explicit
-    plan ("optimized", tile_log2 11..13, fuse 1..5)."""
+    plan ("optimized", tile_log2 11..13, fuse 1..6)."""
     p = _plan(plan)
     if values is None:
         ptr, vptr, kt = _any64_ptr(keys), None, _key_type64(keys, key_type)

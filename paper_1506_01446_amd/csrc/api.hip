@@ -27,7 +27,7 @@ static std::atomic<int> g_tile_log2{14};
 static std::atomic<int> g_fuse{8};
 static std::atomic<int> g_merge_bpc{2};  // 0: one tile per workgroup
 static std::atomic<int> g_wide_tile_log2{12};  // 8-byte sorts
-static std::atomic<int> g_wide_fuse{5};
+static std::atomic<int> g_wide_fuse{6};
 static std::atomic<int> g_seg_bpc{4};    // small-segment workgroups per compute unit
 
 struct Resolved {

@@ -107,6 +107,7 @@ static void launch_wide_pass_st(int f, bool mirror, ST st, uint32_t n, int q, hi
     case 3: launch_column_pass_F<3>(mirror, st, n, q, s); break;
     case 4: launch_column_pass_F<4>(mirror, st, n, q, s); break;
     case 5: launch_column_pass_F<5>(mirror, st, n, q, s); break;
+    case 6: launch_column_pass_F<6>(mirror, st, n, q, s); break;
     default: break;
   }
 }

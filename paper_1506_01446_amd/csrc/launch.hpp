@@ -48,7 +48,7 @@ void launch_step(int sb, bool mirror, int32_t* keys, uint32_t n, uint32_t N, Cod
 constexpr int kWideRegLog = 5;
 constexpr int kWideTileMinLog2 = 11;
 constexpr int kWideTileMaxLog2 = 13;
-constexpr int kWideFuseMax = 5;
+constexpr int kWideFuseMax = 6;
 
 // Tile sort (kind 0) or merge (kind 1) over the 2^L-element tiles of an
 // 8-byte sort: int64 keys at keys64 (values == nullptr), or pairs of 4-byte

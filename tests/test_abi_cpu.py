@@ -75,7 +75,7 @@ def test_wide_argument_errors_are_synchronous(lib):
     assert lib.bitonic_sort_pairs(4, 6, 8, I32, 1, None) == -1        # values misaligned
     assert lib.bitonic_sort_pairs(2, 8, 8, I32, 1, None) == -1        # keys misaligned
     for bad in (B.bitonic_plan(1, 0, 0, 0), B.bitonic_plan(3, 14, 0, 0),
-                B.bitonic_plan(3, 10, 0, 0), B.bitonic_plan(3, 12, 6, 0)):
+                B.bitonic_plan(3, 10, 0, 0), B.bitonic_plan(3, 12, 7, 0)):
         assert lib.bitonic_sort_wide_plan(None, None, 0, I64, 1, ctypes.byref(bad), None) == -1
         assert lib.bitonic_wide_plan_passes(2**20, ctypes.byref(bad)) == -1
     assert lib.bitonic_set_tuning_value(b"wide_tile_log2", 14) == -1
@@ -105,7 +105,7 @@ def test_optimized_pass_count(lib, t, f):
 
 
 @pytest.mark.parametrize("t", [11, 12, 13])
-@pytest.mark.parametrize("f", [1, 2, 3, 4, 5])
+@pytest.mark.parametrize("f", [1, 2, 3, 4, 5, 6])
 def test_wide_pass_count(lib, t, f):
     """The 8-byte sorts run the optimized plan's schedule (section 4: one
     tile sort, then per phase beyond the tile its fused passes and a merge)."""

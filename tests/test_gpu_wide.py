@@ -19,7 +19,7 @@ pytestmark = pytest.mark.gpu
 
 SIZES = [0, 1, 2, 3, 5, 8, 31, 33, 100, 1023, 2047, 2048, 2049, 4097, 8191, 8192, 8193,
          16383, 16385, 65537, 100003, 262144, 300001]
-PLANS = [None] + [("optimized", t, f) for t in (11, 12, 13) for f in (1, 3, 5)]
+PLANS = [None] + [("optimized", t, f) for t in (11, 12, 13) for f in (1, 3, 5, 6)]
 
 
 @pytest.fixture(scope="module", autouse=True)
