@@ -130,14 +130,22 @@ def kernel_table(torch, B, src, plan, repeats=10):
     return rows
 
 
+# The sources that define the single-array sort's kernels (device code and
+# the launch shapes of launch.hpp); the counters of profiles/ are tied to them.
+KERNEL_SOURCES = ("program.hpp", "device.hpp", "codec.hpp", "launch.hpp", "tile_kernels.hpp",
+                  "column_pass.hpp", "kernels_plain.hip", "kernels_tile14.hip",
+                  "kernels_tile15.hip", "kernels_pass.hip", "kernels_column.hip",
+                  "kernels_column8.hip", "kernels_column8m.hip")
+
+
 def kernel_source_hash() -> str:
-    """sha256[:16] over the library's kernel sources (names and contents)."""
-    import glob
+    """sha256[:16] over the single-array sort's kernel sources (names and
+    contents)."""
     import hashlib
     h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(ROOT, "paper_1506_01446_amd", "csrc", "*"))):
-        h.update(os.path.basename(f).encode())
-        with open(f, "rb") as fh:
+    for name in sorted(KERNEL_SOURCES):
+        h.update(name.encode())
+        with open(os.path.join(ROOT, "paper_1506_01446_amd", "csrc", name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
