@@ -505,7 +505,7 @@ def main():
                                    "(seeded SplitMix64), ascending, device-resident; "
                                    "plus n=10,000,000 in extra",
                        "n": n, "plan": {"kind": "optimized",
-                                        "tile_log2": args.tile or B.bitonic_get_tuning_value("tile_log2"),
+                                        "tile_log2": B.bitonic_plan_tile_log2(n, plan),
                                         "fuse": args.fuse or B.bitonic_get_tuning_value("fuse")},
                        "passes": passes, "parallelism": "single GPU"},
             "roofline": roofline, "cpu_baseline": cpu, "extra": extra}

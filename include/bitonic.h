@@ -192,7 +192,8 @@ typedef struct bitonic_plan {
   int kind;                /* enum bitonic_plan_kind */
   int tile_log2;           /* keys per on-chip tile = 2^tile_log2, 11..15 for
                               the optimized plan, 1..13 for semi (0 = library
-                              choice) */
+                              choice: by n for the optimized plan, see
+                              bitonic_plan_tile_log2; 12 for semi) */
   int fuse;                /* max long-stride steps per HBM pass, 1..8
                               (0 = library choice, 8); at most 7 are used
                               when n is not a power of two */
@@ -213,6 +214,14 @@ typedef struct bitonic_plan {
  */
 int bitonic_sort_wide_plan(void* keys, int32_t* values, int64_t n, int key_type, int ascending,
                            const bitonic_plan* plan, void* stream);
+
+/*
+ * The tile size (log2 keys) the 4-byte sort of n keys uses under `plan`
+ * (NULL = BITONIC_PLAN_AUTO): the plan's or the tuned value if set, else the
+ * library's choice by n -- 2^12 keys for n <= 2^16, 2^13 for n <= 2^20, 2^14
+ * above (measured on MI355X).  0 for the Basic plan, -1 for a bad plan or n.
+ */
+int bitonic_plan_tile_log2(int64_t n, const bitonic_plan* plan);
 
 /* Launches of an 8-byte sort of n elements under `plan` (-1: bad plan or n). */
 int64_t bitonic_wide_plan_passes(int64_t n, const bitonic_plan* plan);
@@ -289,8 +298,8 @@ int bitonic_sort_plan_launches_i32(int32_t* keys, int64_t n, int ascending,
  * Tuning.  bitonic_set_tuning(tile_log2, fuse, merge_blocks_per_cu) changes
  * the library's default plan for BITONIC_PLAN_AUTO (values as in
  * bitonic_plan; 0 keeps the current value).  bitonic_set_tuning_value sets
- * one value by name: "tile_log2", "fuse", "merge_blocks_per_cu" (as in
- * bitonic_plan), "seg_blocks_per_cu" (1..16, workgroups per compute unit of
+ * one value by name: "tile_log2" (0 restores the choice by n), "fuse",
+ * "merge_blocks_per_cu" (as in bitonic_plan), "seg_blocks_per_cu" (1..16, workgroups per compute unit of
  * the persistent small-segment kernel), "wide_tile_log2" (11..13) or
  * "wide_fuse" (1..6) (the 8-byte sorts' plan); bitonic_get_tuning_value
  * reads one.

@@ -83,6 +83,7 @@ def load() -> ctypes.CDLL:
                                     ctypes.POINTER(bitonic_plan), vp], ctypes.c_int),
         "bitonic_wide_plan_passes": ([ctypes.c_int64, ctypes.POINTER(bitonic_plan)],
                                      ctypes.c_int64),
+        "bitonic_plan_tile_log2": ([ctypes.c_int64, ctypes.POINTER(bitonic_plan)], ctypes.c_int),
         "bitonic_sort_segmented_keys": ([vp, vp, ctypes.c_int64, ctypes.c_int64, ctypes.c_int,
                                          ctypes.c_int, vp], ctypes.c_int),
         "bitonic_plan_describe": ([ctypes.c_int64, ctypes.POINTER(bitonic_plan), vp, vp,
@@ -319,6 +320,11 @@ def bitonic_sort_segmented_i32(keys, offsets, ascending: bool = True, stream=Non
                load().bitonic_sort_segmented_bounded_i32(kp, op, nseg, int(max_seg_len),
                                                          int(bool(ascending)),
                                                          _stream(stream)))
+
+
+def bitonic_plan_tile_log2(n: int, plan=None) -> int:
+    p = _plan(plan)
+    return int(load().bitonic_plan_tile_log2(int(n), _plan_ref(p)))
 
 
 def bitonic_plan_passes(n: int, plan=None) -> int:

@@ -23,7 +23,7 @@
 
 namespace bitonic {
 
-static std::atomic<int> g_tile_log2{14};
+static std::atomic<int> g_tile_log2{0};  // 0: by n (default_tile_log2)
 static std::atomic<int> g_fuse{8};
 static std::atomic<int> g_merge_bpc{2};  // 0: one tile per workgroup
 static std::atomic<int> g_wide_tile_log2{12};  // 8-byte sorts
@@ -38,7 +38,16 @@ struct Resolved {
   uint32_t merge_blocks;  // merge_bpc x compute units (set when enqueueing)
 };
 
-static int resolve(const bitonic_plan* plan, Resolved* r) {
+// The library's tile size for n keys (measured on MI355X: below 2^21 keys
+// smaller tiles give more workgroups than the 256 CUs need, above it the
+// larger tile's fewer launches win).
+static int default_tile_log2(int64_t n) {
+  int k = 0;
+  while ((int64_t(1) << k) < n) ++k;
+  return k <= 16 ? 12 : (k <= 20 ? 13 : 14);
+}
+
+static int resolve(const bitonic_plan* plan, int64_t n, Resolved* r) {
   r->kind = BITONIC_PLAN_OPTIMIZED;
   r->tile = g_tile_log2.load();
   r->fuse = g_fuse.load();
@@ -57,6 +66,7 @@ static int resolve(const bitonic_plan* plan, Resolved* r) {
     if (!plan || !plan->tile_log2) r->tile = 12;
     if (r->tile < 1 || r->tile > kLdsNetworkMaxLog2) return BITONIC_EINVAL;
   }
+  if (r->kind == BITONIC_PLAN_OPTIMIZED && r->tile == 0) r->tile = default_tile_log2(n);
   if (r->kind == BITONIC_PLAN_OPTIMIZED && !tile_log2_supported(r->tile)) return BITONIC_EINVAL;
   if (r->fuse < 1 || r->fuse > kFuseMax) return BITONIC_EINVAL;
   return BITONIC_OK;
@@ -448,7 +458,7 @@ int bitonic_sort_plan_i32(int32_t* keys, int64_t n, int ascending, const bitonic
   int rc = check_sort_args(keys, n);
   if (rc) return rc;
   Resolved r;
-  rc = resolve(plan, &r);
+  rc = resolve(plan, n, &r);
   if (rc) return rc;
   if (n <= 1) return BITONIC_OK;
   fit_alignment(keys, &r);
@@ -469,7 +479,7 @@ int bitonic_sort_keys(void* keys, int64_t n, int key_type, int ascending, void* 
   int rc = check_sort_args(k, n);
   if (rc) return rc;
   Resolved r;
-  rc = resolve(nullptr, &r);
+  rc = resolve(nullptr, n, &r);
   if (rc) return rc;
   if (n <= 1) return BITONIC_OK;
   fit_alignment(k, &r);
@@ -487,7 +497,7 @@ int bitonic_network_phases_i32(int32_t* keys, int64_t n, int ascending, int last
   if (rc) return rc;
   if (last_phase < 1) return BITONIC_EINVAL;
   Resolved r;
-  rc = resolve(plan, &r);
+  rc = resolve(plan, n, &r);
   if (rc) return rc;
   if (n <= 1) return BITONIC_OK;
   fit_alignment(keys, &r);
@@ -522,10 +532,17 @@ int64_t bitonic_wide_plan_passes(int64_t n, const bitonic_plan* plan) {
   return enqueue_wide(nullptr, nullptr, nullptr, (uint32_t)n, Codec64{0, 0}, L, F, nullptr, true);
 }
 
+int bitonic_plan_tile_log2(int64_t n, const bitonic_plan* plan) {
+  if (n < 0 || n > (int64_t(1) << 31)) return -1;
+  Resolved r;
+  if (resolve(plan, n, &r)) return -1;
+  return r.kind == BITONIC_PLAN_BASIC ? 0 : r.tile;
+}
+
 int64_t bitonic_plan_passes(int64_t n, const bitonic_plan* plan) {
   if (n < 0 || n > (int64_t(1) << 31)) return -1;
   Resolved r;
-  if (resolve(plan, &r)) return -1;
+  if (resolve(plan, n, &r)) return -1;
   if (n <= 1) return 0;
   return enqueue_plain(nullptr, (uint32_t)n, 64, Codec{0, 0}, r, nullptr, true);
 }
@@ -534,7 +551,7 @@ int64_t bitonic_plan_describe(int64_t n, const bitonic_plan* plan, int32_t* kind
                               int32_t* fuse, int64_t cap) {
   if (n < 0 || n > (int64_t(1) << 31) || cap < 0) return -1;
   Resolved r;
-  if (resolve(plan, &r)) return -1;
+  if (resolve(plan, n, &r)) return -1;
   if (n <= 1) return 0;
   Observer obs;
   obs.kinds = kinds;
@@ -550,7 +567,7 @@ int bitonic_sort_plan_events_i32(int32_t* keys, int64_t n, int ascending,
   if (rc) return rc;
   if (nevents < 0 || (nevents > 0 && events == nullptr)) return BITONIC_EINVAL;
   Resolved r;
-  rc = resolve(plan, &r);
+  rc = resolve(plan, n, &r);
   if (rc) return rc;
   if (n <= 1) return BITONIC_OK;
   fit_alignment(keys, &r);
@@ -571,7 +588,7 @@ int bitonic_sort_plan_launches_i32(int32_t* keys, int64_t n, int ascending,
   if (rc) return rc;
   if (first < 0 || count < 0) return BITONIC_EINVAL;
   Resolved r;
-  rc = resolve(plan, &r);
+  rc = resolve(plan, n, &r);
   if (rc) return rc;
   if (n <= 1 || count == 0) return BITONIC_OK;
   fit_alignment(keys, &r);
@@ -643,7 +660,13 @@ int bitonic_set_tuning(int tile_log2, int fuse, int merge_blocks_per_cu) {
 
 int bitonic_set_tuning_value(const char* key, int value) {
   if (!key) return BITONIC_EINVAL;
-  if (!std::strcmp(key, "tile_log2")) return bitonic_set_tuning(value, 0, 0);
+  if (!std::strcmp(key, "tile_log2")) {
+    if (value == 0) {  // back to the library's choice by n
+      g_tile_log2.store(0);
+      return BITONIC_OK;
+    }
+    return bitonic_set_tuning(value, 0, 0);
+  }
   if (!std::strcmp(key, "fuse")) return value ? bitonic_set_tuning(0, value, 0) : BITONIC_EINVAL;
   if (!std::strcmp(key, "merge_blocks_per_cu"))
     return value ? bitonic_set_tuning(0, 0, value) : BITONIC_EINVAL;
@@ -699,7 +722,7 @@ int bitonic_graph_capture_sort_i32(bitonic_graph** out, int32_t* keys, int64_t n
   int rc = check_sort_args(keys, n);
   if (rc) return rc;
   Resolved r;
-  rc = resolve(plan, &r);
+  rc = resolve(plan, n, &r);
   if (rc) return rc;
   fit_alignment(keys, &r);
   rc = bind_device(&r);

@@ -138,6 +138,26 @@ def test_headline_pass_count(lib):
     assert B.bitonic_plan_passes(-1) == -1
 
 
+def test_default_tile_by_n(lib):
+    """The library's tile choice (measured: smaller tiles below 2^21 keys)."""
+    saved = B.bitonic_get_tuning_value("tile_log2")
+    B.bitonic_set_tuning_value("tile_log2", 0)
+    try:
+        for k, t in ((2, 12), (16, 12), (17, 13), (20, 13), (21, 14), (24, 14), (31, 14)):
+            assert B.bitonic_plan_tile_log2(2**k) == t, k
+            assert B.bitonic_plan_tile_log2(2**k - 1 if k > 1 else 2) == t, k
+        assert B.bitonic_plan_tile_log2(2**24, ("optimized", 11, 4)) == 11
+        assert B.bitonic_plan_tile_log2(2**24, ("semi",)) == 12
+        assert B.bitonic_plan_tile_log2(2**24, ("basic",)) == 0
+        assert B.bitonic_plan_passes(2**16) == _closed_form_optimized(16, 12, 8)
+        B.bitonic_set_tuning_value("tile_log2", 13)
+        assert B.bitonic_plan_tile_log2(2**24) == 13 and B.bitonic_plan_tile_log2(2**12) == 13
+        B.bitonic_set_tuning_value("tile_log2", 0)
+        assert B.bitonic_plan_tile_log2(2**24) == 14
+    finally:
+        B.bitonic_set_tuning_value("tile_log2", saved)
+
+
 def test_tuning_values_round_trip(lib, tmp_path):
     from paper_1506_01446_amd import autotune
     saved = {k: B.bitonic_get_tuning_value(k) for k in
