@@ -170,6 +170,24 @@ int bitonic_sort_segmented_keys(void* keys, const int64_t* offsets, int64_t nseg
                                 void* stream);
 
 /*
+ * Segmented sort of (key, value) pairs: every segment of the CSR table is
+ * sorted as bitonic_sort_pairs sorts one array (by key in the requested
+ * direction, equal keys by value ascending as int32; with values 0..len-1 per
+ * segment, a stable per-segment argsort), in the batched launch sequence of
+ * bitonic_sort_segmented_i32 on 8-byte elements.
+ *   keys, values  device pointers to the 4-byte keys (key_type
+ *                 BITONIC_KEY_I32, U32 or F32) and the int32 values, both
+ *                 indexed by the offsets, 4-byte aligned, not overlapping
+ *   offsets, nseg, max_seg_len, ascending, stream  as for
+ *                 bitonic_sort_segmented_keys
+ * Returns as bitonic_sort_segmented_keys; BITONIC_EINVAL also for values
+ * NULL with nseg > 0.
+ */
+int bitonic_sort_segmented_pairs(void* keys, int32_t* values, const int64_t* offsets,
+                                 int64_t nseg, int64_t max_seg_len, int key_type,
+                                 int ascending, void* stream);
+
+/*
  * Plans.  A plan fixes how the k(k+1)/2 steps of the network map onto
  * kernel launches; every plan gives the same sorted keys.
  *   BITONIC_PLAN_BASIC      one launch per step, one compare-exchange per

@@ -84,6 +84,8 @@ def load() -> ctypes.CDLL:
         "bitonic_wide_plan_passes": ([ctypes.c_int64, ctypes.POINTER(bitonic_plan)],
                                      ctypes.c_int64),
         "bitonic_plan_tile_log2": ([ctypes.c_int64, ctypes.POINTER(bitonic_plan)], ctypes.c_int),
+        "bitonic_sort_segmented_pairs": ([vp, vp, vp, ctypes.c_int64, ctypes.c_int64, ctypes.c_int,
+                                          ctypes.c_int, vp], ctypes.c_int),
         "bitonic_sort_segmented_keys": ([vp, vp, ctypes.c_int64, ctypes.c_int64, ctypes.c_int,
                                          ctypes.c_int, vp], ctypes.c_int),
         "bitonic_plan_describe": ([ctypes.c_int64, ctypes.POINTER(bitonic_plan), vp, vp,
@@ -274,6 +276,19 @@ def bitonic_sort_wide_plan(keys, values=None, ascending: bool = True, key_type=N
 def bitonic_wide_plan_passes(n: int, plan=None) -> int:
     p = _plan(plan)
     return int(load().bitonic_wide_plan_passes(int(n), _plan_ref(p)))
+
+
+def bitonic_sort_segmented_pairs(keys, values, offsets, ascending: bool = True, key_type=None,
+                                 max_seg_len: int | None = None, stream=None) -> None:
+    """Sort (key, value) pairs per CSR segment: by key, equal keys by value
+    (values 0..len-1 per segment give a stable per-segment argsort)."""
+    kp, vptr = _pair_ptrs(keys, values)
+    op = _keys_ptr(offsets, "int64")
+    nseg = max(offsets.numel() - 1, 0)
+    _check("bitonic_sort_segmented_pairs",
+           load().bitonic_sort_segmented_pairs(kp, vptr, op, nseg, int(max_seg_len or 0),
+                                               _key_type(keys, key_type), int(bool(ascending)),
+                                               _stream(stream)))
 
 
 def bitonic_sort_segmented_keys(keys, offsets, ascending: bool = True, key_type=None,

@@ -277,18 +277,17 @@ static int bind_device(Resolved* r) {
 
 // The launch sequence of one segmented sort (see kernels_segmented.hip) on
 // the given scratch buffer (seg_scratch_bytes(nseg) bytes).
-static void enqueue_segmented(int32_t* keys, const int64_t* offsets, int64_t nseg,
-                              int64_t max_seg_len, Codec flip, void* scratch, int cus,
-                              hipStream_t st) {
+static void enqueue_segmented(const SegData& d, const int64_t* offsets, int64_t nseg,
+                              int64_t max_seg_len, void* scratch, int cus, hipStream_t st) {
   const SegScratch sc = seg_scratch_carve(scratch, nseg);
   launch_seg_prep(offsets, nseg, sc, st);
   const int64_t slots = (int64_t)cus * g_seg_bpc.load();
   const int small_grid = (int)(slots < nseg ? slots : nseg);
-  launch_seg_small(keys, offsets, sc, flip, small_grid, st);
+  launch_seg_small(d, offsets, sc, small_grid, st);
   const int M = ceil_log2(max_seg_len);
   if (M <= 13) return;
   const int grid = cus * 4;
-  launch_seg_tiles(false, keys, offsets, sc, 14, flip, grid, st);
+  launch_seg_tiles(false, d, offsets, sc, 14, grid, st);
   const int fuse = g_fuse.load() < kSegFuseMax ? g_fuse.load() : kSegFuseMax;
   for (int p = 14; p <= M; ++p) {
     const int nb = p - 13;
@@ -298,10 +297,10 @@ static void enqueue_segmented(int32_t* keys, const int64_t* offsets, int64_t nse
       const int left = top - 13 + 1;
       const int f = (left + (npass - i) - 1) / (npass - i);
       const int q = top - f + 1;
-      launch_seg_pass(f, i == 0, keys, offsets, sc, p, q, flip, grid, st);
+      launch_seg_pass(f, i == 0, d, offsets, sc, p, q, grid, st);
       top = q - 1;
     }
-    launch_seg_tiles(true, keys, offsets, sc, p, flip, grid, st);
+    launch_seg_tiles(true, d, offsets, sc, p, grid, st);
   }
 }
 
@@ -608,8 +607,9 @@ int bitonic_sort_segmented_bounded_i32(int32_t* keys, const int64_t* offsets, in
                                      stream);
 }
 
-int bitonic_sort_segmented_keys(void* keys_v, const int64_t* offsets, int64_t nseg,
-                                int64_t max_seg_len, int key_type, int ascending, void* stream) {
+// Segmented sort of 4-byte keys (values == nullptr) or of (key, value) pairs.
+static int sort_segmented(void* keys_v, int32_t* values, const int64_t* offsets, int64_t nseg,
+                          int64_t max_seg_len, int key_type, int ascending, void* stream) {
   int32_t* keys = static_cast<int32_t*>(keys_v);
   if (key_type < BITONIC_KEY_I32 || key_type > BITONIC_KEY_F32) return BITONIC_EINVAL;
   if (nseg < 0 || max_seg_len < 0) return BITONIC_EINVAL;
@@ -617,6 +617,9 @@ int bitonic_sort_segmented_keys(void* keys_v, const int64_t* offsets, int64_t ns
   if (max_seg_len > (int64_t(1) << 31)) return BITONIC_EUNSUPPORTED;
   if (nseg == 0) return BITONIC_OK;
   if (keys == nullptr || offsets == nullptr) return BITONIC_EINVAL;
+  if ((reinterpret_cast<uintptr_t>(keys) & 3u) != 0 ||
+      (reinterpret_cast<uintptr_t>(values) & 3u) != 0)
+    return BITONIC_EINVAL;
   hipStream_t st = (hipStream_t)stream;
   int dev = 0;
   int rc = current_device(&dev);
@@ -637,9 +640,22 @@ int bitonic_sort_segmented_keys(void* keys_v, const int64_t* offsets, int64_t ns
   rc = stream_scratch(dev, st, seg_scratch_bytes(nseg), &base);
   if (rc) return rc;
   (void)hipGetLastError();
-  enqueue_segmented(keys, offsets, nseg, max_seg_len, make_codec(key_type, ascending != 0), base,
-                    device_cus(dev), st);
+  const SegData d{keys, values, make_codec(key_type, ascending != 0),
+                  make_pair_codec(key_type, ascending != 0)};
+  enqueue_segmented(d, offsets, nseg, max_seg_len, base, device_cus(dev), st);
   return finish_launches();
+}
+
+int bitonic_sort_segmented_keys(void* keys, const int64_t* offsets, int64_t nseg,
+                                int64_t max_seg_len, int key_type, int ascending, void* stream) {
+  return sort_segmented(keys, nullptr, offsets, nseg, max_seg_len, key_type, ascending, stream);
+}
+
+int bitonic_sort_segmented_pairs(void* keys, int32_t* values, const int64_t* offsets,
+                                 int64_t nseg, int64_t max_seg_len, int key_type, int ascending,
+                                 void* stream) {
+  if (nseg > 0 && values == nullptr) return BITONIC_EINVAL;
+  return sort_segmented(keys, values, offsets, nseg, max_seg_len, key_type, ascending, stream);
 }
 
 int bitonic_sort_segmented_i32(int32_t* keys, const int64_t* offsets, int64_t nseg,
@@ -747,8 +763,10 @@ int bitonic_graph_capture_segmented_i32(bitonic_graph** out, int32_t* keys,
   if (nseg > 0 && hipMalloc(&scratch, seg_scratch_bytes(nseg)) != hipSuccess) return BITONIC_ENOMEM;
   const int cus = device_cus(dev);
   rc = capture_graph(out, scratch, [&](hipStream_t cs) {
-    if (nseg > 0)
-      enqueue_segmented(keys, offsets, nseg, max_seg_len, make_codec(BITONIC_KEY_I32, ascending), scratch, cus, cs);
+    if (nseg > 0) {
+      const SegData d{keys, nullptr, make_codec(BITONIC_KEY_I32, ascending != 0), Codec64{0, 0}};
+      enqueue_segmented(d, offsets, nseg, max_seg_len, scratch, cus, cs);
+    }
   });
   if (rc && scratch) (void)hipFree(scratch);
   return rc;

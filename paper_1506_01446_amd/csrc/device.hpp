@@ -68,9 +68,11 @@ struct Prog {
   static constexpr uint32_t LDSW = lds_words(L_);  // padded LDS words of a tile
   static constexpr bool VEC = KIND_ < 2;  // 16-byte vector global I/O allowed
   // Recompute each layout's thread base at its regroup (fewer registers,
-  // more ALU); used by the segment kernels, which run several programs, and
-  // by tiles of 2^14 keys, whose 512-thread workgroups need it to fit.
-  static constexpr bool LEAN = KIND_ >= 2 || L_ >= 14;
+  // more ALU); used by the segment kernels, which run several programs in
+  // one kernel.  (The single-array tile kernels keep the bases: 59 VGPRs
+  // for the 2^14-key sort, 114 for the 2^15-key merge loop, both within the
+  // 128 their workgroup sizes allow.)
+  static constexpr bool LEAN = KIND_ >= 2;
   static constexpr Program value = make_program(L_, R_LOG_, KIND_);
   static_assert(value.ngroups <= kMaxGroups, "program too long");
 };

@@ -54,15 +54,23 @@ inline SegScratch seg_scratch_carve(void* base, int64_t nseg) {
   return s;
 }
 
+// The data of one segmented sort: 4-byte keys (values == nullptr, codec
+// cd), or (key, value) pairs moving as 8-byte elements (codec cd64).
+struct SegData {
+  int32_t* keys;
+  int32_t* values;
+  Codec cd;
+  Codec64 cd64;
+};
+
 void launch_seg_prep(const int64_t* offsets, int64_t nseg, const SegScratch& sc, hipStream_t st);
-void launch_seg_small(int32_t* keys, const int64_t* offsets, const SegScratch& sc, Codec cd,
-                      int grid, hipStream_t st);
+void launch_seg_small(const SegData& d, const int64_t* offsets, const SegScratch& sc, int grid,
+                      hipStream_t st);
 // Tile sort (merge == false) or tile merge of the big segments of class >= cls_min.
-void launch_seg_tiles(bool merge, int32_t* keys, const int64_t* offsets, const SegScratch& sc,
-                      int cls_min, Codec cd, int grid, hipStream_t st);
+void launch_seg_tiles(bool merge, const SegData& d, const int64_t* offsets, const SegScratch& sc,
+                      int cls_min, int grid, hipStream_t st);
 // f fused steps on bits q+f-1 .. q of the big segments of class >= cls.
-void launch_seg_pass(int f, bool mirror, int32_t* keys, const int64_t* offsets,
-                     const SegScratch& sc, int cls, int q, Codec cd, int grid,
-                     hipStream_t st);
+void launch_seg_pass(int f, bool mirror, const SegData& d, const int64_t* offsets,
+                     const SegScratch& sc, int cls, int q, int grid, hipStream_t st);
 
 }  // namespace bitonic

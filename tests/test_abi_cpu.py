@@ -78,6 +78,12 @@ def test_wide_argument_errors_are_synchronous(lib):
                 B.bitonic_plan(3, 10, 0, 0), B.bitonic_plan(3, 12, 7, 0)):
         assert lib.bitonic_sort_wide_plan(None, None, 0, I64, 1, ctypes.byref(bad), None) == -1
         assert lib.bitonic_wide_plan_passes(2**20, ctypes.byref(bad)) == -1
+    assert lib.bitonic_sort_segmented_pairs(None, None, None, 0, 0, I32, 1, None) == 0
+    assert lib.bitonic_sort_segmented_pairs(None, None, None, -1, 0, I32, 1, None) == -1
+    assert lib.bitonic_sort_segmented_pairs(4, None, 8, 3, 0, I32, 1, None) == -1   # no values
+    assert lib.bitonic_sort_segmented_pairs(4, 6, 8, 3, 0, I32, 1, None) == -1      # misaligned
+    assert lib.bitonic_sort_segmented_pairs(4, 8, 8, 3, 0, I64, 1, None) == -1      # 8-byte key
+    assert lib.bitonic_sort_segmented_pairs(4, 8, 8, 3, -1, I32, 1, None) == -1
     assert lib.bitonic_set_tuning_value(b"wide_tile_log2", 14) == -1
     assert lib.bitonic_set_tuning_value(b"wide_fuse", 0) == -1
 

@@ -233,3 +233,69 @@ def test_pairs_maximum_size():
         assert bool(((k1 > k0) | ((k1 == k0) & (v1 > v0))).all().item()), a
     del k, v
     torch.cuda.empty_cache()
+
+
+# -- segmented pairs -----------------------------------------------------------------
+
+def _seg_pairs_gpu(keys, values, off, asc, key_type="int32", max_seg_len=None):
+    k = torch.from_numpy(np.ascontiguousarray(keys).view(np.int32).copy()).cuda()
+    v = torch.from_numpy(np.ascontiguousarray(values, dtype=np.int32).copy()).cuda()
+    o = torch.from_numpy(np.ascontiguousarray(off, dtype=np.int64)).cuda()
+    B.bitonic_sort_segmented_pairs(k, v, o, asc, key_type, max_seg_len=max_seg_len)
+    torch.cuda.synchronize()
+    return k.cpu().numpy(), v.cpu().numpy()
+
+
+def _seg_pairs_oracle(keys, values, off, asc, kt=O.KEY_I32):
+    wk, wv = np.array(keys, copy=True), np.array(values, copy=True)
+    for a, b in zip(off[:-1], off[1:]):
+        if b > a:
+            wk[a:b], wv[a:b] = O.sort_pairs(keys[a:b], values[a:b], kt, asc)
+    return wk, wv
+
+
+def test_segmented_pairs_edge_lengths():
+    """One call over segments of every edge length (empty, one key, tile and
+    class boundaries, big classes sorted phase by phase) at an unaligned
+    start; keys with few distinct values, so ties fall to the values."""
+    lens = [0, 1, 2, 3, 5, 31, 32, 33, 255, 256, 257, 2047, 2049, 8191, 8192, 8193,
+            16385, 70001, (1 << 17) + 3, 0, 7]
+    off = np.concatenate([[3], 3 + np.cumsum(lens)]).astype(np.int64)
+    n = int(off[-1]) + 5
+    keys = (W.uniform_i32(W.SEED_BASE + 120, n).astype(np.int64) % 61 - 30).astype(np.int32)
+    values = W.uniform_i32(W.SEED_BASE + 121, n)
+    for asc in (True, False):
+        for bound in (None, max(lens)):
+            print(f"[case] segmented pairs edge asc={asc} bound={bound}", flush=True)
+            gk, gv = _seg_pairs_gpu(keys, values, off, asc, max_seg_len=bound)
+            wk, wv = _seg_pairs_oracle(keys, values, off, asc)
+            assert np.array_equal(gk, wk) and np.array_equal(gv, wv), (asc, bound)
+
+
+def test_segmented_pairs_argsort_workload():
+    """The 8192-segment batched workload as a per-segment argsort: values
+    0..len-1 in every segment come out as numpy's stable argsort."""
+    keys, off = W.batched_workload()
+    idx = np.concatenate([np.arange(b - a, dtype=np.int32) for a, b in zip(off[:-1], off[1:])])
+    gk, gv = _seg_pairs_gpu(keys, idx, off, True)
+    for s, (a, b) in enumerate(zip(off[:-1], off[1:])):
+        want = np.argsort(keys[a:b], kind="stable")
+        assert np.array_equal(gv[a:b], want), s
+        assert np.array_equal(gk[a:b], keys[a:b][want]), s
+
+
+@pytest.mark.parametrize("key_type", ["uint32", "float32"])
+def test_segmented_pairs_other_key_types(key_type):
+    kt = O.KEY_U32 if key_type == "uint32" else O.KEY_F32
+    lens = [1, 100, 4096, 9000, 40000]
+    off = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    n = int(off[-1])
+    bits = (W.uniform_i32(W.SEED_BASE + 130, n).astype(np.int64) % 500).astype(np.uint32)
+    bits[::5] = W.uniform_i32(W.SEED_BASE + 131, n)[::5].view(np.uint32)
+    values = W.uniform_i32(W.SEED_BASE + 132, n)
+    dt = np.uint32 if key_type == "uint32" else np.float32
+    for asc in (True, False):
+        gk, gv = _seg_pairs_gpu(bits, values, off, asc, key_type)
+        wk, wv = _seg_pairs_oracle(bits.view(dt), values, off, asc, kt)
+        assert np.array_equal(gk.view(np.uint32), wk.view(np.uint32)), (key_type, asc)
+        assert np.array_equal(gv, wv), (key_type, asc)
