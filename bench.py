@@ -275,6 +275,39 @@ def wide_sorts(torch, B, W, n=1 << 24, reps=10):
     return out
 
 
+def batched_pairs(torch, B, W, reps=7):
+    """The 8192-segment batched workload as a per-segment argsort: (key,
+    index) pairs sorted per segment by bitonic_sort_segmented_pairs."""
+    import numpy as np
+    keys, off = W.batched_workload()
+    idx = np.concatenate([np.arange(b - a, dtype=np.int32) for a, b in zip(off[:-1], off[1:])])
+    kt = torch.from_numpy(keys).cuda()
+    vt = torch.from_numpy(idx).cuda()
+    ot = torch.from_numpy(off).cuda()
+    mx = int((off[1:] - off[:-1]).max())
+    ev = B.HipEvents(2)
+    rt = ev.rt
+    rt.hipEventRecord.argtypes = [B.ctypes.c_void_p, B.ctypes.c_void_p]
+    stream = torch.cuda.current_stream().cuda_stream
+    times = []
+    for _ in range(reps + 1):
+        k, v = kt.clone(), vt.clone()
+        torch.cuda.synchronize()
+        rt.hipEventRecord(ev.ev[0], stream)
+        B.bitonic_sort_segmented_pairs(k, v, ot, True, max_seg_len=mx)
+        rt.hipEventRecord(ev.ev[1], stream)
+        torch.cuda.synchronize()
+        times.append(ev.elapsed_ms(0, 1))
+    ev.close()
+    times = sorted(times[1:])
+    med = times[len(times) // 2]
+    a, b = int(off[0]), int(off[1])
+    ok = bool(np.array_equal(v[a:b].cpu().numpy(), np.argsort(keys[a:b], kind="stable")))
+    return {"segments": len(off) - 1, "pairs": int(off[-1]), "median_ms": round(med, 4),
+            "gpairs_s": round(int(off[-1]) / (med * 1e-3) / 1e9, 3),
+            "first_segment_is_stable_argsort": ok}
+
+
 def cpu_network_context(n=1 << 20):
     """The oracle's scalar flip network (one thread) at a bounded size: the
     analogue of the paper's CPU bitonic-sort column, as context only."""
@@ -484,6 +517,8 @@ def main():
     if not args.no_batched:
         extra["batched"] = batched_vs_looped(torch, B, W)
         log(f"[bench] batched: {json.dumps(extra['batched'])}")
+        extra["batched_pairs"] = batched_pairs(torch, B, W)
+        log(f"[bench] batched pairs: {json.dumps(extra['batched_pairs'])}")
     if args.serve_seconds > 0:
         from paper_1506_01446_amd import serving
         extra["serving"] = serving.run_gpu(duration_s=args.serve_seconds)
