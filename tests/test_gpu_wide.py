@@ -2,7 +2,7 @@
 value) pairs, against the CPU oracle, bit for bit.
 
 Sizes span one to several tiles with ragged tails at every plan shape
-(tile 2^11..2^13 elements, 1..5 fused steps); full-size cases check the
+(tile 2^11..2^13 elements, 1..6 fused steps); full-size cases check the
 whole array against the oracle; the maximum size is checked by properties
 that hold at any size (order, an exact permutation check, sampled order
 statistics counted in the input).
