@@ -164,7 +164,9 @@ int bitonic_sort_segmented_bounded_i32(int32_t* keys, const int64_t* offsets,
                                        int ascending, void* stream);
 
 /* bitonic_sort_segmented_bounded_i32 for any key type (max_seg_len 0 =
- * unknown, as above). */
+ * unknown, as above): 4-byte keys need 4-byte alignment, 8-byte keys
+ * (BITONIC_KEY_I64, U64, F64) 8-byte alignment; BITONIC_EINVAL for an
+ * unknown key_type or a misaligned pointer. */
 int bitonic_sort_segmented_keys(void* keys, const int64_t* offsets, int64_t nseg,
                                 int64_t max_seg_len, int key_type, int ascending,
                                 void* stream);

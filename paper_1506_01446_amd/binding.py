@@ -293,6 +293,16 @@ def bitonic_sort_segmented_pairs(keys, values, offsets, ascending: bool = True, 
 
 def bitonic_sort_segmented_keys(keys, offsets, ascending: bool = True, key_type=None,
                                 max_seg_len: int = 0, stream=None) -> None:
+    """Per-segment sort of keys of any type: 4-byte (int32, uint32, float32)
+    or 8-byte (int64, uint64, float64), from the dtype or key_type."""
+    if keys.element_size() == 8:
+        kp, kt = _any64_ptr(keys), _key_type64(keys, key_type)
+        op = _keys_ptr(offsets, "int64")
+        _check("bitonic_sort_segmented_keys",
+               load().bitonic_sort_segmented_keys(kp, op, max(offsets.numel() - 1, 0),
+                                                  int(max_seg_len), kt, int(bool(ascending)),
+                                                  _stream(stream)))
+        return
     kp = _any32_ptr(keys)
     op = _keys_ptr(offsets, "int64")
     _check("bitonic_sort_segmented_keys",

@@ -607,17 +607,20 @@ int bitonic_sort_segmented_bounded_i32(int32_t* keys, const int64_t* offsets, in
                                      stream);
 }
 
-// Segmented sort of 4-byte keys (values == nullptr) or of (key, value) pairs.
+// Segmented sort of keys of any key type (values == nullptr) or of (key,
+// value) pairs with 4-byte keys.
 static int sort_segmented(void* keys_v, int32_t* values, const int64_t* offsets, int64_t nseg,
                           int64_t max_seg_len, int key_type, int ascending, void* stream) {
   int32_t* keys = static_cast<int32_t*>(keys_v);
-  if (key_type < BITONIC_KEY_I32 || key_type > BITONIC_KEY_F32) return BITONIC_EINVAL;
+  if (key_type < BITONIC_KEY_I32 || key_type > BITONIC_KEY_F64) return BITONIC_EINVAL;
+  const bool wide_keys = key_type >= BITONIC_KEY_I64;
+  if (wide_keys && values != nullptr) return BITONIC_EINVAL;
   if (nseg < 0 || max_seg_len < 0) return BITONIC_EINVAL;
   if (nseg >= (int64_t(1) << 31)) return BITONIC_EUNSUPPORTED;
   if (max_seg_len > (int64_t(1) << 31)) return BITONIC_EUNSUPPORTED;
   if (nseg == 0) return BITONIC_OK;
   if (keys == nullptr || offsets == nullptr) return BITONIC_EINVAL;
-  if ((reinterpret_cast<uintptr_t>(keys) & 3u) != 0 ||
+  if ((reinterpret_cast<uintptr_t>(keys) & (wide_keys ? 7u : 3u)) != 0 ||
       (reinterpret_cast<uintptr_t>(values) & 3u) != 0)
     return BITONIC_EINVAL;
   hipStream_t st = (hipStream_t)stream;
@@ -640,8 +643,16 @@ static int sort_segmented(void* keys_v, int32_t* values, const int64_t* offsets,
   rc = stream_scratch(dev, st, seg_scratch_bytes(nseg), &base);
   if (rc) return rc;
   (void)hipGetLastError();
-  const SegData d{keys, values, make_codec(key_type, ascending != 0),
-                  make_pair_codec(key_type, ascending != 0)};
+  SegData d{};
+  if (wide_keys) {
+    d.keys64 = static_cast<int64_t*>(keys_v);
+    d.cd64 = make_codec64(key_type, ascending != 0);
+  } else {
+    d.keys = keys;
+    d.values = values;
+    d.cd = make_codec(key_type, ascending != 0);
+    d.cd64 = make_pair_codec(key_type, ascending != 0);
+  }
   enqueue_segmented(d, offsets, nseg, max_seg_len, base, device_cus(dev), st);
   return finish_launches();
 }
@@ -654,6 +665,7 @@ int bitonic_sort_segmented_keys(void* keys, const int64_t* offsets, int64_t nseg
 int bitonic_sort_segmented_pairs(void* keys, int32_t* values, const int64_t* offsets,
                                  int64_t nseg, int64_t max_seg_len, int key_type, int ascending,
                                  void* stream) {
+  if (key_type < BITONIC_KEY_I32 || key_type > BITONIC_KEY_F32) return BITONIC_EINVAL;
   if (nseg > 0 && values == nullptr) return BITONIC_EINVAL;
   return sort_segmented(keys, values, offsets, nseg, max_seg_len, key_type, ascending, stream);
 }
@@ -764,7 +776,9 @@ int bitonic_graph_capture_segmented_i32(bitonic_graph** out, int32_t* keys,
   const int cus = device_cus(dev);
   rc = capture_graph(out, scratch, [&](hipStream_t cs) {
     if (nseg > 0) {
-      const SegData d{keys, nullptr, make_codec(BITONIC_KEY_I32, ascending != 0), Codec64{0, 0}};
+      SegData d{};
+      d.keys = keys;
+      d.cd = make_codec(BITONIC_KEY_I32, ascending != 0);
       enqueue_segmented(d, offsets, nseg, max_seg_len, scratch, cus, cs);
     }
   });

@@ -1,0 +1,279 @@
+// Kernel templates of the segmented sort (see kernels_segmented.hip), over a
+// storage type ST (column_pass.hpp): Keys32, Keys64 or Pairs.  Each storage
+// is instantiated in a file of its own (kernels_seg32.hip,
+// kernels_segpairs.hip, kernels_seg64.hip) so that they compile in parallel.
+#pragma once
+
+#include <type_traits>
+
+#include "column_pass.hpp"
+#include "device.hpp"
+#include "launch.hpp"
+#include "segmented.hpp"
+
+namespace bitonic {
+
+constexpr int kSegTileLog = 13;
+constexpr int kSegThreads = 256;
+
+__device__ __forceinline__ int ceil_log2_u64(uint64_t n) {
+  return n <= 1 ? 0 : 64 - __clzll(n - 1);
+}
+
+// Small classes 13, 12, ..., 6, and "<= 5" (index 8): segments per item.
+__device__ __forceinline__ int small_class_of_index(int i) { return 13 - i; }  // 5 for i == 8
+__device__ __forceinline__ uint32_t small_per_item(int cls) {
+  return cls <= 5 ? 256u : (256u >> (cls - 5));
+}
+
+// Storage ST of a segmented sort: Keys32 (4-byte keys, Codec) or Pairs
+// (key, value pairs as 8-byte elements, Codec64); every kernel maps keys into
+// the sorting domain as it loads them and back as it stores them.
+//
+// One tile of a storage in a scalar-I/O program (KIND 2 or 3), `valid` of its
+// elements real.  4-byte keys take the single-array sort's tile program.
+template <class PR, class ST, class CD>
+__device__ __forceinline__ void seg_tile_program(ST tile, uint32_t valid, CD cd,
+                                                 typename ST::E* lds, uint32_t tid) {
+  if constexpr (std::is_same_v<ST, Keys32>) {
+    tile_program<PR>(tile.k, valid, cd, lds, tid);
+  } else {
+    using E = typename ST::E;
+    constexpr int LAST = PR::value.ngroups - 1;
+    const bool full = valid >= (uint32_t)PR::T;
+    E x[PR::R];
+    {
+      constexpr Group gr = PR::value.g[0];
+      const uint32_t base = deposit<free_mask(gr, PR::L)>(tid);
+      if (full) {
+        static_for<0, PR::R>([&](auto J) { x[J] = cd.enc(tile.get(slot_index<PR, 0, J>(base))); });
+      } else {
+        static_for<0, PR::R>([&](auto J) {
+          const uint32_t i = slot_index<PR, 0, J>(base);
+          x[J] = i < valid ? cd.enc(tile.get(i)) : ST::kPadE;
+        });
+      }
+    }
+    run_from<PR, 0>(x, lds, tid);
+    {
+      if constexpr (PR::LEAN) asm volatile("" : "+v"(tid));
+      constexpr Group gr = PR::value.g[LAST];
+      const uint32_t base = deposit<free_mask(gr, PR::L)>(tid);
+      if (full) {
+        static_for<0, PR::R>([&](auto J) { tile.put(slot_index<PR, LAST, J>(base), cd.dec(x[J])); });
+      } else {
+        static_for<0, PR::R>([&](auto J) {
+          const uint32_t i = slot_index<PR, LAST, J>(base);
+          if (i < valid) tile.put(i, cd.dec(x[J]));
+        });
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// small segments
+
+constexpr uint32_t kSmallLdsWords = (kSegThreads << kTileRegLogSeg) / 32 * 33;
+
+// Not inlined: each class's program keeps its own register allocation
+// instead of the kernel carrying the union of all of them.
+template <int L, class ST, class CD>
+__device__ __attribute__((noinline)) void seg_small_item(ST keys,
+                                               const int64_t* __restrict__ offsets,
+                                               const uint32_t* __restrict__ ids, uint32_t first,
+                                               uint32_t count, CD cd, typename ST::E* lds) {
+  using PR = Prog<L, kTileRegLogSeg, 2>;
+  constexpr uint32_t NT = PR::NT;
+  static_assert((kSegThreads / NT) * PR::LDSW <= kSmallLdsWords, "padded tiles exceed LDS");
+  const uint32_t grp = threadIdx.x / NT;
+  const uint32_t ltid = threadIdx.x % NT;
+  ST p = keys;
+  uint32_t len = 0;
+  if (grp < count) {
+    const uint32_t s = ids[first + grp];
+    const int64_t off = offsets[s];
+    p = keys.at(off);
+    len = (uint32_t)(offsets[s + 1] - off);
+  }
+  seg_tile_program<PR>(p, len, cd, lds + grp * PR::LDSW, ltid);
+}
+
+template <class ST, class CD>
+__global__ __launch_bounds__(kSegThreads) void seg_small_kernel(
+    ST keys, const int64_t* __restrict__ offsets, SegMeta* __restrict__ meta,
+    const uint32_t* __restrict__ small_ids, CD cd) {
+  // room for 256 / 2^(m-5) padded tiles of 2^m elements, for every class m
+  __shared__ typename ST::E lds[kSmallLdsWords];
+  __shared__ uint32_t item_s;
+  const uint32_t total = meta->small_items;
+  for (;;) {
+    if (threadIdx.x == 0) item_s = atomicAdd(&meta->small_counter, 1u);
+    __syncthreads();
+    const uint32_t item = item_s;
+    __syncthreads();
+    if (item >= total) break;
+    int ci = 0;
+    while (ci + 1 < kSmallClasses && meta->item_prefix[ci + 1] <= item) ++ci;
+    const int cls = small_class_of_index(ci);
+    const uint32_t per = small_per_item(cls);
+    const uint32_t k = item - meta->item_prefix[ci];
+    const uint32_t first = meta->small_start[ci] + k * per;
+    const uint32_t left = meta->small_count[ci] - k * per;
+    const uint32_t count = left < per ? left : per;
+    switch (cls) {
+      case 13: seg_small_item<13>(keys, offsets, small_ids, first, count, cd, lds); break;
+      case 12: seg_small_item<12>(keys, offsets, small_ids, first, count, cd, lds); break;
+      case 11: seg_small_item<11>(keys, offsets, small_ids, first, count, cd, lds); break;
+      case 10: seg_small_item<10>(keys, offsets, small_ids, first, count, cd, lds); break;
+      case 9: seg_small_item<9>(keys, offsets, small_ids, first, count, cd, lds); break;
+      case 8: seg_small_item<8>(keys, offsets, small_ids, first, count, cd, lds); break;
+      case 7: seg_small_item<7>(keys, offsets, small_ids, first, count, cd, lds); break;
+      case 6: seg_small_item<6>(keys, offsets, small_ids, first, count, cd, lds); break;
+      default: seg_small_item<5>(keys, offsets, small_ids, first, count, cd, lds); break;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// big segments
+
+// Largest i in [0, cnt) with prefix[i] <= v (prefix nondecreasing, prefix[0] = 0).
+__device__ __forceinline__ uint32_t upper_index(const uint64_t* __restrict__ prefix, uint32_t cnt,
+                                                uint64_t v) {
+  uint32_t lo = 0, hi = cnt;  // answer in [lo, hi)
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (prefix[mid] <= v) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// Every 2^13-key tile of the big segments of class >= cls_min: sort
+// (KIND 2) or merge (KIND 3).
+template <int KIND, class ST, class CD>
+__global__ __launch_bounds__(kSegThreads) void seg_tile_kernel(
+    ST keys, const int64_t* __restrict__ offsets,
+    const SegMeta* __restrict__ meta, const uint32_t* __restrict__ big_ids,
+    const uint64_t* __restrict__ big_tiles, int cls_min, CD cd) {
+  using PR = Prog<kSegTileLog, kTileRegLogSeg, KIND>;
+  static_assert(PR::NT == kSegThreads, "one tile per workgroup");
+  __shared__ typename ST::E lds[PR::LDSW];
+  const uint32_t cnt = meta->big_ge[cls_min];
+  const uint64_t total = big_tiles[cnt];
+  for (uint64_t u = blockIdx.x; u < total; u += gridDim.x) {
+    // recompute the layouts' thread bases per tile instead of holding them
+    uint32_t tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    const uint32_t i = upper_index(big_tiles, cnt, u);
+    const uint64_t tile = u - big_tiles[i];
+    const uint32_t s = big_ids[i];
+    const int64_t off = offsets[s];
+    const uint64_t len = (uint64_t)(offsets[s + 1] - off);
+    const uint64_t t0 = tile << kSegTileLog;
+    const uint64_t left = len - t0;
+    const uint32_t valid = left < (uint64_t)PR::T ? (uint32_t)left : (uint32_t)PR::T;
+    seg_tile_program<PR>(keys.at(off + t0), valid, cd, lds, tid);
+    __syncthreads();  // LDS reuse by the next tile
+  }
+}
+
+// Segment-local index of register slot (RHO, J) of a pass unit: row RHO of
+// the block at blk, column c0 + threadIdx.x + 256 J (mirrored rows: the
+// mirror image inside the block).
+template <int F, bool MIRROR, int RHO, int J>
+__device__ __forceinline__ uint32_t seg_pass_index(uint32_t blk, uint32_t c0, int q) {
+  constexpr int ROWS = 1 << F;
+  constexpr int TOP = ROWS >> 1;
+  const uint32_t col = c0 + threadIdx.x + 256u * (uint32_t)J;
+  if constexpr (MIRROR && (RHO & TOP))
+    return blk + ((uint32_t)((ROWS - 1) ^ (RHO & (TOP - 1))) << q) + (((1u << q) - 1u) - col);
+  else
+    return blk + ((uint32_t)RHO << q) + col;
+}
+
+// F fused long-stride steps (bits q+F-1 .. q) over the big segments of class
+// >= cls.  A workgroup unit is 1024 consecutive columns x 2^F rows of one
+// 2^(q+F)-key block of one segment; thread t holds columns c0 + t + 256 j
+// (j = 0..3), so every load and store of a wave is 256 consecutive bytes.
+template <int F, bool MIRROR, class ST, class CD>
+__global__ __launch_bounds__(kSegThreads) void seg_pass_kernel(
+    ST keys, const int64_t* __restrict__ offsets,
+    const SegMeta* __restrict__ meta, const uint32_t* __restrict__ big_ids,
+    const uint64_t* __restrict__ big_keys, int cls, int q, CD cd) {
+  constexpr int ROWS = 1 << F;
+  constexpr int TOP = ROWS >> 1;
+  constexpr int UNIT_LOG = 10 + F;  // keys per unit = 1024 columns x 2^F rows
+  const uint32_t cnt = meta->big_ge[cls];
+  const uint64_t total = big_keys[cnt] >> UNIT_LOG;
+  for (uint64_t u = blockIdx.x; u < total; u += gridDim.x) {
+    const uint64_t key0 = u << UNIT_LOG;
+    const uint32_t i = upper_index(big_keys, cnt, key0);
+    const uint64_t lk = key0 - big_keys[i];  // unit's first key, segment-local
+    const uint32_t s = big_ids[i];
+    const int64_t off = offsets[s];
+    const uint32_t len = (uint32_t)(offsets[s + 1] - off);
+    const ST a = keys.at(off);
+    // unit -> block and column run: a block holds 2^q / 1024 units;
+    // segment-local indices fit 32 bits (segments hold < 2^31 keys)
+    const uint32_t lu = (uint32_t)(lk >> UNIT_LOG);
+    const int upb_log = q - 10;
+    const uint32_t blk = (lu >> upb_log) << (q + F);
+    const uint32_t c0 = (lu & ((1u << upb_log) - 1u)) << 10;
+    typename ST::E x[4 * ROWS];
+    static_for<0, ROWS>([&](auto RHO) {
+      static_for<0, 4>([&](auto J) {
+        const uint32_t idx = seg_pass_index<F, MIRROR, RHO, J>(blk, c0, q);
+        x[4 * RHO + J] = idx < len ? cd.enc(a.get(idx)) : ST::kPadE;
+      });
+    });
+    pass_steps<F, MIRROR>(x);
+    static_for<0, ROWS>([&](auto RHO) {
+      static_for<0, 4>([&](auto J) {
+        const uint32_t idx = seg_pass_index<F, MIRROR, RHO, J>(blk, c0, q);
+        if (idx < len) a.put(idx, cd.dec(x[4 * RHO + J]));
+      });
+    });
+  }
+}
+
+// ---------------------------------------------------------------------------
+// launch of one kernel of the sequence (SegLaunch) on a storage
+
+template <class ST, class CD>
+void seg_run(ST keys, CD cd, const SegLaunch& l, const int64_t* offsets, const SegScratch& sc,
+             hipStream_t st) {
+  switch (l.what) {
+    case SegLaunch::kSmall:
+      seg_small_kernel<<<l.grid, kSegThreads, 0, st>>>(keys, offsets, sc.meta, sc.small_ids, cd);
+      break;
+    case SegLaunch::kTileSort:
+      seg_tile_kernel<2><<<l.grid, kSegThreads, 0, st>>>(keys, offsets, sc.meta, sc.big_ids,
+                                                         sc.big_tiles, l.cls, cd);
+      break;
+    case SegLaunch::kTileMerge:
+      seg_tile_kernel<3><<<l.grid, kSegThreads, 0, st>>>(keys, offsets, sc.meta, sc.big_ids,
+                                                         sc.big_tiles, l.cls, cd);
+      break;
+    case SegLaunch::kPass: {
+#define BITONIC_SEG_PASS(F)                                                                     \
+  if (l.mirror)                                                                                 \
+    seg_pass_kernel<F, true><<<l.grid, kSegThreads, 0, st>>>(keys, offsets, sc.meta, sc.big_ids, \
+                                                             sc.big_keys, l.cls, l.q, cd);      \
+  else                                                                                          \
+    seg_pass_kernel<F, false><<<l.grid, kSegThreads, 0, st>>>(keys, offsets, sc.meta,           \
+                                                              sc.big_ids, sc.big_keys, l.cls,   \
+                                                              l.q, cd);
+      if (l.f == 1) { BITONIC_SEG_PASS(1) }
+      else if (l.f == 2) { BITONIC_SEG_PASS(2) }
+      else if (l.f == 3) { BITONIC_SEG_PASS(3) }
+#undef BITONIC_SEG_PASS
+      break;
+    }
+    default:
+      break;
+  }
+}
+
+}  // namespace bitonic

@@ -54,14 +54,37 @@ inline SegScratch seg_scratch_carve(void* base, int64_t nseg) {
   return s;
 }
 
-// The data of one segmented sort: 4-byte keys (values == nullptr, codec
-// cd), or (key, value) pairs moving as 8-byte elements (codec cd64).
+// The data of one segmented sort: 4-byte keys (keys, codec cd), (key,
+// value) pairs moving as 8-byte elements (keys and values, codec cd64), or
+// 8-byte keys (keys64, codec cd64).
 struct SegData {
   int32_t* keys;
   int32_t* values;
+  int64_t* keys64;
   Codec cd;
   Codec64 cd64;
 };
+
+// One launch of the sequence: the small-segment kernel, a big-segment tile
+// sort or merge of the segments of class >= cls, or a pass of f steps on
+// bits q+f-1 .. q of them.
+struct SegLaunch {
+  enum : int { kSmall = 0, kTileSort = 1, kTileMerge = 2, kPass = 3 };
+  int what;
+  int f;
+  bool mirror;
+  int cls;
+  int q;
+  int grid;
+};
+
+// Per storage type (kernels_seg32.hip, kernels_segpairs.hip, kernels_seg64.hip).
+void seg_run_keys32(const SegData& d, const SegLaunch& l, const int64_t* offsets,
+                    const SegScratch& sc, hipStream_t st);
+void seg_run_pairs(const SegData& d, const SegLaunch& l, const int64_t* offsets,
+                   const SegScratch& sc, hipStream_t st);
+void seg_run_keys64(const SegData& d, const SegLaunch& l, const int64_t* offsets,
+                    const SegScratch& sc, hipStream_t st);
 
 void launch_seg_prep(const int64_t* offsets, int64_t nseg, const SegScratch& sc, hipStream_t st);
 void launch_seg_small(const SegData& d, const int64_t* offsets, const SegScratch& sc, int grid,

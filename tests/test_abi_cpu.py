@@ -83,6 +83,8 @@ def test_wide_argument_errors_are_synchronous(lib):
     assert lib.bitonic_sort_segmented_pairs(4, None, 8, 3, 0, I32, 1, None) == -1   # no values
     assert lib.bitonic_sort_segmented_pairs(4, 6, 8, 3, 0, I32, 1, None) == -1      # misaligned
     assert lib.bitonic_sort_segmented_pairs(4, 8, 8, 3, 0, I64, 1, None) == -1      # 8-byte key
+    assert lib.bitonic_sort_segmented_keys(4, 8, 3, 0, I64, 1, None) == -1          # misaligned
+    assert lib.bitonic_sort_segmented_keys(8, 8, 3, 0, 6, 1, None) == -1            # no such type
     assert lib.bitonic_sort_segmented_pairs(4, 8, 8, 3, -1, I32, 1, None) == -1
     assert lib.bitonic_set_tuning_value(b"wide_tile_log2", 14) == -1
     assert lib.bitonic_set_tuning_value(b"wide_fuse", 0) == -1

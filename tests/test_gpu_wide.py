@@ -299,3 +299,27 @@ def test_segmented_pairs_other_key_types(key_type):
         wk, wv = _seg_pairs_oracle(bits.view(dt), values, off, asc, kt)
         assert np.array_equal(gk.view(np.uint32), wk.view(np.uint32)), (key_type, asc)
         assert np.array_equal(gv, wv), (key_type, asc)
+
+
+@pytest.mark.parametrize("key_type", ["int64", "uint64", "float64"])
+def test_segmented_8_byte_keys(key_type):
+    """Per-segment sorts of 8-byte keys (edge lengths, a big class, an
+    unaligned start), special values of the type included."""
+    kt = {"int64": O.KEY_I64, "uint64": O.KEY_U64, "float64": O.KEY_F64}[key_type]
+    dt = {"int64": np.int64, "uint64": np.uint64, "float64": np.float64}[key_type]
+    lens = [0, 1, 2, 3, 33, 257, 2049, 8191, 8193, 20001, 70001, 5]
+    off = np.concatenate([[1], 1 + np.cumsum(lens)]).astype(np.int64)
+    n = int(off[-1]) + 3
+    bits = W.uniform_i64(W.SEED_BASE + 140 + kt, n).view(np.uint64).copy()
+    bits[::7] = np.array(TOTAL_ORDER64, dtype=np.uint64)[np.arange(len(bits[::7])) % len(TOTAL_ORDER64)]
+    for asc in (True, False):
+        t = torch.from_numpy(bits.view(np.int64).copy()).cuda()
+        o = torch.from_numpy(off).cuda()
+        B.bitonic_sort_segmented_keys(t, o, asc, key_type)
+        torch.cuda.synchronize()
+        got = t.cpu().numpy().view(np.uint64)
+        want = bits.copy()
+        for a, b in zip(off[:-1], off[1:]):
+            if b > a:
+                want[a:b] = O.sort_keys64(bits[a:b].view(dt), kt, asc).view(np.uint64)
+        assert np.array_equal(got, want), (key_type, asc)
