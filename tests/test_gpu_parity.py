@@ -150,6 +150,39 @@ def test_guard_bands():
         assert np.array_equal(h[1024:1024 + n], O.sort_i32(keys, asc))
 
 
+def test_unaligned_pointers():
+    """Views that start 4, 8 or 12 bytes past a 16-byte boundary (the
+    optimized plan needs 16-byte alignment and falls back to scalar
+    accesses): sorted, and nothing outside the view is touched."""
+    canary = np.int32(0x5AFE5AFE)
+    for n in (1000, 70001, (1 << 20) + 3):
+        keys = W.uniform_i32(W.SEED_BASE + 60 + n, n)
+        for shift in (1, 2, 3):
+            buf = torch.full((n + 64,), int(canary), dtype=torch.int32, device="cuda")
+            buf[shift:shift + n] = torch.from_numpy(keys).cuda()
+            for asc, plan in ((True, None), (False, ("optimized", 14, 8))):
+                view = buf[shift:shift + n]
+                print(f"[case] unaligned n={n} shift={shift} asc={asc} plan={plan}", flush=True)
+                if plan is None:
+                    B.bitonic_sort_i32(view, asc)
+                else:
+                    B.bitonic_sort_plan_i32(view, asc, plan)
+                torch.cuda.synchronize()
+                h = buf.cpu().numpy()
+                assert (h[:shift] == canary).all() and (h[shift + n:] == canary).all()
+                assert np.array_equal(h[shift:shift + n], O.sort_i32(keys, asc)), (n, shift)
+        bits = keys.view(np.uint32)
+        for key_type, kt, dt in (("uint32", O.KEY_U32, np.uint32), ("float32", O.KEY_F32, np.float32)):
+            buf = torch.full((n + 8,), int(canary), dtype=torch.int32, device="cuda")
+            buf[3:3 + n] = torch.from_numpy(keys).cuda()
+            B.bitonic_sort_keys(buf[3:3 + n], True, key_type)
+            torch.cuda.synchronize()
+            h = buf.cpu().numpy()
+            assert (h[:3] == canary).all() and (h[3 + n:] == canary).all()
+            want = O.sort_keys(bits.view(dt), kt, True).view(np.int32)
+            assert np.array_equal(h[3:3 + n], want), key_type
+
+
 def test_keygen_matches_host_generator():
     for seed, start, n in ((1, 0, 1000), (W.SEED_BASE + 2, 12345, 70001), (2**63 + 5, 7, 33)):
         t = torch.empty(n, dtype=torch.int32, device="cuda")

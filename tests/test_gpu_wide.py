@@ -323,3 +323,31 @@ def test_segmented_8_byte_keys(key_type):
             if b > a:
                 want[a:b] = O.sort_keys64(bits[a:b].view(dt), kt, asc).view(np.uint64)
         assert np.array_equal(got, want), (key_type, asc)
+
+
+def test_wide_unaligned_views():
+    """int64 keys that start 8 bytes past a 16-byte boundary and pairs whose
+    arrays start at odd 4-byte offsets; nothing outside the views is
+    touched."""
+    n = 300001
+    keys = _i64(W.SEED_BASE + 150, n)
+    buf = torch.full((n + 4,), 77, dtype=torch.int64, device="cuda")
+    buf[1:1 + n] = torch.from_numpy(keys).cuda()
+    B.bitonic_sort_keys64(buf[1:1 + n], False, "int64")
+    torch.cuda.synchronize()
+    h = buf.cpu().numpy()
+    assert h[0] == 77 and (h[1 + n:] == 77).all()
+    assert np.array_equal(h[1:1 + n], O.sort_keys64(keys, O.KEY_I64, False))
+    k32 = (W.uniform_i32(W.SEED_BASE + 151, n).astype(np.int64) % 1000).astype(np.int32)
+    v32 = W.uniform_i32(W.SEED_BASE + 152, n)
+    kb = torch.full((n + 8,), -5, dtype=torch.int32, device="cuda")
+    vb = torch.full((n + 8,), -6, dtype=torch.int32, device="cuda")
+    kb[3:3 + n] = torch.from_numpy(k32).cuda()
+    vb[5:5 + n] = torch.from_numpy(v32).cuda()
+    B.bitonic_sort_pairs(kb[3:3 + n], vb[5:5 + n], True)
+    torch.cuda.synchronize()
+    hk, hv = kb.cpu().numpy(), vb.cpu().numpy()
+    assert (hk[:3] == -5).all() and (hk[3 + n:] == -5).all()
+    assert (hv[:5] == -6).all() and (hv[5 + n:] == -6).all()
+    wk, wv = O.sort_pairs(k32, v32, O.KEY_I32, True)
+    assert np.array_equal(hk[3:3 + n], wk) and np.array_equal(hv[5:5 + n], wv)
