@@ -28,8 +28,9 @@
  *    key at the lower index), in which a comparator whose upper end is a
  *    sentinel never moves anything, so it is skipped.
  *  - The optimized kernels move keys in 16-byte vectors; a keys pointer that
- *    is not 16-byte aligned is sorted with the semi plan instead (same
- *    result, scalar accesses).
+ *    is not 16-byte aligned (but 4-byte aligned) is sorted by the same plan
+ *    with scalar-access tile kernels of 2^13 keys and one-column passes
+ *    (same result).
  *  - Errors in the arguments are reported synchronously and nothing is
  *    enqueued.  No exception crosses this interface.
  *  - Calls are reentrant on different streams.  The segmented sort uses a

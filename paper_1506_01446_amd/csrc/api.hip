@@ -36,6 +36,7 @@ struct Resolved {
   int fuse;
   int merge_bpc;          // tile-merge workgroups per compute unit
   uint32_t merge_blocks;  // merge_bpc x compute units (set when enqueueing)
+  bool scalar_io = false;  // optimized plan for an array off a 16-byte boundary
 };
 
 // The library's tile size for n keys (measured on MI355X: below 2^21 keys
@@ -140,6 +141,8 @@ static int64_t enqueue_plain(int32_t* keys, uint32_t n, int K, Codec flip, const
     if (K < kTileMinLog2)
       emit(BITONIC_LAUNCH_LDS_NETWORK, 0,
            [&] { launch_lds_network(K, 1, K, false, keys, n, flip, st); });
+    else if (r.scalar_io)
+      emit(BITONIC_LAUNCH_TILE_SORT, 0, [&] { launch_tile_scalar(0, keys, n, flip, CX_BOTH, st); });
     else
       emit(BITONIC_LAUNCH_TILE_SORT, 0, [&] { launch_tile(K, 0, keys, n, flip, CX_BOTH, 0, st); });
     return launches;
@@ -151,7 +154,12 @@ static int64_t enqueue_plain(int32_t* keys, uint32_t n, int K, Codec flip, const
   // a pass that straddles n takes the bounds-checked eight-step kernel, which
   // runs out of registers, so such sorts use at most seven.
   const int fuse = (r.fuse > kFuseMaxRagged && (n & (n - 1)) != 0) ? kFuseMaxRagged : r.fuse;
-  emit(BITONIC_LAUNCH_TILE_SORT, 0, [&] { launch_tile(L, 0, keys, n, flip, CX_ENC, 0, st); });
+  emit(BITONIC_LAUNCH_TILE_SORT, 0, [&] {
+    if (r.scalar_io)
+      launch_tile_scalar(0, keys, n, flip, CX_ENC, st);
+    else
+      launch_tile(L, 0, keys, n, flip, CX_ENC, 0, st);
+  });
   for (int p = L + 1; p <= K; ++p) {
     const int nb = p - L;                          // long-stride steps
     const int npass = (nb + fuse - 1) / fuse;      // fused HBM passes
@@ -165,23 +173,32 @@ static int64_t enqueue_plain(int32_t* keys, uint32_t n, int K, Codec flip, const
       const int passes_left = npass - i;
       const int f = fuse < left - (passes_left - 1) ? fuse : left - (passes_left - 1);
       const int q = top - f + 1;
-      emit(BITONIC_LAUNCH_GLOBAL_PASS, f,
-           [&] { launch_global_pass(f, i == 0, keys, n, q, st); });
+      emit(BITONIC_LAUNCH_GLOBAL_PASS, f, [&] {
+        if (r.scalar_io)
+          launch_column_pass_i32(f, i == 0, keys, n, q, st);
+        else
+          launch_global_pass(f, i == 0, keys, n, q, st);
+      });
       top = q - 1;
     }
     const int cx = p == K ? CX_DEC : CX_NONE;
-    emit(BITONIC_LAUNCH_TILE_MERGE, 0,
-         [&] { launch_tile(L, 1, keys, n, flip, cx, r.merge_blocks, st); });
+    emit(BITONIC_LAUNCH_TILE_MERGE, 0, [&] {
+      if (r.scalar_io)
+        launch_tile_scalar(1, keys, n, flip, cx, st);
+      else
+        launch_tile(L, 1, keys, n, flip, cx, r.merge_blocks, st);
+    });
   }
   return launches;
 }
 
 // The optimized kernels move keys in 16-byte vectors, which needs a 16-byte
-// aligned base; other pointers take the semi plan (scalar accesses).
+// aligned base; other pointers take the same plan with scalar-access tile
+// kernels (2^13-key tiles) and one-column passes.
 static void fit_alignment(const int32_t* keys, Resolved* r) {
   if (r->kind == BITONIC_PLAN_OPTIMIZED && (reinterpret_cast<uintptr_t>(keys) & 15u) != 0) {
-    r->kind = BITONIC_PLAN_SEMI;
-    r->tile = 12;
+    r->scalar_io = true;
+    r->tile = kScalarTileLog2;
   }
 }
 

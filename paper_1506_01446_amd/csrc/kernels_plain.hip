@@ -88,6 +88,25 @@ void launch_tile(int L, int kind, int32_t* keys, uint32_t n, Codec cd, int cx,
   }
 }
 
+void launch_tile_scalar(int kind, int32_t* keys, uint32_t n, Codec cd, int cx, hipStream_t st) {
+  constexpr int L = kScalarTileLog2;
+  const uint32_t ntiles = (uint32_t)(((uint64_t)n + (1u << L) - 1) >> L);
+  constexpr int NT = 1 << (L - kTileRegLog);
+  if (codec_is_identity(cd)) cx = CX_NONE;
+  if (kind == 0) {
+    if (cx == CX_NONE)
+      tile_kernel<L, kTileRegLog, 2, CX_NONE><<<ntiles, NT, 0, st>>>(keys, n, cd);
+    else if (cx == CX_ENC)
+      tile_kernel<L, kTileRegLog, 2, CX_ENC><<<ntiles, NT, 0, st>>>(keys, n, cd);
+    else
+      tile_kernel<L, kTileRegLog, 2, CX_BOTH><<<ntiles, NT, 0, st>>>(keys, n, cd);
+  } else if (cx == CX_NONE) {
+    tile_kernel<L, kTileRegLog, 3, CX_NONE><<<ntiles, NT, 0, st>>>(keys, n, cd);
+  } else {
+    tile_kernel<L, kTileRegLog, 3, CX_DEC><<<ntiles, NT, 0, st>>>(keys, n, cd);
+  }
+}
+
 void launch_lds_network(int L, int p_first, int p_last, bool tail, int32_t* keys, uint32_t n,
                         Codec cd, hipStream_t st) {
   const uint32_t T = 1u << L;

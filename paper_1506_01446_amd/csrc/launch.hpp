@@ -25,13 +25,20 @@ bool tile_log2_supported(int L);
 void launch_tile(int L, int kind, int32_t* keys, uint32_t n, Codec cd, int cx,
                  uint32_t max_blocks, hipStream_t st);
 
+// Arrays that do not start on a 16-byte boundary: tile sort (kind 0) or merge
+// (kind 1) of 2^kScalarTileLog2-key tiles whose global accesses put lanes on
+// consecutive keys (4-byte alignment suffices).  cx as for launch_tile.
+constexpr int kScalarTileLog2 = 13;
+void launch_tile_scalar(int kind, int32_t* keys, uint32_t n, Codec cd, int cx, hipStream_t st);
+
 // f fused steps on bits q+f-1 .. q (the first one the mirror step if
 // `mirror`) on keys already in the sorting domain.  Requires q >= 8,
 // q + f <= 31, 1 <= f <= kFuseMax (f <= 5: four columns per thread; 6..8:
 // one column).
 void launch_global_pass(int f, bool mirror, int32_t* keys, uint32_t n, int q, hipStream_t st);
 
-// The one-column passes behind launch_global_pass for f = 6 .. kFuseMax.
+// The one-column passes: behind launch_global_pass for f = 6 .. kFuseMax,
+// and for every f (1 .. kFuseMax) in the plan for unaligned arrays.
 void launch_column_pass_i32(int f, bool mirror, int32_t* keys, uint32_t n, int q, hipStream_t st);
 
 // LDS network on 2^L tiles (L <= kLdsNetworkMaxLog2).
