@@ -1,4 +1,6 @@
-// Planner and C interface of the single-array sort (include/bitonic.h).
+// Planners and C interface (include/bitonic.h): single-array sorts of 4-byte
+// keys, of 8-byte keys and of (key, value) pairs, the segmented sort, graph
+// capture, tuning.
 //
 // The planner maps the k(k+1)/2 steps of the network for N = 2^k keys
 // (sections 3.2, 3.3) onto kernel launches, all enqueued on the caller's
@@ -9,6 +11,9 @@
 //   semi:      LDS tile network for phases 1..t, one launch per long-stride
 //              step, one LDS tail per phase (section 4.1 alone);
 //   basic:     one launch per step (section 3.3).
+// The 8-byte sorts use the optimized plan on 8-byte elements (enqueue_wide);
+// the segmented sort classifies its segments on the device and runs the
+// optimized plan's structure per class (enqueue_segmented).
 #include <atomic>
 #include <climits>
 #include <cstdio>
