@@ -20,8 +20,18 @@ Printed JSON line (one line, rank 0):
                summary (profiles/sort_n<n>_hbm_traffic.txt), null when the
                kernel sources changed since those counters were taken
   cpu_baseline the CPU oracle (std::sort, one thread) on a bounded sample
-  extra        n = 10,000,000, per-kernel table, batched vs looped
-               segmented sorting, serving latency when run
+  extra        per-kernel table; n = 10,000,000; per-repetition medians and
+               p90 (warm and cold) at 2^24 and 2^26; the 8-byte sorts (int64
+               keys, key-value pairs) at 2^24; batched vs looped segmented
+               sorting and the batched per-segment argsort; serving latency;
+               the oracle's scalar network as a second CPU context figure
+               (each part can be switched off: --no-extra, --no-batched,
+               --serve-seconds 0, --no-cpu)
+
+python bench.py --ablation   re-measures the paper's Table 1 (Basic, Semi,
+                             Optimized plans for n = 2^17 .. 2^28)
+python bench.py --counters   a short run for rocprofv3 --pmc (a device copy for
+                             calibration and three sorts)
 """
 from __future__ import annotations
 

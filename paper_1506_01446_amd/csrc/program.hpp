@@ -171,12 +171,15 @@ constexpr void add_merge_bits(Program& P, int top, bool mirror) {
 // Phases 1..L of the flip network on one tile: afterwards the tile is
 // ascending.  Phases 1..r run in the blocked layout (thread holds R
 // consecutive keys, where the mirror step is a register-index mask).  A tile
-// of L == r bits is one thread's registers: one group and no LDS.
+// of L == r bits is one thread's registers: one group and no LDS.  With
+// vector I/O the keys are loaded straight into the blocked layout (R / 4
+// 16-byte loads per thread); with scalar I/O they are loaded in the scalar
+// I/O layout and regrouped.
 constexpr Program make_tile_sort(int L, int r, bool vector_io) {
   Program P{};
   P.L = L;
   P.r = r;
-  if (L > r) P.g[P.ngroups++] = vector_io ? io_group(L, r) : io_scalar_group(L, r);
+  if (L > r && !vector_io) P.g[P.ngroups++] = io_scalar_group(L, r);
   Group g0 = blocked_group(r);
   const int pin = L < r ? L : r;
   for (int p = 1; p <= pin; ++p) {
