@@ -65,7 +65,7 @@ struct Prog {
   static constexpr int R = 1 << R_LOG_;
   static constexpr int NT = 1 << (L_ - R_LOG_);
   static constexpr int T = 1 << L_;
-  static constexpr uint32_t LDSW = lds_words(L_);  // padded LDS words of a tile
+  static constexpr uint32_t LDSW = lds_words(L_, R_LOG_);  // padded LDS words of a tile
   static constexpr bool VEC = KIND_ < 2;  // 16-byte vector global I/O allowed
   // Recompute each layout's thread base at its regroup (fewer registers,
   // more ALU); used by the segment kernels, which run several programs in
@@ -105,16 +105,16 @@ struct LdsBase {
   __device__ __forceinline__ explicit LdsBase(uint32_t tid) {
     constexpr Group gr = PR::value.g[G];
     const uint32_t b = deposit<free_mask(gr, PR::L)>(tid);
-    plain = lds_pad(b);
+    plain = lds_pad(b, PR::RL);
     if constexpr (gr.vmirror > 0)
-      mirrored = lds_pad(b ^ (mirror_mask(gr) & free_mask(gr, PR::L)));
+      mirrored = lds_pad(b ^ (mirror_mask(gr) & free_mask(gr, PR::L)), PR::RL);
     else
       mirrored = plain;
   }
   template <uint32_t J>
   __device__ __forceinline__ uint32_t at() const {
     constexpr Group gr = PR::value.g[G];
-    constexpr uint32_t o = lds_pad(real_off(gr, J));
+    constexpr uint32_t o = lds_pad(real_off(gr, J), PR::RL);
     return (slot_mirrored(gr, J) ? mirrored : plain) + o;
   }
 };

@@ -6,7 +6,9 @@
 // (sections 3.1-4.2 of the paper): a tile sort of phases 1..L per 2^L-element
 // tile in registers and LDS, then for every phase p > L its long strides in
 // fused passes over global memory and its last L strides in a tile merge.
-// Only the element width changes, and with it the global access pattern:
+// The element width changes, and with it the register count (16 elements per
+// thread, so that a 2^12-element tile of 8-byte words is a four-wave
+// workgroup and a CU holds 16 waves) and the global access pattern:
 // threads move one element per register slot with lanes on consecutive
 // elements (8-byte accesses for int64 keys, a 4-byte access into each array
 // for pairs), which needs no alignment beyond the element's own.

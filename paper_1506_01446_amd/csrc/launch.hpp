@@ -52,7 +52,7 @@ void launch_step(int sb, bool mirror, int32_t* keys, uint32_t n, uint32_t N, Cod
 // Sort of 8-byte elements (kernels_wide.hip): 2^kWideRegLog elements per
 // thread in the tile kernels, tiles of 2^kWideTileMinLog2 .. 2^kWideTileMaxLog2
 // elements, up to kWideFuseMax steps per pass.
-constexpr int kWideRegLog = 5;
+constexpr int kWideRegLog = 4;
 constexpr int kWideTileMinLog2 = 11;
 constexpr int kWideTileMaxLog2 = 13;
 constexpr int kWideFuseMax = 6;

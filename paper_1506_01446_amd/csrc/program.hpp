@@ -107,11 +107,15 @@ constexpr bool slot_is_lower(const Group& G, uint32_t j, uint32_t D) {
   return ((real_off(G, j) >> h) & 1u) == 0;
 }
 
-// Padded LDS position of tile index i.
-constexpr uint32_t lds_pad(uint32_t i) { return i + (i >> 5); }
+// Padded LDS position of tile index i: one word of padding after every 2^s,
+// s = the log2 of the slots per thread.  A regroup's lanes then step through
+// LDS in strides that are odd multiples of a word, bank-conflict free for
+// the layouts of make_program.  Additive over indices with disjoint bits, so
+// a slot's position is P(thread part) + P(register part).
+constexpr uint32_t lds_pad(uint32_t i, int s = 5) { return i + (i >> s); }
 
 // Words of LDS a padded tile of 2^L keys occupies.
-constexpr uint32_t lds_words(int L) { return lds_pad((1u << L) - 1u) + 1u; }
+constexpr uint32_t lds_words(int L, int s = 5) { return lds_pad((1u << L) - 1u, s) + 1u; }
 
 // Layout for 16-byte global loads and stores: each thread holds 4
 // consecutive keys (index bits 0, 1) of r - 2 rows (the top tile bits), so a

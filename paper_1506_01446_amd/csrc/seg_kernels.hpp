@@ -150,15 +150,27 @@ __device__ __forceinline__ uint32_t upper_index(const uint64_t* __restrict__ pre
   return lo;
 }
 
+// Register slots (log2) per thread of the big-segment tile programs: 32 for
+// 4-byte keys; 16 for 8-byte elements, whose 2^13-element tile fills twice
+// the LDS, so that a CU still runs 16 waves of them.
+template <class ST>
+constexpr int seg_tile_reg_log() {
+  return sizeof(typename ST::E) == 8 ? 4 : kTileRegLogSeg;
+}
+template <class ST>
+constexpr int seg_tile_threads() {
+  return 1 << (kSegTileLog - seg_tile_reg_log<ST>());
+}
+
 // Every 2^13-key tile of the big segments of class >= cls_min: sort
 // (KIND 2) or merge (KIND 3).
 template <int KIND, class ST, class CD>
-__global__ __launch_bounds__(kSegThreads) void seg_tile_kernel(
+__global__ __launch_bounds__(seg_tile_threads<ST>()) void seg_tile_kernel(
     ST keys, const int64_t* __restrict__ offsets,
     const SegMeta* __restrict__ meta, const uint32_t* __restrict__ big_ids,
     const uint64_t* __restrict__ big_tiles, int cls_min, CD cd) {
-  using PR = Prog<kSegTileLog, kTileRegLogSeg, KIND>;
-  static_assert(PR::NT == kSegThreads, "one tile per workgroup");
+  using PR = Prog<kSegTileLog, seg_tile_reg_log<ST>(), KIND>;
+  static_assert(PR::NT == seg_tile_threads<ST>(), "one tile per workgroup");
   __shared__ typename ST::E lds[PR::LDSW];
   const uint32_t cnt = meta->big_ge[cls_min];
   const uint64_t total = big_tiles[cnt];
@@ -249,12 +261,12 @@ void seg_run(ST keys, CD cd, const SegLaunch& l, const int64_t* offsets, const S
       seg_small_kernel<<<l.grid, kSegThreads, 0, st>>>(keys, offsets, sc.meta, sc.small_ids, cd);
       break;
     case SegLaunch::kTileSort:
-      seg_tile_kernel<2><<<l.grid, kSegThreads, 0, st>>>(keys, offsets, sc.meta, sc.big_ids,
-                                                         sc.big_tiles, l.cls, cd);
+      seg_tile_kernel<2><<<l.grid, seg_tile_threads<ST>(), 0, st>>>(
+          keys, offsets, sc.meta, sc.big_ids, sc.big_tiles, l.cls, cd);
       break;
     case SegLaunch::kTileMerge:
-      seg_tile_kernel<3><<<l.grid, kSegThreads, 0, st>>>(keys, offsets, sc.meta, sc.big_ids,
-                                                         sc.big_tiles, l.cls, cd);
+      seg_tile_kernel<3><<<l.grid, seg_tile_threads<ST>(), 0, st>>>(
+          keys, offsets, sc.meta, sc.big_ids, sc.big_tiles, l.cls, cd);
       break;
     case SegLaunch::kPass: {
 #define BITONIC_SEG_PASS(F)                                                                     \

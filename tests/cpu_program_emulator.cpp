@@ -28,7 +28,7 @@ static uint32_t deposit_rt(uint32_t mask, uint32_t t) {
 static uint32_t lds_addr(const Group& G, int L, uint32_t t, uint32_t j) {
   uint32_t base = deposit_rt(free_mask(G, L), t);
   if (slot_mirrored(G, j)) base ^= mirror_mask(G) & free_mask(G, L);
-  return lds_pad(base) + lds_pad(real_off(G, j));
+  return lds_pad(base, G.r) + lds_pad(real_off(G, j), G.r);
 }
 
 // Real tile index of slot j of thread t (checks the additive address form).
@@ -81,8 +81,9 @@ int emulate_tile(int L, int r, int kind, int32_t* tile, uint32_t valid) {
     }
   }
   int steps = 0;
-  std::vector<int32_t> lds(lds_words(L));
-  std::vector<int> hit(lds_words(L));
+  const uint32_t W = lds_words(L, r);
+  std::vector<int32_t> lds(W);
+  std::vector<int> hit(W);
   for (int g = 0; g < P.ngroups; ++g) {
     const Group& G = P.g[g];
     if (g > 0) {
@@ -91,13 +92,13 @@ int emulate_tile(int L, int r, int kind, int32_t* tile, uint32_t valid) {
       for (uint32_t t = 0; t < NT; ++t) {
         for (uint32_t j = 0; j < R; ++j) {
           const uint32_t a = lds_addr(A, L, t, j);
-          if (a >= lds_words(L) || a != lds_pad(real_index(A, L, t, j))) return -1;
+          if (a >= W || a != lds_pad(real_index(A, L, t, j), r)) return -1;
           lds[a] = x[t * R + j];
           hit[a]++;
         }
       }
       uint32_t filled = 0;
-      for (uint32_t a = 0; a < lds_words(L); ++a) {
+      for (uint32_t a = 0; a < W; ++a) {
         if (hit[a] > 1) return -1;
         filled += hit[a];
       }
@@ -105,7 +106,7 @@ int emulate_tile(int L, int r, int kind, int32_t* tile, uint32_t valid) {
       for (uint32_t t = 0; t < NT; ++t)
         for (uint32_t j = 0; j < R; ++j) {
           const uint32_t a = lds_addr(G, L, t, j);
-          if (a != lds_pad(real_index(G, L, t, j))) return -1;
+          if (a != lds_pad(real_index(G, L, t, j), r)) return -1;
           x[t * R + j] = lds[a];
         }
     }
@@ -137,9 +138,12 @@ int emulate_tile(int L, int r, int kind, int32_t* tile, uint32_t valid) {
   return steps;
 }
 
-// Worst number of lanes of one half-wave (32 lanes) that hit the same LDS
-// bank (of `banks`) in any 32-bit access of any regrouping of the program.
-int worst_bank_conflict(int L, int r, int kind, int banks) {
+// Worst number of lanes of one group of `lanes` consecutive lanes that hit
+// the same LDS bank (of `banks`, in units of one LDS word) in any access of
+// any regrouping of the program.  32 lanes over 32 banks models 4-byte words
+// (a half-wave per access cycle); 16 lanes over 32 banks models 8-byte words
+// (a quarter-wave of 128 bytes per cycle, each word on a pair of banks).
+int worst_bank_conflict_lanes(int L, int r, int kind, int banks, int lanes) {
   const Program P = make(L, r, kind);
   if (!layouts_valid(P, L)) return -1;
   const uint32_t NT = 1u << (L - r), R = 1u << r;
@@ -147,10 +151,10 @@ int worst_bank_conflict(int L, int r, int kind, int banks) {
   for (int g = 1; g < P.ngroups; ++g) {
     for (int side = 0; side < 2; ++side) {
       const Group& G = side == 0 ? P.g[g - 1] : P.g[g];
-      for (uint32_t w0 = 0; w0 < NT; w0 += 32)
+      for (uint32_t w0 = 0; w0 < NT; w0 += (uint32_t)lanes)
         for (uint32_t j = 0; j < R; ++j) {
           std::vector<int> cnt(banks, 0);
-          for (uint32_t t = w0; t < w0 + 32 && t < NT; ++t) {
+          for (uint32_t t = w0; t < w0 + (uint32_t)lanes && t < NT; ++t) {
             const uint32_t a = lds_addr(G, L, t, j);
             worst = std::max(worst, ++cnt[a % banks]);
           }
@@ -158,6 +162,10 @@ int worst_bank_conflict(int L, int r, int kind, int banks) {
     }
   }
   return worst;
+}
+
+int worst_bank_conflict(int L, int r, int kind, int banks) {
+  return worst_bank_conflict_lanes(L, r, kind, banks, 32);
 }
 
 int program_groups(int L, int r, int kind) { return make(L, r, kind).ngroups; }

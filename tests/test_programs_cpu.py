@@ -29,6 +29,8 @@ def emu(tmp_path_factory):
     lib.emulate_tile.restype = ctypes.c_int
     lib.worst_bank_conflict.argtypes = [ctypes.c_int] * 4
     lib.worst_bank_conflict.restype = ctypes.c_int
+    lib.worst_bank_conflict_lanes.argtypes = [ctypes.c_int] * 5
+    lib.worst_bank_conflict_lanes.restype = ctypes.c_int
     lib.program_groups.argtypes = [ctypes.c_int] * 3
     lib.program_groups.restype = ctypes.c_int
     return lib
@@ -109,3 +111,25 @@ def test_scalar_io_programs(emu, L):
     if L > 5:
         assert emu.worst_bank_conflict(L, 5, 2, 32) == 1
         assert emu.worst_bank_conflict(L, 5, 3, 32) == 1
+
+
+@pytest.mark.parametrize("L", [11, 12, 13])
+def test_wide_programs(emu, L):
+    """The programs of the 8-byte tile kernels: 16 elements per thread (r = 4),
+    scalar I/O, LDS padded after every 16 words.  Sort and merge, full and
+    partial tiles; conflict-free for 8-byte LDS words (16 lanes per access
+    cycle over 32 two-word banks)."""
+    T = 1 << L
+    for valid in (T, T - 1, T // 2 + 3, 1):
+        keys = W.uniform_i32(L * 31 + valid, T)
+        out, steps = _run(emu, L, 4, 2, keys, valid)
+        assert steps == L * (L + 1) // 2
+        assert (out[:valid] == np.sort(keys[:valid])).all()
+        assert (out[valid:] == keys[valid:]).all()
+    keys = W.uniform_i32(L + 91, T)
+    cut = T // 5
+    bit = np.concatenate([np.sort(keys[:cut]), np.sort(keys[cut:])[::-1]])
+    out, steps = _run(emu, L, 4, 3, bit, T)
+    assert steps == L and (out == np.sort(keys)).all()
+    for kind in (2, 3):
+        assert emu.worst_bank_conflict_lanes(L, 4, kind, 32, 16) == 1
