@@ -69,6 +69,9 @@ def parse():
     ap.add_argument("--counters", action="store_true",
                     help="short run for rocprofv3 --pmc: one n-key device copy (the "
                          "calibration kernel) and three sorts, no timing")
+    ap.add_argument("--wide-only", action="store_true",
+                    help="only the 8-byte sorts at n = 2^24 (int64 keys, pairs), "
+                         "one JSON line; for kernel traces of those sorts")
     return ap.parse_args()
 
 
@@ -478,6 +481,11 @@ def main():
     if args.ablation:
         del src
         ablation(torch, B, W, args.out)
+        return
+    if args.wide_only:
+        del src
+        res = wide_sorts(torch, B, W)
+        print(json.dumps({"wide": res}), flush=True)
         return
     if args.counters:
         dst = torch.empty_like(src)

@@ -114,9 +114,17 @@ __global__ __launch_bounds__(256) void column_pass_kernel(ST st, uint32_t n, int
   __builtin_amdgcn_sched_barrier(0);
   pass_steps<F, MIRROR, 1>(x);
   __builtin_amdgcn_sched_barrier(0);
+  // 4-byte keys: the stores take their row starts from an opaque copy of the
+  // block start, so the loads' 2^F row addresses (64-bit scalar pairs) die at
+  // the loads instead of living across the steps, where from 64 of them on
+  // they overflow the scalar registers and spill to vector lanes (seven-step
+  // passes 24-25 -> 22-23 us at n = 2^24).  The 8-byte passes measured slower
+  // this way (more vector registers at the same occupancy) and keep theirs.
+  uint32_t bs_st = bs;
+  if constexpr (sizeof(E) == 4) asm volatile("" : "+s"(bs_st));
   static_for<0, ROWS>([&](auto RHO) {
     constexpr bool mir = MIRROR && (RHO & TOP);
-    const uint32_t r0 = bs + (row_of(RHO) << q);
+    const uint32_t r0 = bs_st + (row_of(RHO) << q);
     if (!BOUNDED || r0 + (mir ? mcol : col) < n) st.at(r0).putb(mir ? moff : off, x[RHO]);
     __builtin_amdgcn_sched_barrier(0);
   });
