@@ -321,7 +321,8 @@ int bitonic_sort_plan_launches_i32(int32_t* keys, int64_t n, int ascending,
  * bitonic_plan; 0 keeps the current value).  bitonic_set_tuning_value sets
  * one value by name: "tile_log2" (0 restores the choice by n), "fuse",
  * "merge_blocks_per_cu" (as in bitonic_plan), "seg_blocks_per_cu" (1..16, workgroups per compute unit of
- * the persistent small-segment kernel), "wide_tile_log2" (11..13) or
+ * the persistent small-segment kernel), "seg_pass_blocks_per_cu" (1..32,
+ * workgroups per compute unit of the big-segment passes, default 8), "wide_tile_log2" (11..13) or
  * "wide_fuse" (1..6) (the 8-byte sorts' plan); bitonic_get_tuning_value
  * reads one.
  * bitonic_load_tuning reads "<name> <value>" lines (the autotuner's output

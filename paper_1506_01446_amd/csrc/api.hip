@@ -34,6 +34,7 @@ static std::atomic<int> g_merge_bpc{2};  // 0: one tile per workgroup
 static std::atomic<int> g_wide_tile_log2{12};  // 8-byte sorts
 static std::atomic<int> g_wide_fuse{6};
 static std::atomic<int> g_seg_bpc{4};    // small-segment workgroups per compute unit
+static std::atomic<int> g_seg_pass_bpc{8};  // big-segment pass workgroups per compute unit
 
 struct Resolved {
   int kind;
@@ -309,6 +310,7 @@ static void enqueue_segmented(const SegData& d, const int64_t* offsets, int64_t 
   const int M = ceil_log2(max_seg_len);
   if (M <= 13) return;
   const int grid = cus * 4;
+  const int pass_grid = cus * g_seg_pass_bpc.load();
   launch_seg_tiles(false, d, offsets, sc, 14, grid, st);
   const int fuse = g_fuse.load() < kSegFuseMax ? g_fuse.load() : kSegFuseMax;
   for (int p = 14; p <= M; ++p) {
@@ -319,7 +321,7 @@ static void enqueue_segmented(const SegData& d, const int64_t* offsets, int64_t 
       const int left = top - 13 + 1;
       const int f = (left + (npass - i) - 1) / (npass - i);
       const int q = top - f + 1;
-      launch_seg_pass(f, i == 0, d, offsets, sc, p, q, grid, st);
+      launch_seg_pass(f, i == 0, d, offsets, sc, p, q, pass_grid, st);
       top = q - 1;
     }
     launch_seg_tiles(true, d, offsets, sc, p, grid, st);
@@ -725,6 +727,11 @@ int bitonic_set_tuning_value(const char* key, int value) {
     g_seg_bpc.store(value);
     return BITONIC_OK;
   }
+  if (!std::strcmp(key, "seg_pass_blocks_per_cu")) {
+    if (value < 1 || value > 32) return BITONIC_EINVAL;
+    g_seg_pass_bpc.store(value);
+    return BITONIC_OK;
+  }
   if (!std::strcmp(key, "wide_tile_log2")) {
     if (value < kWideTileMinLog2 || value > kWideTileMaxLog2) return BITONIC_EINVAL;
     g_wide_tile_log2.store(value);
@@ -744,6 +751,7 @@ int bitonic_get_tuning_value(const char* key, int* value) {
   else if (!std::strcmp(key, "fuse")) *value = g_fuse.load();
   else if (!std::strcmp(key, "merge_blocks_per_cu")) *value = g_merge_bpc.load() ? g_merge_bpc.load() : -1;
   else if (!std::strcmp(key, "seg_blocks_per_cu")) *value = g_seg_bpc.load();
+  else if (!std::strcmp(key, "seg_pass_blocks_per_cu")) *value = g_seg_pass_bpc.load();
   else if (!std::strcmp(key, "wide_tile_log2")) *value = g_wide_tile_log2.load();
   else if (!std::strcmp(key, "wide_fuse")) *value = g_wide_fuse.load();
   else return BITONIC_EINVAL;

@@ -150,6 +150,25 @@ __device__ __forceinline__ uint32_t upper_index(const uint64_t* __restrict__ pre
   return lo;
 }
 
+// A workgroup's share of `total` work units: the contiguous range
+// [*first, *end), so that it searches the segment prefix sums once and then
+// walks forward (a search per unit is ~11 dependent loads, which dominated
+// the one-step passes).
+__device__ __forceinline__ void unit_range(uint64_t total, uint64_t* first, uint64_t* end) {
+  const uint64_t per = (total + gridDim.x - 1) / gridDim.x;
+  const uint64_t a = (uint64_t)blockIdx.x * per;
+  *first = a < total ? a : total;
+  *end = a + per < total ? a + per : total;
+}
+
+// upper_index(prefix, cnt, v) given i = upper_index(prefix, cnt, v') for some
+// v' <= v.
+__device__ __forceinline__ uint32_t advance_index(const uint64_t* __restrict__ prefix,
+                                                  uint32_t cnt, uint32_t i, uint64_t v) {
+  while (i + 1 < cnt && prefix[i + 1] <= v) ++i;
+  return i;
+}
+
 // Register slots (log2) per thread of the big-segment tile programs: 32 for
 // 4-byte keys; 16 for 8-byte elements, whose 2^13-element tile fills twice
 // the LDS, so that a CU still runs 16 waves of them.
@@ -173,12 +192,14 @@ __global__ __launch_bounds__(seg_tile_threads<ST>()) void seg_tile_kernel(
   static_assert(PR::NT == seg_tile_threads<ST>(), "one tile per workgroup");
   __shared__ typename ST::E lds[PR::LDSW];
   const uint32_t cnt = meta->big_ge[cls_min];
-  const uint64_t total = big_tiles[cnt];
-  for (uint64_t u = blockIdx.x; u < total; u += gridDim.x) {
+  uint64_t u, uend;
+  unit_range(big_tiles[cnt], &u, &uend);
+  uint32_t i = u < uend ? upper_index(big_tiles, cnt, u) : 0u;
+  for (; u < uend; ++u) {
     // recompute the layouts' thread bases per tile instead of holding them
     uint32_t tid = threadIdx.x;
     asm volatile("" : "+v"(tid));
-    const uint32_t i = upper_index(big_tiles, cnt, u);
+    i = advance_index(big_tiles, cnt, i, u);
     const uint64_t tile = u - big_tiles[i];
     const uint32_t s = big_ids[i];
     const int64_t off = offsets[s];
@@ -218,10 +239,12 @@ __global__ __launch_bounds__(kSegThreads) void seg_pass_kernel(
   constexpr int TOP = ROWS >> 1;
   constexpr int UNIT_LOG = 10 + F;  // keys per unit = 1024 columns x 2^F rows
   const uint32_t cnt = meta->big_ge[cls];
-  const uint64_t total = big_keys[cnt] >> UNIT_LOG;
-  for (uint64_t u = blockIdx.x; u < total; u += gridDim.x) {
+  uint64_t u, uend;
+  unit_range(big_keys[cnt] >> UNIT_LOG, &u, &uend);
+  uint32_t i = u < uend ? upper_index(big_keys, cnt, u << UNIT_LOG) : 0u;
+  for (; u < uend; ++u) {
     const uint64_t key0 = u << UNIT_LOG;
-    const uint32_t i = upper_index(big_keys, cnt, key0);
+    i = advance_index(big_keys, cnt, i, key0);
     const uint64_t lk = key0 - big_keys[i];  // unit's first key, segment-local
     const uint32_t s = big_ids[i];
     const int64_t off = offsets[s];

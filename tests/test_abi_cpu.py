@@ -169,7 +169,8 @@ def test_default_tile_by_n(lib):
 def test_tuning_values_round_trip(lib, tmp_path):
     from paper_1506_01446_amd import autotune
     saved = {k: B.bitonic_get_tuning_value(k) for k in
-             ("tile_log2", "fuse", "merge_blocks_per_cu", "seg_blocks_per_cu")}
+             ("tile_log2", "fuse", "merge_blocks_per_cu", "seg_blocks_per_cu",
+              "seg_pass_blocks_per_cu")}
     try:
         p = tmp_path / "tuning.txt"
         autotune.write_tuning(str(p), {"tile_log2": 12, "fuse": 3, "merge_blocks_per_cu": 4,
@@ -185,6 +186,11 @@ def test_tuning_values_round_trip(lib, tmp_path):
             B.bitonic_set_tuning_value("no_such_knob", 1)
         with pytest.raises(B.BitonicError):
             B.bitonic_set_tuning_value("seg_blocks_per_cu", 0)
+        B.bitonic_set_tuning_value("seg_pass_blocks_per_cu", 16)
+        assert B.bitonic_get_tuning_value("seg_pass_blocks_per_cu") == 16
+        for bad in (0, 33):
+            with pytest.raises(B.BitonicError):
+                B.bitonic_set_tuning_value("seg_pass_blocks_per_cu", bad)
     finally:
         for k, v in saved.items():
             B.bitonic_set_tuning_value(k, v)
