@@ -9,6 +9,8 @@ Searches, on the GPU, the plan parameters that do not change the result:
 for the single-array sort of n keys, and
   seg_blocks_per_cu    workgroups per compute unit of the persistent
                        small-segment kernel
+  seg_pass_blocks_per_cu  workgroups per compute unit of the big-segment
+                       passes
 on the batched segmented workload.  Every candidate is timed with HIP events
 over fresh copies of the same seeded input (median of several runs) and its
 output checked sorted; the fastest are written as "<name> <value>" lines that
@@ -95,9 +97,17 @@ def tune(n: int = 1 << 24, reps: int = 5, quick: bool = False, log=print) -> dic
         log(json.dumps({"seg_blocks_per_cu": bpc, "ms": round(ms, 4)}))
     seg.sort()
     B.bitonic_set_tuning_value("seg_blocks_per_cu", seg[0][1])
+    segp = []
+    for bpc in ((8,) if quick else (4, 8, 16)):
+        B.bitonic_set_tuning_value("seg_pass_blocks_per_cu", bpc)
+        ms = _time_segmented(torch, kt, ot, max_len, reps)
+        segp.append((ms, bpc))
+        log(json.dumps({"seg_pass_blocks_per_cu": bpc, "ms": round(ms, 4)}))
+    segp.sort()
+    B.bitonic_set_tuning_value("seg_pass_blocks_per_cu", segp[0][1])
     return {"tile_log2": best[1], "fuse": best[2], "merge_blocks_per_cu": best[3],
-            "seg_blocks_per_cu": seg[0][1], "sort_ms": round(best[0], 4),
-            "segmented_ms": round(seg[0][0], 4), "n": n}
+            "seg_blocks_per_cu": seg[0][1], "seg_pass_blocks_per_cu": segp[0][1],
+            "sort_ms": round(best[0], 4), "segmented_ms": round(segp[0][0], 4), "n": n}
 
 
 def write_tuning(path: str, best: dict) -> None:
@@ -106,6 +116,8 @@ def write_tuning(path: str, best: dict) -> None:
         f.write(f"fuse {best['fuse']}\n")
         f.write(f"merge_blocks_per_cu {best['merge_blocks_per_cu']}\n")
         f.write(f"seg_blocks_per_cu {best['seg_blocks_per_cu']}\n")
+        if "seg_pass_blocks_per_cu" in best:
+            f.write(f"seg_pass_blocks_per_cu {best['seg_pass_blocks_per_cu']}\n")
 
 
 def main(argv=None) -> int:

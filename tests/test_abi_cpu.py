@@ -174,12 +174,13 @@ def test_tuning_values_round_trip(lib, tmp_path):
     try:
         p = tmp_path / "tuning.txt"
         autotune.write_tuning(str(p), {"tile_log2": 12, "fuse": 3, "merge_blocks_per_cu": 4,
-                                       "seg_blocks_per_cu": 2})
+                                       "seg_blocks_per_cu": 2, "seg_pass_blocks_per_cu": 12})
         B.bitonic_load_tuning(str(p))
         assert B.bitonic_get_tuning_value("tile_log2") == 12
         assert B.bitonic_get_tuning_value("fuse") == 3
         assert B.bitonic_get_tuning_value("merge_blocks_per_cu") == 4
         assert B.bitonic_get_tuning_value("seg_blocks_per_cu") == 2
+        assert B.bitonic_get_tuning_value("seg_pass_blocks_per_cu") == 12
         # the default plan follows the tuning
         assert B.bitonic_plan_passes(2**24) == _closed_form_optimized(24, 12, 3)
         with pytest.raises(B.BitonicError):
