@@ -304,6 +304,23 @@ def test_segmented_big_classes_unaligned():
         assert np.array_equal(got, want), ("bounded", asc)
 
 
+def test_segmented_pass_grid_extremes():
+    """The big-segment kernels split their units into one contiguous range per
+    workgroup: with 1 pass workgroup per CU a range spans many segments, with
+    32 most ranges are short or empty.  Odd lengths up to 2^17."""
+    keys, off = W.batched_workload(nseg=700, seed=9, max_log2=17)
+    saved = B.bitonic_get_tuning_value("seg_pass_blocks_per_cu")
+    try:
+        want = {asc: O.sort_segmented_i32(keys, off, asc) for asc in (True, False)}
+        for bpc in (1, 3, 32):
+            B.bitonic_set_tuning_value("seg_pass_blocks_per_cu", bpc)
+            for asc in (True, False):
+                got = gpu_sort_segmented(keys, off, asc)
+                assert np.array_equal(got, want[asc]), (bpc, asc)
+    finally:
+        B.bitonic_set_tuning_value("seg_pass_blocks_per_cu", saved)
+
+
 def test_segmented_many_small():
     lens = (W.splitmix64(77, 0, 20000) % np.uint64(70)).astype(np.int64)
     off = W.offsets_from_lengths(lens)
