@@ -10,6 +10,7 @@
 #include "device.hpp"
 #include "launch.hpp"
 #include "segmented.hpp"
+#include "split_regroup.hpp"
 
 namespace bitonic {
 
@@ -32,7 +33,10 @@ __device__ __forceinline__ uint32_t small_per_item(int cls) {
 //
 // One tile of a storage in a scalar-I/O program (KIND 2 or 3), `valid` of its
 // elements real.  4-byte keys take the single-array sort's tile program.
-template <class PR, class ST, class CD>
+//
+// SPLIT (8-byte elements only): lds is an array of PR::LDSW 4-byte words and
+// the regroups move high and low words in turn (run_from_split).
+template <class PR, bool SPLIT = false, class ST, class CD>
 __device__ __forceinline__ void seg_tile_program(ST tile, uint32_t valid, CD cd,
                                                  typename ST::E* lds, uint32_t tid) {
   if constexpr (std::is_same_v<ST, Keys32>) {
@@ -54,7 +58,10 @@ __device__ __forceinline__ void seg_tile_program(ST tile, uint32_t valid, CD cd,
         });
       }
     }
-    run_from<PR, 0>(x, lds, tid);
+    if constexpr (SPLIT)
+      run_from_split<PR, 0>(x, reinterpret_cast<uint32_t*>(lds), tid);
+    else
+      run_from<PR, 0>(x, lds, tid);
     {
       if constexpr (PR::LEAN) asm volatile("" : "+v"(tid));
       constexpr Group gr = PR::value.g[LAST];
@@ -190,7 +197,11 @@ __global__ __launch_bounds__(seg_tile_threads<ST>()) void seg_tile_kernel(
     const uint64_t* __restrict__ big_tiles, int cls_min, CD cd) {
   using PR = Prog<kSegTileLog, seg_tile_reg_log<ST>(), KIND>;
   static_assert(PR::NT == seg_tile_threads<ST>(), "one tile per workgroup");
-  __shared__ typename ST::E lds[PR::LDSW];
+  // 8-byte elements regroup through 4-byte words (half the LDS: four
+  // workgroups per CU instead of two)
+  constexpr bool SPLIT = sizeof(typename ST::E) == 8;
+  __shared__ uint32_t lds32[PR::LDSW * (SPLIT ? 1 : sizeof(typename ST::E) / 4)];
+  typename ST::E* lds = reinterpret_cast<typename ST::E*>(lds32);
   const uint32_t cnt = meta->big_ge[cls_min];
   uint64_t u, uend;
   unit_range(big_tiles[cnt], &u, &uend);
@@ -207,7 +218,7 @@ __global__ __launch_bounds__(seg_tile_threads<ST>()) void seg_tile_kernel(
     const uint64_t t0 = tile << kSegTileLog;
     const uint64_t left = len - t0;
     const uint32_t valid = left < (uint64_t)PR::T ? (uint32_t)left : (uint32_t)PR::T;
-    seg_tile_program<PR>(keys.at(off + t0), valid, cd, lds, tid);
+    seg_tile_program<PR, SPLIT>(keys.at(off + t0), valid, cd, lds, tid);
     __syncthreads();  // LDS reuse by the next tile
   }
 }
