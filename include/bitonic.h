@@ -230,7 +230,7 @@ typedef struct bitonic_plan {
  * sorts pairs (bitonic_sort_pairs).  The plan's kind
  * must be BITONIC_PLAN_AUTO or BITONIC_PLAN_OPTIMIZED, its tile_log2 11..13
  * (elements per tile), its fuse 1..6; merge_blocks_per_cu is ignored (one
- * tile per workgroup).  Library choices (0): tile_log2 12, fuse 6 (tuning
+ * tile per workgroup).  Library choices (0): tile_log2 13, fuse 6 (tuning
  * values "wide_tile_log2" and "wide_fuse").
  */
 int bitonic_sort_wide_plan(void* keys, int32_t* values, int64_t n, int key_type, int ascending,

@@ -31,7 +31,7 @@ namespace bitonic {
 static std::atomic<int> g_tile_log2{0};  // 0: by n (default_tile_log2)
 static std::atomic<int> g_fuse{8};
 static std::atomic<int> g_merge_bpc{2};  // 0: one tile per workgroup
-static std::atomic<int> g_wide_tile_log2{12};  // 8-byte sorts
+static std::atomic<int> g_wide_tile_log2{13};  // 8-byte sorts
 static std::atomic<int> g_wide_fuse{6};
 static std::atomic<int> g_seg_bpc{4};    // small-segment workgroups per compute unit
 static std::atomic<int> g_seg_pass_bpc{8};  // big-segment pass workgroups per compute unit

@@ -22,6 +22,7 @@
 // INT64_MAX sentinels of the sorting domain.
 #include "column_pass.hpp"
 #include "launch.hpp"
+#include "split_regroup.hpp"
 
 namespace bitonic {
 
@@ -31,7 +32,7 @@ __global__ __launch_bounds__(1 << (L - kWideRegLog)) void wide_tile_kernel(ST st
                                                                            Codec64 codec) {
   using PR = Prog<L, kWideRegLog, KIND>;
   constexpr int LAST = PR::value.ngroups - 1;
-  __shared__ int64_t lds[PR::LDSW];
+  __shared__ uint32_t lds[PR::LDSW];  // 4-byte words: run_from_split
   const KeyIO<CX, Codec64> cd{codec};
   const uint32_t t0 = (uint32_t)blockIdx.x << L;
   const uint32_t left = n - t0;
@@ -51,7 +52,7 @@ __global__ __launch_bounds__(1 << (L - kWideRegLog)) void wide_tile_kernel(ST st
       });
     }
   }
-  run_from<PR, 0>(x, lds, threadIdx.x);
+  run_from_split<PR, 0>(x, lds, threadIdx.x);
   {
     uint32_t tid = threadIdx.x;
     asm volatile("" : "+v"(tid));
