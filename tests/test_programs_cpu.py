@@ -117,8 +117,10 @@ def test_scalar_io_programs(emu, L):
 def test_wide_programs(emu, L):
     """The programs of the 8-byte tile kernels: 16 elements per thread (r = 4),
     scalar I/O, LDS padded after every 16 words.  Sort and merge, full and
-    partial tiles; conflict-free for 8-byte LDS words (16 lanes per access
-    cycle over 32 two-word banks)."""
+    partial tiles.  The layouts are conflict-free for 8-byte LDS words (16
+    lanes per access cycle over 32 two-word banks); the kernels regroup high
+    and low words in turn through 4-byte words, where a half-wave meets at
+    most 2-way conflicts."""
     T = 1 << L
     for valid in (T, T - 1, T // 2 + 3, 1):
         keys = W.uniform_i32(L * 31 + valid, T)
@@ -133,3 +135,4 @@ def test_wide_programs(emu, L):
     assert steps == L and (out == np.sort(keys)).all()
     for kind in (2, 3):
         assert emu.worst_bank_conflict_lanes(L, 4, kind, 32, 16) == 1
+        assert emu.worst_bank_conflict_lanes(L, 4, kind, 32, 32) <= 2
