@@ -7,8 +7,9 @@
 // tile in registers and LDS, then for every phase p > L its long strides in
 // fused passes over global memory and its last L strides in a tile merge.
 // The element width changes, and with it the register count (16 elements per
-// thread, so that a 2^12-element tile of 8-byte words is a four-wave
-// workgroup and a CU holds 16 waves) and the global access pattern:
+// thread), the regroups (high words, then low words, through 4-byte LDS
+// words: a 2^13-element tile is an eight-wave workgroup of 34 KiB and four
+// share a CU) and the global access pattern:
 // threads move one element per register slot with lanes on consecutive
 // elements (8-byte accesses for int64 keys, a 4-byte access into each array
 // for pairs), which needs no alignment beyond the element's own.
