@@ -287,11 +287,60 @@ enum bitonic_launch_kind {
   BITONIC_LAUNCH_GLOBAL_PASS = 2, /* fused long-stride steps (one HBM pass) */
   BITONIC_LAUNCH_TILE_MERGE = 3,  /* strides 2^(t-1)..1 on every tile (one HBM pass) */
   BITONIC_LAUNCH_LDS_NETWORK = 4, /* LDS network on tiles (one HBM pass) */
-  BITONIC_LAUNCH_STEP = 5         /* one step in global memory (one HBM pass) */
+  BITONIC_LAUNCH_STEP = 5,        /* one step in global memory (one HBM pass) */
+  BITONIC_LAUNCH_SEG_PREP = 6,    /* segmented sort: classify the segments */
+  BITONIC_LAUNCH_SEG_SMALL = 7    /* segmented sort: all segments of <= 2^13 keys */
 };
 
 int64_t bitonic_plan_describe(int64_t n, const bitonic_plan* plan, int32_t* kinds,
                               int32_t* fuse, int64_t cap);
+
+/*
+ * Launch shapes, for checks of the planners; nothing is enqueued and no
+ * device is touched.  For launch i (i < cap) of a sort of n elements laid out
+ * as `layout`, under `plan` (NULL = the library's choice; ignored by the
+ * segmented layouts, which follow the tuning values), writes shapes[i]:
+ *   kind         enum bitonic_launch_kind
+ *   fuse         network steps of a global pass, 1 for a step, else 0
+ *   q            lowest index bit a global pass or step works on (its steps
+ *                cover bits q + fuse - 1 .. q, segment-local for segmented
+ *                sorts); log2 of the tile for tile, LDS and small-segment
+ *                launches
+ *   mirror       1 if the launch's first step is the mirror step of a phase
+ *   elem_bytes   bytes per element in each array: 4 (4-byte keys; pairs,
+ *                whose keys and values are two 4-byte arrays) or 8 (8-byte keys)
+ *   offset_bits  width of the byte offsets the kernel adds to a row or tile
+ *                start: 32, or 64 where it indexes through 64-bit pointers
+ * A kernel stays in range when every row of 2^q elements spans at most
+ * 2^offset_bits bytes.  Layouts: BITONIC_LAYOUT_KEYS32 (4-byte keys,
+ * 16-byte aligned), BITONIC_LAYOUT_KEYS32_UNALIGNED (4-byte keys off a
+ * 16-byte boundary), BITONIC_LAYOUT_KEYS64, BITONIC_LAYOUT_PAIRS, and the
+ * segmented sorts BITONIC_LAYOUT_SEG_KEYS32, BITONIC_LAYOUT_SEG_PAIRS,
+ * BITONIC_LAYOUT_SEG_KEYS64, whose longest segment holds n elements (the
+ * bound of bitonic_sort_segmented_bounded_i32).  Returns the number of
+ * launches, or -1 for a bad argument (n < 0, n > 2^31, a bad plan or layout).
+ */
+typedef struct bitonic_launch_shape {
+  int32_t kind;
+  int32_t fuse;
+  int32_t q;
+  int32_t mirror;
+  int32_t elem_bytes;
+  int32_t offset_bits;
+} bitonic_launch_shape;
+
+enum bitonic_layout {
+  BITONIC_LAYOUT_KEYS32 = 0,
+  BITONIC_LAYOUT_KEYS32_UNALIGNED = 1,
+  BITONIC_LAYOUT_KEYS64 = 2,
+  BITONIC_LAYOUT_PAIRS = 3,
+  BITONIC_LAYOUT_SEG_KEYS32 = 4,
+  BITONIC_LAYOUT_SEG_PAIRS = 5,
+  BITONIC_LAYOUT_SEG_KEYS64 = 6
+};
+
+int64_t bitonic_plan_shapes(int64_t n, int layout, const bitonic_plan* plan,
+                            bitonic_launch_shape* shapes, int64_t cap);
 
 /*
  * bitonic_sort_plan_i32 that also records HIP events on `stream`:

@@ -93,6 +93,8 @@ def load() -> ctypes.CDLL:
         "bitonic_sort_plan_launches_i32": ([vp, ctypes.c_int64, ctypes.c_int,
                                             ctypes.POINTER(bitonic_plan), ctypes.c_int64,
                                             ctypes.c_int64, vp], ctypes.c_int),
+        "bitonic_plan_shapes": ([ctypes.c_int64, ctypes.c_int, ctypes.POINTER(bitonic_plan),
+                                 vp, ctypes.c_int64], ctypes.c_int64),
         "bitonic_sort_plan_events_i32": ([vp, ctypes.c_int64, ctypes.c_int,
                                           ctypes.POINTER(bitonic_plan), vp, ctypes.c_int64,
                                           vp], ctypes.c_int),
@@ -372,6 +374,31 @@ def bitonic_plan_describe(n: int, plan=None) -> list[tuple[str, int]]:
     fuse = np.zeros(max(m, 1), np.int32)
     load().bitonic_plan_describe(int(n), _plan_ref(p), kinds.ctypes.data, fuse.ctypes.data, m)
     return [(LAUNCH_KINDS[int(k)], int(f)) for k, f in zip(kinds[:m], fuse[:m])]
+
+
+class bitonic_launch_shape(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("fuse", ctypes.c_int32), ("q", ctypes.c_int32),
+                ("mirror", ctypes.c_int32), ("elem_bytes", ctypes.c_int32),
+                ("offset_bits", ctypes.c_int32)]
+
+
+LAYOUTS = {"keys32": 0, "keys32_unaligned": 1, "keys64": 2, "pairs": 3, "seg_keys32": 4,
+           "seg_pairs": 5, "seg_keys64": 6}
+LAUNCH_KINDS.update({6: "seg_prep", 7: "seg_small"})
+
+
+def bitonic_plan_shapes(n: int, layout: str = "keys32", plan=None) -> list[dict]:
+    """The shape of every launch of a sort of n elements (bitonic_plan_shapes):
+    [{kind, fuse, q, mirror, elem_bytes, offset_bits}]."""
+    p = _plan(plan)
+    lay = LAYOUTS[layout] if isinstance(layout, str) else int(layout)
+    m = int(load().bitonic_plan_shapes(int(n), lay, _plan_ref(p), None, 0))
+    if m < 0:
+        raise BitonicError("bitonic_plan_shapes", m)
+    arr = (bitonic_launch_shape * max(m, 1))()
+    load().bitonic_plan_shapes(int(n), lay, _plan_ref(p), ctypes.cast(arr, ctypes.c_void_p), m)
+    return [{"kind": LAUNCH_KINDS[a.kind], "fuse": a.fuse, "q": a.q, "mirror": a.mirror,
+             "elem_bytes": a.elem_bytes, "offset_bits": a.offset_bits} for a in arr[:m]]
 
 
 class HipEvents:

@@ -24,6 +24,7 @@
 
 #include "bitonic.h"
 #include "launch.hpp"
+#include "scratch_cache.hpp"
 #include "segmented.hpp"
 
 namespace bitonic {
@@ -89,6 +90,7 @@ static int ceil_log2(int64_t n) {
 struct Observer {
   int32_t* kinds = nullptr;   // launch kind per launch (bitonic_launch_kind)
   int32_t* fuse = nullptr;    // fused steps per launch (global passes), else 0
+  bitonic_launch_shape* shapes = nullptr;  // full shape per launch
   int64_t cap = 0;
   hipEvent_t* events = nullptr;  // events[i + 1] recorded after launch i
   int64_t nevents = 0;
@@ -105,14 +107,18 @@ static int64_t enqueue_plain(int32_t* keys, uint32_t n, int K, Codec flip, const
   int64_t launches = 0;
   if (K > k) K = k;
   if (K <= 0) return 0;
-  auto emit = [&](int kind, int f, auto&& launch) {
+  // every launch is described by its shape (bitonic_plan_shapes); the
+  // 4-byte kernels index elements through 64-bit pointers except the fused
+  // passes, whose lane byte offsets are 32-bit (column_pass_offset_bits)
+  auto emit = [&](bitonic_launch_shape sh, auto&& launch) {
     const bool selected =
         !obs || (launches >= obs->first && launches - obs->first < obs->count);
     if (!count_only && selected) launch();
     if (obs) {
       if (launches < obs->cap) {
-        if (obs->kinds) obs->kinds[launches] = kind;
-        if (obs->fuse) obs->fuse[launches] = f;
+        if (obs->kinds) obs->kinds[launches] = sh.kind;
+        if (obs->fuse) obs->fuse[launches] = sh.fuse;
+        if (obs->shapes) obs->shapes[launches] = sh;
       }
       if (!count_only && obs->events && launches + 1 < obs->nevents)
         (void)hipEventRecord(obs->events[launches + 1], st);
@@ -122,21 +128,28 @@ static int64_t enqueue_plain(int32_t* keys, uint32_t n, int K, Codec flip, const
   if (obs && !count_only && obs->events && obs->nevents > 0)
     (void)hipEventRecord(obs->events[0], st);
 
+  auto step_shape = [](int sb, bool mirror) {
+    return bitonic_launch_shape{BITONIC_LAUNCH_STEP, 1, sb, mirror ? 1 : 0, 4, 64};
+  };
+  auto tile_shape = [](int kind, int L) { return bitonic_launch_shape{kind, 0, L, 0, 4, 64}; };
+
   if (r.kind == BITONIC_PLAN_BASIC) {
     for (int p = 1; p <= K; ++p)
       for (int sb = p - 1; sb >= 0; --sb)
-        emit(BITONIC_LAUNCH_STEP, 1, [&] { launch_step(sb, sb == p - 1, keys, n, N, flip, st); });
+        emit(step_shape(sb, sb == p - 1),
+             [&] { launch_step(sb, sb == p - 1, keys, n, N, flip, st); });
     return launches;
   }
 
   if (r.kind == BITONIC_PLAN_SEMI) {
     const int L = K < r.tile ? K : r.tile;
-    emit(BITONIC_LAUNCH_LDS_NETWORK, 0,
+    emit(tile_shape(BITONIC_LAUNCH_LDS_NETWORK, L),
          [&] { launch_lds_network(L, 1, L, false, keys, n, flip, st); });
     for (int p = L + 1; p <= K; ++p) {
       for (int sb = p - 1; sb >= L; --sb)
-        emit(BITONIC_LAUNCH_STEP, 1, [&] { launch_step(sb, sb == p - 1, keys, n, N, flip, st); });
-      emit(BITONIC_LAUNCH_LDS_NETWORK, 0,
+        emit(step_shape(sb, sb == p - 1),
+             [&] { launch_step(sb, sb == p - 1, keys, n, N, flip, st); });
+      emit(tile_shape(BITONIC_LAUNCH_LDS_NETWORK, L),
            [&] { launch_lds_network(L, 0, 0, true, keys, n, flip, st); });
     }
     return launches;
@@ -144,13 +157,18 @@ static int64_t enqueue_plain(int32_t* keys, uint32_t n, int K, Codec flip, const
 
   // optimized
   if (K <= r.tile) {
-    if (K < kTileMinLog2)
-      emit(BITONIC_LAUNCH_LDS_NETWORK, 0,
+    // Phases 1..K.  The scalar-access tile sorts 2^13-key tiles, which is
+    // phases 1..K only when one tile holds all n keys (K == k); fewer phases
+    // of a longer array run in the LDS network.
+    if (K < kTileMinLog2 || (r.scalar_io && K < kScalarTileLog2 && K < k))
+      emit(tile_shape(BITONIC_LAUNCH_LDS_NETWORK, K),
            [&] { launch_lds_network(K, 1, K, false, keys, n, flip, st); });
     else if (r.scalar_io)
-      emit(BITONIC_LAUNCH_TILE_SORT, 0, [&] { launch_tile_scalar(0, keys, n, flip, CX_BOTH, st); });
+      emit(tile_shape(BITONIC_LAUNCH_TILE_SORT, kScalarTileLog2),
+           [&] { launch_tile_scalar(0, keys, n, flip, CX_BOTH, st); });
     else
-      emit(BITONIC_LAUNCH_TILE_SORT, 0, [&] { launch_tile(K, 0, keys, n, flip, CX_BOTH, 0, st); });
+      emit(tile_shape(BITONIC_LAUNCH_TILE_SORT, K),
+           [&] { launch_tile(K, 0, keys, n, flip, CX_BOTH, 0, st); });
     return launches;
   }
   // The tile sort encodes the keys and the last merge decodes them; the
@@ -160,7 +178,7 @@ static int64_t enqueue_plain(int32_t* keys, uint32_t n, int K, Codec flip, const
   // a pass that straddles n takes the bounds-checked eight-step kernel, which
   // runs out of registers, so such sorts use at most seven.
   const int fuse = (r.fuse > kFuseMaxRagged && (n & (n - 1)) != 0) ? kFuseMaxRagged : r.fuse;
-  emit(BITONIC_LAUNCH_TILE_SORT, 0, [&] {
+  emit(tile_shape(BITONIC_LAUNCH_TILE_SORT, L), [&] {
     if (r.scalar_io)
       launch_tile_scalar(0, keys, n, flip, CX_ENC, st);
     else
@@ -179,7 +197,12 @@ static int64_t enqueue_plain(int32_t* keys, uint32_t n, int K, Codec flip, const
       const int passes_left = npass - i;
       const int f = fuse < left - (passes_left - 1) ? fuse : left - (passes_left - 1);
       const int q = top - f + 1;
-      emit(BITONIC_LAUNCH_GLOBAL_PASS, f, [&] {
+      // the four-column passes (f <= 5, aligned) form 32-bit byte offsets
+      // below 2^(q+2); the one-column passes follow column_pass_offset_bits
+      const bool one_col = r.scalar_io || f > kFuseMaxFourColumn;
+      const bitonic_launch_shape sh{BITONIC_LAUNCH_GLOBAL_PASS, f, q, i == 0 ? 1 : 0, 4,
+                                    one_col ? column_pass_offset_bits(4, f, q) : 32};
+      emit(sh, [&] {
         if (r.scalar_io)
           launch_column_pass_i32(f, i == 0, keys, n, q, st);
         else
@@ -188,7 +211,7 @@ static int64_t enqueue_plain(int32_t* keys, uint32_t n, int K, Codec flip, const
       top = q - 1;
     }
     const int cx = p == K ? CX_DEC : CX_NONE;
-    emit(BITONIC_LAUNCH_TILE_MERGE, 0, [&] {
+    emit(tile_shape(BITONIC_LAUNCH_TILE_MERGE, L), [&] {
       if (r.scalar_io)
         launch_tile_scalar(1, keys, n, flip, cx, st);
       else
@@ -227,7 +250,6 @@ struct DeviceState {
   std::atomic<int> cus{0};
 };
 static DeviceState g_dev[kMaxDevices];
-static std::mutex g_dev_mu;
 
 static int current_device(int* dev) {
   if (hipGetDevice(dev) != hipSuccess || *dev < 0 || *dev >= kMaxDevices) return BITONIC_EDEVICE;
@@ -243,49 +265,33 @@ static int device_cus(int dev) {
   return c;
 }
 
-// Scratch of the segmented sort, one buffer per (device, stream), grown on
-// demand and kept until the process ends.  Calls on different streams use
-// different buffers, so they may overlap; a buffer is never allocated while
-// its stream is being captured into a graph.
-struct ScratchSlot {
-  int dev;
-  hipStream_t stream;
-  void* ptr;
-  size_t bytes;
+// Scratch of the eager segmented sorts: one buffer per (device, stream),
+// grown on demand, replaced buffers retired and never freed, the stream never
+// waited for (scratch_cache.hpp).
+struct HipAlloc {
+  void* alloc(size_t bytes) {
+    void* p = nullptr;
+    return hipMalloc(&p, bytes) == hipSuccess ? p : nullptr;
+  }
 };
-static std::vector<ScratchSlot> g_scratch;
+static ScratchCache<HipAlloc> g_scratch;
+
+// An eager segmented call on a stream that is being captured into a graph
+// would bind the graph to the stream's shared, growable buffer, so that its
+// replays and later eager calls on other streams could race on it: such
+// calls are refused (BITONIC_EINVAL).  Graphs take
+// bitonic_graph_capture_segmented_i32 (a buffer of their own) or the
+// allocation-free entry point.
+static bool stream_is_capturing(hipStream_t st) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  return hipStreamIsCapturing(st, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone;
+}
 
 static int stream_scratch(int dev, hipStream_t st, size_t bytes, void** out) {
-  std::lock_guard<std::mutex> lock(g_dev_mu);
-  for (auto& s : g_scratch) {
-    if (s.dev == dev && s.stream == st) {
-      if (s.bytes >= bytes) {
-        *out = s.ptr;
-        return BITONIC_OK;
-      }
-      hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-      if (hipStreamIsCapturing(st, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
-        return BITONIC_ENOMEM;  // cannot grow inside a capture
-      // the old buffer may still be in use by earlier work on this stream
-      if (hipStreamSynchronize(st) != hipSuccess) return BITONIC_EDEVICE;
-      (void)hipFree(s.ptr);
-      s.ptr = nullptr;
-      s.bytes = 0;
-      size_t want = bytes + bytes / 2;
-      if (hipMalloc(&s.ptr, want) != hipSuccess) return BITONIC_ENOMEM;
-      s.bytes = want;
-      *out = s.ptr;
-      return BITONIC_OK;
-    }
-  }
-  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-  if (hipStreamIsCapturing(st, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
-    return BITONIC_ENOMEM;
-  void* ptr = nullptr;
-  const size_t want = bytes < (size_t(1) << 20) ? (size_t(1) << 20) : bytes;
-  if (hipMalloc(&ptr, want) != hipSuccess) return BITONIC_ENOMEM;
-  g_scratch.push_back({dev, st, ptr, want});
-  *out = ptr;
+  if (stream_is_capturing(st)) return BITONIC_EINVAL;
+  void* p = g_scratch.get(dev, st, bytes);
+  if (!p) return BITONIC_ENOMEM;
+  *out = p;
   return BITONIC_OK;
 }
 
@@ -299,33 +305,51 @@ static int bind_device(Resolved* r) {
 }
 
 // The launch sequence of one segmented sort (see kernels_segmented.hip) on
-// the given scratch buffer (seg_scratch_bytes(nseg) bytes).
-static void enqueue_segmented(const SegData& d, const int64_t* offsets, int64_t nseg,
-                              int64_t max_seg_len, void* scratch, int cus, hipStream_t st) {
-  const SegScratch sc = seg_scratch_carve(scratch, nseg);
-  launch_seg_prep(offsets, nseg, sc, st);
+// the given scratch buffer (seg_scratch_bytes(nseg) bytes); returns the
+// number of launches (enqueued unless count_only; shapes to obs, with `unit`
+// the bytes per element and array: 4 for 4-byte keys and pairs, 8 for 8-byte
+// keys).  The kernels index segments through 64-bit pointers.
+static int64_t enqueue_segmented(const SegData& d, const int64_t* offsets, int64_t nseg,
+                                 int64_t max_seg_len, void* scratch, int cus, hipStream_t st,
+                                 bool count_only = false, Observer* obs = nullptr,
+                                 int unit = 4) {
+  int64_t launches = 0;
+  auto emit = [&](bitonic_launch_shape sh, auto&& launch) {
+    if (!count_only) launch();
+    if (obs && launches < obs->cap && obs->shapes) obs->shapes[launches] = sh;
+    ++launches;
+  };
+  const SegScratch sc = count_only ? SegScratch{} : seg_scratch_carve(scratch, nseg);
+  emit({BITONIC_LAUNCH_SEG_PREP, 0, 0, 0, unit, 64},
+       [&] { launch_seg_prep(offsets, nseg, sc, st); });
   const int64_t slots = (int64_t)cus * g_seg_bpc.load();
   const int small_grid = (int)(slots < nseg ? slots : nseg);
-  launch_seg_small(d, offsets, sc, small_grid, st);
+  emit({BITONIC_LAUNCH_SEG_SMALL, 0, kSegSmallMaxLog2, 0, unit, 64},
+       [&] { launch_seg_small(d, offsets, sc, small_grid, st); });
   const int M = ceil_log2(max_seg_len);
-  if (M <= 13) return;
+  if (M <= kSegSmallMaxLog2) return launches;
+  const int T = kSegSmallMaxLog2;  // big segments run 2^13-element tiles
   const int grid = cus * 4;
   const int pass_grid = cus * g_seg_pass_bpc.load();
-  launch_seg_tiles(false, d, offsets, sc, 14, grid, st);
+  emit({BITONIC_LAUNCH_TILE_SORT, 0, T, 0, unit, 64},
+       [&] { launch_seg_tiles(false, d, offsets, sc, T + 1, grid, st); });
   const int fuse = g_fuse.load() < kSegFuseMax ? g_fuse.load() : kSegFuseMax;
-  for (int p = 14; p <= M; ++p) {
-    const int nb = p - 13;
+  for (int p = T + 1; p <= M; ++p) {
+    const int nb = p - T;
     const int npass = (nb + fuse - 1) / fuse;
     int top = p - 1;
     for (int i = 0; i < npass; ++i) {
-      const int left = top - 13 + 1;
+      const int left = top - T + 1;
       const int f = (left + (npass - i) - 1) / (npass - i);
       const int q = top - f + 1;
-      launch_seg_pass(f, i == 0, d, offsets, sc, p, q, pass_grid, st);
+      emit({BITONIC_LAUNCH_GLOBAL_PASS, f, q, i == 0 ? 1 : 0, unit, 64},
+           [&] { launch_seg_pass(f, i == 0, d, offsets, sc, p, q, pass_grid, st); });
       top = q - 1;
     }
-    launch_seg_tiles(true, d, offsets, sc, p, grid, st);
+    emit({BITONIC_LAUNCH_TILE_MERGE, 0, T, 0, unit, 64},
+         [&] { launch_seg_tiles(true, d, offsets, sc, p, grid, st); });
   }
+  return launches;
 }
 
 }  // namespace bitonic
@@ -383,21 +407,28 @@ static int capture_graph(bitonic_graph** out, void* scratch, F&& enqueue) {
 // long strides in passes of at most F steps and its last L strides in a tile
 // merge -- the optimized plan of the 4-byte sort on 8-byte elements.  Returns
 // the number of launches (enqueued unless count_only).
+// With `unit` 4 (pairs: a 4-byte key and a 4-byte value array) or 8 (8-byte
+// keys) for the shapes written to obs (bitonic_plan_shapes).
 static int64_t enqueue_wide(int64_t* k64, int32_t* k32, int32_t* vals, uint32_t n, Codec64 cd,
-                            int L, int F, hipStream_t st, bool count_only) {
+                            int L, int F, hipStream_t st, bool count_only,
+                            Observer* obs = nullptr, int unit = 8) {
   const int K = ceil_log2(n);
   if (K <= 0) return 0;
   int64_t launches = 0;
-  auto emit = [&](auto&& launch) {
+  auto emit = [&](bitonic_launch_shape sh, auto&& launch) {
     if (!count_only) launch();
+    if (obs && launches < obs->cap && obs->shapes) obs->shapes[launches] = sh;
     ++launches;
   };
+  auto tile_shape = [&](int kind, int Lt) { return bitonic_launch_shape{kind, 0, Lt, 0, unit, 64}; };
   if (K <= L) {
     const int Lt = K < kWideTileMinLog2 ? kWideTileMinLog2 : K;
-    emit([&] { launch_wide_tile(Lt, 0, k64, k32, vals, n, cd, CX_BOTH, st); });
+    emit(tile_shape(BITONIC_LAUNCH_TILE_SORT, Lt),
+         [&] { launch_wide_tile(Lt, 0, k64, k32, vals, n, cd, CX_BOTH, st); });
     return launches;
   }
-  emit([&] { launch_wide_tile(L, 0, k64, k32, vals, n, cd, CX_ENC, st); });
+  emit(tile_shape(BITONIC_LAUNCH_TILE_SORT, L),
+       [&] { launch_wide_tile(L, 0, k64, k32, vals, n, cd, CX_ENC, st); });
   for (int p = L + 1; p <= K; ++p) {
     const int nb = p - L;
     const int npass = (nb + F - 1) / F;
@@ -407,11 +438,14 @@ static int64_t enqueue_wide(int64_t* k64, int32_t* k32, int32_t* vals, uint32_t 
       const int passes_left = npass - i;
       const int f = F < left - (passes_left - 1) ? F : left - (passes_left - 1);
       const int q = top - f + 1;
-      emit([&] { launch_wide_pass(f, i == 0, k64, k32, vals, n, q, st); });
+      const bitonic_launch_shape sh{BITONIC_LAUNCH_GLOBAL_PASS, f, q, i == 0 ? 1 : 0, unit,
+                                    column_pass_offset_bits((uint32_t)unit, f, q)};
+      emit(sh, [&] { launch_wide_pass(f, i == 0, k64, k32, vals, n, q, st); });
       top = q - 1;
     }
     const int cx = p == K ? CX_DEC : CX_NONE;
-    emit([&] { launch_wide_tile(L, 1, k64, k32, vals, n, cd, cx, st); });
+    emit(tile_shape(BITONIC_LAUNCH_TILE_MERGE, L),
+         [&] { launch_wide_tile(L, 1, k64, k32, vals, n, cd, cx, st); });
   }
   return launches;
 }
@@ -581,6 +615,43 @@ int64_t bitonic_plan_describe(int64_t n, const bitonic_plan* plan, int32_t* kind
   obs.fuse = fuse;
   obs.cap = cap;
   return enqueue_plain(nullptr, (uint32_t)n, 64, Codec{0, 0}, r, nullptr, true, &obs);
+}
+
+int64_t bitonic_plan_shapes(int64_t n, int layout, const bitonic_plan* plan,
+                            bitonic_launch_shape* shapes, int64_t cap) {
+  if (n < 0 || n > (int64_t(1) << 31) || cap < 0) return -1;
+  Observer obs;
+  obs.shapes = shapes;
+  obs.cap = shapes ? cap : 0;
+  switch (layout) {
+    case BITONIC_LAYOUT_KEYS32:
+    case BITONIC_LAYOUT_KEYS32_UNALIGNED: {
+      Resolved r;
+      if (resolve(plan, n, &r)) return -1;
+      if (n <= 1) return 0;
+      if (layout == BITONIC_LAYOUT_KEYS32_UNALIGNED)
+        fit_alignment(reinterpret_cast<const int32_t*>(uintptr_t(4)), &r);
+      return enqueue_plain(nullptr, (uint32_t)n, 64, Codec{0, 0}, r, nullptr, true, &obs);
+    }
+    case BITONIC_LAYOUT_KEYS64:
+    case BITONIC_LAYOUT_PAIRS: {
+      int L = 0, F = 0;
+      if (resolve_wide(plan, &L, &F)) return -1;
+      if (n <= 1) return 0;
+      return enqueue_wide(nullptr, nullptr, nullptr, (uint32_t)n, Codec64{0, 0}, L, F, nullptr,
+                          true, &obs, layout == BITONIC_LAYOUT_KEYS64 ? 8 : 4);
+    }
+    case BITONIC_LAYOUT_SEG_KEYS32:
+    case BITONIC_LAYOUT_SEG_PAIRS:
+    case BITONIC_LAYOUT_SEG_KEYS64: {
+      if (n == 0) return 0;
+      SegData d{};
+      return enqueue_segmented(d, nullptr, 1, n, nullptr, 256, nullptr, true, &obs,
+                               layout == BITONIC_LAYOUT_SEG_KEYS64 ? 8 : 4);
+    }
+    default:
+      return -1;
+  }
 }
 
 int bitonic_sort_plan_events_i32(int32_t* keys, int64_t n, int ascending,

@@ -9,13 +9,17 @@
 // kPadE the sentinel of the sorting domain for indices >= n.
 #pragma once
 
+#include <type_traits>
+
 #include "device.hpp"
+#include "launch.hpp"
 
 namespace bitonic {
 
 // get/put take an element index; getb/putb take the index times kUnit as a
-// 32-bit byte offset, so a uniform base plus a lane offset maps onto the
-// scalar-base + vector-offset global addressing form.
+// byte offset, 32-bit wherever it fits (pass_offset_bits), so a uniform base
+// plus a lane offset maps onto the scalar-base + vector-offset global
+// addressing form.
 struct Keys32 {
   using E = int32_t;
   static constexpr E kPadE = kPad;
@@ -24,10 +28,12 @@ struct Keys32 {
   __device__ __forceinline__ int32_t get(uint32_t i) const { return k[i]; }
   __device__ __forceinline__ void put(uint32_t i, int32_t x) const { k[i] = x; }
   __device__ __forceinline__ Keys32 at(size_t i) const { return Keys32{k + i}; }
-  __device__ __forceinline__ int32_t getb(uint32_t b) const {
+  template <class O>
+  __device__ __forceinline__ int32_t getb(O b) const {
     return *reinterpret_cast<const int32_t*>(reinterpret_cast<const char*>(k) + b);
   }
-  __device__ __forceinline__ void putb(uint32_t b, int32_t x) const {
+  template <class O>
+  __device__ __forceinline__ void putb(O b, int32_t x) const {
     *reinterpret_cast<int32_t*>(reinterpret_cast<char*>(k) + b) = x;
   }
 };
@@ -40,10 +46,12 @@ struct Keys64 {
   __device__ __forceinline__ int64_t get(uint32_t i) const { return k[i]; }
   __device__ __forceinline__ void put(uint32_t i, int64_t x) const { k[i] = x; }
   __device__ __forceinline__ Keys64 at(size_t i) const { return Keys64{k + i}; }
-  __device__ __forceinline__ int64_t getb(uint32_t b) const {
+  template <class O>
+  __device__ __forceinline__ int64_t getb(O b) const {
     return *reinterpret_cast<const int64_t*>(reinterpret_cast<const char*>(k) + b);
   }
-  __device__ __forceinline__ void putb(uint32_t b, int64_t x) const {
+  template <class O>
+  __device__ __forceinline__ void putb(O b, int64_t x) const {
     *reinterpret_cast<int64_t*>(reinterpret_cast<char*>(k) + b) = x;
   }
 };
@@ -62,12 +70,14 @@ struct Pairs {
   }
   __device__ __forceinline__ Pairs at(size_t i) const { return Pairs{k + i, v + i}; }
   static constexpr uint32_t kUnit = 4;
-  __device__ __forceinline__ int64_t getb(uint32_t b) const {
+  template <class O>
+  __device__ __forceinline__ int64_t getb(O b) const {
     const uint32_t hi = *reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(k) + b);
     const uint32_t lo = *reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(v) + b);
     return (int64_t)(((uint64_t)hi << 32) | lo);
   }
-  __device__ __forceinline__ void putb(uint32_t b, int64_t x) const {
+  template <class O>
+  __device__ __forceinline__ void putb(O b, int64_t x) const {
     *reinterpret_cast<int32_t*>(reinterpret_cast<char*>(k) + b) = (int32_t)((uint64_t)x >> 32);
     *reinterpret_cast<int32_t*>(reinterpret_cast<char*>(v) + b) = (int32_t)(uint32_t)(uint64_t)x;
   }
@@ -81,13 +91,16 @@ struct Pairs {
 // Consecutive threads own consecutive columns, so every row access is
 // coalesced.  Since 256 divides 2^q a workgroup stays inside one block, so a
 // row's address is a workgroup-uniform row start plus the lane's column (or
-// its mirror image) as a 32-bit byte offset, which keeps few vector
+// its mirror image) as a byte offset (32-bit wherever it fits), which keeps few vector
 // registers live.  BOUNDED == false: the whole block lies below n and nothing
 // is checked.  BOUNDED == true: indices >= n read as sentinels and are not
-// stored.
-template <int F, bool MIRROR, bool BOUNDED, class ST>
+// stored.  OFF64: the lane byte offsets are formed in 64 bits, for rows of
+// 2^q elements of kUnit bytes that span more than 2^32 bytes (8-byte
+// elements at q = 30; see column_pass_offset_bits).
+template <int F, bool MIRROR, bool BOUNDED, class ST, bool OFF64 = false>
 __global__ __launch_bounds__(256) void column_pass_kernel(ST st, uint32_t n, int q, uint32_t g0) {
   using E = typename ST::E;
+  using Off = std::conditional_t<OFF64, uint64_t, uint32_t>;
   constexpr int ROWS = 1 << F;
   constexpr int TOP = ROWS >> 1;
   E x[ROWS];
@@ -97,8 +110,8 @@ __global__ __launch_bounds__(256) void column_pass_kernel(ST st, uint32_t n, int
   const uint32_t mcol = ((1u << q) - 1u) - col;
   // the thread's lowest index is bs + col; its mirrored rows lie higher
   if (BOUNDED && bs + col >= n) return;
-  const uint32_t off = col * ST::kUnit;                       // byte offsets, < 2^(q+3)
-  const uint32_t moff = mcol * ST::kUnit;
+  const Off off = (Off)col * ST::kUnit;                       // byte offsets, < 2^q kUnit
+  const Off moff = (Off)mcol * ST::kUnit;
   auto row_of = [&](int rho) -> uint32_t {                    // uniform row
     return (MIRROR && (rho & TOP)) ? (uint32_t)(ROWS - 1 - (rho & (TOP - 1))) : (uint32_t)rho;
   };
@@ -130,18 +143,32 @@ __global__ __launch_bounds__(256) void column_pass_kernel(ST st, uint32_t n, int
   });
 }
 
-template <int F, bool MIRROR, class ST>
-static void launch_column_pass_FM(ST st, uint32_t n, int q, hipStream_t s) {
+template <int F, bool MIRROR, class ST, bool OFF64>
+static void launch_column_pass_FMO(ST st, uint32_t n, int q, hipStream_t s) {
   // 2^q threads per 2^(q+F) block: blocks wholly below n take the unchecked
   // kernel, the block that straddles n (if any) the checked one
   const uint64_t full = ((uint64_t)n >> (q + F)) << q;   // a multiple of 256 (q >= 8)
   const uint64_t blocks = ((uint64_t)n + (1ull << (q + F)) - 1) >> (q + F);
   const uint64_t total = blocks << q;
   if (full > 0)
-    column_pass_kernel<F, MIRROR, false, ST><<<(uint32_t)(full / 256), 256, 0, s>>>(st, n, q, 0u);
+    column_pass_kernel<F, MIRROR, false, ST, OFF64><<<(uint32_t)(full / 256), 256, 0, s>>>(
+        st, n, q, 0u);
   if (total > full)
-    column_pass_kernel<F, MIRROR, true, ST><<<(uint32_t)((total - full + 255) / 256), 256, 0, s>>>(
-        st, n, q, (uint32_t)full);
+    column_pass_kernel<F, MIRROR, true, ST, OFF64>
+        <<<(uint32_t)((total - full + 255) / 256), 256, 0, s>>>(st, n, q, (uint32_t)full);
+}
+
+template <int F, bool MIRROR, class ST>
+static void launch_column_pass_FM(ST st, uint32_t n, int q, hipStream_t s) {
+  // 64-bit offsets only where column_pass_offset_bits asks for them (one-step
+  // passes of 8-byte elements), so only those are instantiated
+  if constexpr (F == 1 && ST::kUnit > 4) {
+    if (column_pass_offset_bits(ST::kUnit, F, q) > 32) {
+      launch_column_pass_FMO<F, MIRROR, ST, true>(st, n, q, s);
+      return;
+    }
+  }
+  launch_column_pass_FMO<F, MIRROR, ST, false>(st, n, q, s);
 }
 
 template <int F, class ST>

@@ -9,6 +9,7 @@
 namespace bitonic {
 
 constexpr int kTileRegLogPlain = 5;  // 32 keys per thread in the tile kernels
+constexpr int kFuseMaxFourColumn = 5;  // wider aligned passes take the one-column kernel
 constexpr int kTileMinLog2 = 11;
 constexpr int kTileMaxLog2 = 15;
 constexpr int kFuseMax = 8;
@@ -67,6 +68,18 @@ void launch_wide_tile(int L, int kind, int64_t* keys64, int32_t* keys32, int32_t
 // Requires q + f <= 31, 1 <= f <= kWideFuseMax.
 void launch_wide_pass(int f, bool mirror, int64_t* keys64, int32_t* keys32, int32_t* values,
                       uint32_t n, int q, hipStream_t st);
+
+// Width of the lane byte offsets a one-column pass forms for rows of 2^q
+// elements of `unit` bytes: 32 bits while 2^q * unit <= 2^32, else 64.  Sorts
+// hold n <= 2^31 elements and q + f <= 31, so only one-step passes of 8-byte
+// elements at q = 30 (phase 31) need 64; the launcher instantiates the
+// 64-bit form for exactly those (column_pass.hpp).
+constexpr int pass_offset_bits(uint32_t unit, int q) {
+  return ((uint64_t)unit << q) <= (uint64_t(1) << 32) ? 32 : 64;
+}
+constexpr int column_pass_offset_bits(uint32_t unit, int f, int q) {
+  return (f == 1 && unit > 4) ? pass_offset_bits(unit, q) : 32;
+}
 
 // Input generator.
 void launch_keygen(int32_t* out, uint64_t n, uint64_t seed, uint64_t start, hipStream_t st);

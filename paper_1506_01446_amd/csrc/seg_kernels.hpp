@@ -14,7 +14,7 @@
 
 namespace bitonic {
 
-constexpr int kSegTileLog = 13;
+constexpr int kSegTileLog = kSegSmallMaxLog2;  // big segments: 2^13-element tiles
 constexpr int kSegThreads = 256;
 
 __device__ __forceinline__ int ceil_log2_u64(uint64_t n) {

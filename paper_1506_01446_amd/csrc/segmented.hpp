@@ -9,6 +9,7 @@
 namespace bitonic {
 
 constexpr int kTileRegLogSeg = 5;  // 32 keys per thread
+constexpr int kSegSmallMaxLog2 = 13;  // segments of up to 2^13 keys are "small"
 constexpr int kSmallClasses = 9;   // classes 13, 12, ..., 6 and "<= 5"
 constexpr int kSegFuseMax = 3;
 

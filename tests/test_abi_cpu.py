@@ -215,3 +215,83 @@ def test_bench_traffic_lookup(monkeypatch):
     monkeypatch.setattr(bench, "kernel_source_hash", lambda: "0000000000000000")
     assert bench.committed_traffic("tile_merge", 1 << 24) is None
     assert bench.committed_traffic("tile_merge", 12345) is None
+
+
+def _ceil_log2(n):
+    return max(0, (n - 1).bit_length())
+
+
+# n = 2^k, 2^k - 1 (k = 1..31) and the first size past 2^30 that is not a
+# power of two, where phase 31's mirror step can run as a pass on its own
+SHAPE_SIZES = sorted({2**k for k in range(1, 32)} | {2**k - 1 for k in range(2, 32)}
+                     | {2**30 + 2**20})
+
+
+def _check_shapes(shapes, n, elem_bytes):
+    k = _ceil_log2(n)
+    for s in shapes:
+        assert s["elem_bytes"] == elem_bytes
+        # every byte offset a kernel adds to a row (pass, step) or tile start
+        # fits its width: rows of 2^q elements span 2^q * elem_bytes bytes
+        assert (1 << s["q"]) * s["elem_bytes"] <= 2 ** s["offset_bits"], (n, s)
+        if s["kind"] in ("global_pass", "step"):
+            assert 1 <= s["fuse"] and s["q"] + s["fuse"] <= k <= 31, (n, s)
+
+
+@pytest.mark.parametrize("layout", ["keys32", "keys32_unaligned"])
+def test_plan_shapes_4byte(lib, layout):
+    """Every launch shape the 4-byte planner can emit for n <= 2^31, under
+    every optimized plan and the Basic and Semi plans, keeps its byte
+    offsets within their width; the shapes are the plan's launches."""
+    plans = [None, "basic", ("semi", 8), ("semi", 13)] + \
+        [("optimized", t, f) for t in (11, 12, 13, 14, 15) for f in range(1, 9)]
+    for plan in plans:
+        for n in SHAPE_SIZES:
+            sh = B.bitonic_plan_shapes(n, layout, plan)
+            if layout == "keys32":
+                assert len(sh) == B.bitonic_plan_passes(n, plan), (plan, n)
+            _check_shapes(sh, n, 4)
+
+
+@pytest.mark.parametrize("layout,unit", [("keys64", 8), ("pairs", 4)])
+def test_plan_shapes_8byte(lib, layout, unit):
+    """The 8-byte planner under every accepted plan (tiles 2^11..2^13, 1..6
+    fused steps) for n <= 2^31: every pass keeps its byte offsets within
+    their width.  One-step passes of phase 31 over 8-byte keys span 2^33
+    bytes per row, so they must take 64-bit offsets."""
+    wide_q30 = 0
+    for t in (11, 12, 13):
+        for f in range(1, 7):
+            plan = ("optimized", t, f)
+            for n in SHAPE_SIZES:
+                sh = B.bitonic_plan_shapes(n, layout, plan)
+                assert len(sh) == B.bitonic_wide_plan_passes(n, plan), (plan, n)
+                _check_shapes(sh, n, unit)
+                wide_q30 += sum(1 for s in sh if s["kind"] == "global_pass" and s["q"] == 30)
+    assert wide_q30 > 0   # the case that needs 64-bit offsets is reached
+    sh = B.bitonic_plan_shapes(2**30 + 2**20, layout, ("optimized", 13, 1))
+    q30 = [s for s in sh if s["kind"] == "global_pass" and s["q"] == 30]
+    assert q30 and all(s["offset_bits"] == (64 if unit == 8 else 32) for s in q30)
+
+
+@pytest.mark.parametrize("layout,unit", [("seg_keys32", 4), ("seg_pairs", 4),
+                                         ("seg_keys64", 8)])
+def test_plan_shapes_segmented(lib, layout, unit):
+    """The segmented planner, for a longest segment of 1..2^31 elements:
+    prep, the small-segment kernel, and for segments past 2^13 elements the
+    tile sort and per phase its passes (at most three steps each) and merge."""
+    for k in range(0, 32):
+        n = 2**k
+        sh = B.bitonic_plan_shapes(n, layout)
+        assert [s["kind"] for s in sh[:2]] == ["seg_prep", "seg_small"]
+        _check_shapes(sh, n, unit)
+        if k <= 13:
+            assert len(sh) == 2
+            continue
+        assert sh[2]["kind"] == "tile_sort" and sh[2]["q"] == 13
+        merges = [s for s in sh if s["kind"] == "tile_merge"]
+        passes = [s for s in sh if s["kind"] == "global_pass"]
+        assert len(merges) == k - 13
+        assert all(s["fuse"] <= 3 for s in passes)
+        # every phase p > 13 performs steps on bits p-1 .. 13 exactly once
+        assert sum(s["fuse"] for s in passes) == sum(p - 13 for p in range(14, k + 1))

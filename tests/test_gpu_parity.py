@@ -136,6 +136,26 @@ def test_per_phase_states(plan):
         assert np.array_equal(t.cpu().numpy(), states[p]), (plan, p)
 
 
+@pytest.mark.parametrize("shift", [1, 2, 3])
+def test_per_phase_states_unaligned(shift):
+    """The same on views 1-3 keys past a 16-byte boundary, which take the
+    scalar-access plan (2^13-key tiles): phases 1..p for p below the tile
+    size must stop at p, not run the whole tile."""
+    n = (1 << 15) + 1234
+    keys = W.uniform_i32(78 + shift, n)
+    states = {}
+    O.bitonic_i32(keys, True, O.FLIP_VIRTUAL,
+                  hook=lambda p, s, x: states.__setitem__(p, x) if s == p else None)
+    buf = torch.zeros(n + 4, dtype=torch.int32, device="cuda")
+    for p in sorted(states):
+        buf[shift:shift + n] = torch.from_numpy(keys).cuda()
+        v = buf[shift:shift + n]
+        assert v.data_ptr() % 16 != 0
+        B.bitonic_network_phases_i32(v, p, True)
+        torch.cuda.synchronize()
+        assert np.array_equal(v.cpu().numpy(), states[p]), (shift, p)
+
+
 def test_guard_bands():
     n = 300001
     keys = W.uniform_i32(9, n)

@@ -205,6 +205,37 @@ def test_int64_maximum_size():
     torch.cuda.empty_cache()
 
 
+def test_int64_one_step_passes_past_2_30():
+    """int64 keys, n = 2^30 + 2^20, 2^13-element tiles and one step per pass:
+    the mirror pass of phase 31 runs on its own at q = 30, where a row spans
+    2^33 bytes, past what 32-bit byte offsets reach (the pass then forms
+    64-bit offsets).  Checked by order, two multiset hashes, the extremes and
+    sampled order statistics counted in the input (section 3.3: one step per
+    launch at any n)."""
+    n = (1 << 30) + (1 << 20)
+    plan = ("optimized", 13, 1)
+    shapes = B.bitonic_plan_shapes(n, "keys64", plan)
+    assert any(s["kind"] == "global_pass" and s["q"] == 30 and s["offset_bits"] == 64
+               for s in shapes)
+    print(f"[case] int64 one-step passes n={n} plan={plan}", flush=True)
+    t = _i64_on_device(n, W.SEED_BASE + 96)
+    h0 = _hash64(t)
+    lo, hi = int(t.min().item()), int(t.max().item())
+    src = t.clone()
+    B.bitonic_sort_wide_plan(t, None, True, "int64", plan)
+    torch.cuda.synchronize()
+    assert _sorted64(t)
+    assert _hash64(t) == h0
+    assert int(t[0].item()) == lo and int(t[-1].item()) == hi
+    for i in (0, 1 << 29, (1 << 30) - 1, 1 << 30, (1 << 30) + 1, n // 3, n - 1):
+        v = int(t[i].item())
+        below = int((src < v).sum().item())
+        upto = int((src <= v).sum().item())
+        assert below <= i < upto, i
+    del src, t
+    torch.cuda.empty_cache()
+
+
 def test_pairs_maximum_size():
     """n = 2^31 - 1 pairs with values 0..n-1: every output pair is an input
     pair (key == input key at the value's index), the values are a
