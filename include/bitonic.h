@@ -33,11 +33,13 @@
  *    (same result).
  *  - Errors in the arguments are reported synchronously and nothing is
  *    enqueued.  No exception crosses this interface.
- *  - Calls are reentrant on different streams.  The segmented sort uses a
- *    scratch buffer per (device, stream) that the library allocates on first
- *    use on that stream (or when a larger one is needed, after waiting for
- *    the stream); segmented calls on one stream are ordered by the stream,
- *    calls on different streams use different buffers.
+ *  - Calls are reentrant on different streams.  The eager segmented sorts
+ *    use a scratch buffer per (device, stream) that the library allocates on
+ *    first use on that stream, and replaces by a larger one when a call needs
+ *    more; a replaced buffer is kept (never freed) until the process ends,
+ *    since work enqueued earlier may still use it, so no call waits for the
+ *    stream.  Segmented calls on one stream are ordered by the stream, calls
+ *    on different streams use different buffers.
  */
 #ifndef BITONIC_MI355X_H
 #define BITONIC_MI355X_H
@@ -138,10 +140,18 @@ int bitonic_sort_pairs(void* keys, int32_t* values, int64_t n, int key_type, int
  *   nseg       number of segments, >= 0; 0 enqueues nothing
  *   ascending  as above, for every segment
  *   stream     hipStream_t
- * The launch sequence depends on the largest segment: this call reads
- * offsets[0] and offsets[nseg] back to the host (one blocking copy on
- * `stream`) to bound it.  bitonic_sort_segmented_bounded_i32 takes the bound
- * from the caller and never blocks.  Bad offsets are undefined behaviour.
+ * The call only enqueues work; it never reads the offsets on the host and
+ * never waits.  How many merge phases it enqueues depends on a bound on the
+ * segment length: here the number of keys from `keys` to the end of the
+ * device allocation that holds them (the runtime's allocation records,
+ * consulted on the host), or 2^31 where that is unknown.  Phases past the
+ * longest segment actually present find no segment of their class on the
+ * device and return at once, at the cost of their launches (a few
+ * microseconds each); bitonic_sort_segmented_bounded_i32 with a tight bound
+ * enqueues only the phases needed.  Bad offsets are undefined behaviour.
+ * Calls on a stream that is being captured into a graph are refused
+ * (BITONIC_EINVAL): the graph would share the stream's scratch buffer with
+ * later eager calls; capture bitonic_graph_capture_segmented_i32 instead.
  * Returns BITONIC_OK, BITONIC_EINVAL, BITONIC_ENOMEM (scratch), BITONIC_EDEVICE
  * or BITONIC_ELAUNCH.
  */
@@ -150,15 +160,14 @@ int bitonic_sort_segmented_i32(int32_t* keys, const int64_t* offsets,
 
 /*
  * As bitonic_sort_segmented_i32, with a host-side bound: every segment holds
- * at most max_seg_len keys (0 = unknown: then offsets[0] and offsets[nseg]
- * are read back, as above).  With a bound the call only enqueues work and can
- * be captured into a HIP graph (once the stream's scratch buffer is large
- * enough: the buffer is never allocated during a capture, BITONIC_ENOMEM).
- * The bound fixes how many merge phases are enqueued; a segment longer than
- * the bound is undefined behaviour.  Launches: a prep kernel, one persistent
- * kernel for all segments of up to 2^13 keys, and, if the bound exceeds 2^13,
- * one tile-sort launch plus, per phase p = 14 .. ceil(log2 bound), the fused
- * long-stride passes and one tile merge.
+ * at most max_seg_len keys (0 = unknown: then the bound of
+ * bitonic_sort_segmented_i32 is taken).  The bound fixes how many merge
+ * phases are enqueued; a segment longer than the bound is undefined
+ * behaviour.  Launches: a prep kernel, one persistent kernel for all segments
+ * of up to 2^13 keys, and, if the bound exceeds 2^13, one tile-sort launch
+ * plus, per phase p = 14 .. ceil(log2 bound), its fused long-stride passes
+ * (at most "seg_fuse" steps each, default 5) and one tile merge.  Like
+ * bitonic_sort_segmented_i32 it refuses a capturing stream.
  */
 int bitonic_sort_segmented_bounded_i32(int32_t* keys, const int64_t* offsets,
                                        int64_t nseg, int64_t max_seg_len,
@@ -371,7 +380,8 @@ int bitonic_sort_plan_launches_i32(int32_t* keys, int64_t n, int ascending,
  * one value by name: "tile_log2" (0 restores the choice by n), "fuse",
  * "merge_blocks_per_cu" (as in bitonic_plan), "seg_blocks_per_cu" (1..16, workgroups per compute unit of
  * the persistent small-segment kernel), "seg_pass_blocks_per_cu" (1..32,
- * workgroups per compute unit of the big-segment passes, default 8), "wide_tile_log2" (11..13) or
+ * workgroups per compute unit of the big-segment passes, default 8),
+ * "seg_fuse" (1..5, steps per big-segment pass, default 5), "wide_tile_log2" (11..13) or
  * "wide_fuse" (1..6) (the 8-byte sorts' plan); bitonic_get_tuning_value
  * reads one.
  * bitonic_load_tuning reads "<name> <value>" lines (the autotuner's output

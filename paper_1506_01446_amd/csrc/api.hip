@@ -36,6 +36,7 @@ static std::atomic<int> g_wide_tile_log2{13};  // 8-byte sorts
 static std::atomic<int> g_wide_fuse{6};
 static std::atomic<int> g_seg_bpc{4};    // small-segment workgroups per compute unit
 static std::atomic<int> g_seg_pass_bpc{8};  // big-segment pass workgroups per compute unit
+static std::atomic<int> g_seg_fuse{kSegFuseMax};  // steps per big-segment pass
 
 struct Resolved {
   int kind;
@@ -280,8 +281,7 @@ static ScratchCache<HipAlloc> g_scratch;
 // would bind the graph to the stream's shared, growable buffer, so that its
 // replays and later eager calls on other streams could race on it: such
 // calls are refused (BITONIC_EINVAL).  Graphs take
-// bitonic_graph_capture_segmented_i32 (a buffer of their own) or the
-// allocation-free entry point.
+// bitonic_graph_capture_segmented_i32 (a buffer of their own).
 static bool stream_is_capturing(hipStream_t st) {
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   return hipStreamIsCapturing(st, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone;
@@ -333,7 +333,7 @@ static int64_t enqueue_segmented(const SegData& d, const int64_t* offsets, int64
   const int pass_grid = cus * g_seg_pass_bpc.load();
   emit({BITONIC_LAUNCH_TILE_SORT, 0, T, 0, unit, 64},
        [&] { launch_seg_tiles(false, d, offsets, sc, T + 1, grid, st); });
-  const int fuse = g_fuse.load() < kSegFuseMax ? g_fuse.load() : kSegFuseMax;
+  const int fuse = g_seg_fuse.load();
   for (int p = T + 1; p <= M; ++p) {
     const int nb = p - T;
     const int npass = (nb + fuse - 1) / fuse;
@@ -702,6 +702,28 @@ int bitonic_sort_segmented_bounded_i32(int32_t* keys, const int64_t* offsets, in
                                      stream);
 }
 
+// A bound on the segment length when the caller gives none, found without
+// reading the offsets: no segment reaches past the end of the device
+// allocation that holds the keys (hipMemGetAddressRange consults the
+// runtime's allocation records on the host; nothing is enqueued or waited
+// for).  Where the range is unknown the bound is 2^31.  The phases between the
+// longest segment present and this bound find no segment of their class on
+// the device and return at once.
+static int64_t allocation_bound(const void* keys, int elem_bytes) {
+  const int64_t cap = int64_t(1) << 31;
+  void* base = nullptr;
+  size_t size = 0;
+  if (hipMemGetAddressRange(&base, &size, const_cast<void*>(keys)) != hipSuccess || !base) {
+    (void)hipGetLastError();
+    return cap;
+  }
+  const uintptr_t end = reinterpret_cast<uintptr_t>(base) + size;
+  const uintptr_t at = reinterpret_cast<uintptr_t>(keys);
+  if (end <= at) return cap;
+  const int64_t elems = (int64_t)((end - at) / (uintptr_t)elem_bytes);
+  return elems < 1 ? 1 : (elems < cap ? elems : cap);
+}
+
 // Segmented sort of keys of any key type (values == nullptr) or of (key,
 // value) pairs with 4-byte keys.
 static int sort_segmented(void* keys_v, int32_t* values, const int64_t* offsets, int64_t nseg,
@@ -722,18 +744,7 @@ static int sort_segmented(void* keys_v, int32_t* values, const int64_t* offsets,
   int dev = 0;
   int rc = current_device(&dev);
   if (rc) return rc;
-  if (max_seg_len == 0) {
-    // No bound given: read the first and last offsets (a blocking copy).
-    int64_t ends[2] = {0, 0};
-    if (hipMemcpyAsync(&ends[0], offsets, sizeof(int64_t), hipMemcpyDeviceToHost, st) != hipSuccess ||
-        hipMemcpyAsync(&ends[1], offsets + nseg, sizeof(int64_t), hipMemcpyDeviceToHost, st) !=
-            hipSuccess ||
-        hipStreamSynchronize(st) != hipSuccess)
-      return BITONIC_EDEVICE;
-    max_seg_len = ends[1] - ends[0];
-    if (max_seg_len < 0) return BITONIC_EINVAL;
-    if (max_seg_len > (int64_t(1) << 31)) max_seg_len = int64_t(1) << 31;
-  }
+  if (max_seg_len == 0) max_seg_len = allocation_bound(keys_v, wide_keys ? 8 : 4);
   void* base = nullptr;
   rc = stream_scratch(dev, st, seg_scratch_bytes(nseg), &base);
   if (rc) return rc;
@@ -803,6 +814,11 @@ int bitonic_set_tuning_value(const char* key, int value) {
     g_seg_pass_bpc.store(value);
     return BITONIC_OK;
   }
+  if (!std::strcmp(key, "seg_fuse")) {
+    if (value < 1 || value > kSegFuseMax) return BITONIC_EINVAL;
+    g_seg_fuse.store(value);
+    return BITONIC_OK;
+  }
   if (!std::strcmp(key, "wide_tile_log2")) {
     if (value < kWideTileMinLog2 || value > kWideTileMaxLog2) return BITONIC_EINVAL;
     g_wide_tile_log2.store(value);
@@ -823,6 +839,7 @@ int bitonic_get_tuning_value(const char* key, int* value) {
   else if (!std::strcmp(key, "merge_blocks_per_cu")) *value = g_merge_bpc.load() ? g_merge_bpc.load() : -1;
   else if (!std::strcmp(key, "seg_blocks_per_cu")) *value = g_seg_bpc.load();
   else if (!std::strcmp(key, "seg_pass_blocks_per_cu")) *value = g_seg_pass_bpc.load();
+  else if (!std::strcmp(key, "seg_fuse")) *value = g_seg_fuse.load();
   else if (!std::strcmp(key, "wide_tile_log2")) *value = g_wide_tile_log2.load();
   else if (!std::strcmp(key, "wide_fuse")) *value = g_wide_fuse.load();
   else return BITONIC_EINVAL;

@@ -223,6 +223,12 @@ __global__ __launch_bounds__(seg_tile_threads<ST>()) void seg_tile_kernel(
   }
 }
 
+// Columns per thread of a big-segment pass of F steps: 4 up to F = 3, then
+// fewer as the rows double, so that a thread holds at most 32 elements
+// (2^F rows x the columns).
+constexpr int seg_pass_cols(int F) { return F <= 3 ? 4 : (F == 4 ? 2 : 1); }
+constexpr int seg_pass_cols_log(int F) { return F <= 3 ? 2 : (F == 4 ? 1 : 0); }
+
 // Segment-local index of register slot (RHO, J) of a pass unit: row RHO of
 // the block at blk, column c0 + threadIdx.x + 256 J (mirrored rows: the
 // mirror image inside the block).
@@ -237,18 +243,21 @@ __device__ __forceinline__ uint32_t seg_pass_index(uint32_t blk, uint32_t c0, in
     return blk + ((uint32_t)RHO << q) + col;
 }
 
-// F fused long-stride steps (bits q+F-1 .. q) over the big segments of class
-// >= cls.  A workgroup unit is 1024 consecutive columns x 2^F rows of one
-// 2^(q+F)-key block of one segment; thread t holds columns c0 + t + 256 j
-// (j = 0..3), so every load and store of a wave is 256 consecutive bytes.
+// F fused long-stride steps (bits q+F-1 .. q, F <= kSegFuseMax) over the big
+// segments of class >= cls.  A workgroup unit is 256 C consecutive columns x
+// 2^F rows of one 2^(q+F)-element block of one segment (C = seg_pass_cols(F));
+// thread t holds columns c0 + t + 256 j (j < C), so every load and store of
+// a wave is 64 consecutive elements.  Since q >= 13, a block holds whole
+// units.
 template <int F, bool MIRROR, class ST, class CD>
 __global__ __launch_bounds__(kSegThreads) void seg_pass_kernel(
     ST keys, const int64_t* __restrict__ offsets,
     const SegMeta* __restrict__ meta, const uint32_t* __restrict__ big_ids,
     const uint64_t* __restrict__ big_keys, int cls, int q, CD cd) {
   constexpr int ROWS = 1 << F;
-  constexpr int TOP = ROWS >> 1;
-  constexpr int UNIT_LOG = 10 + F;  // keys per unit = 1024 columns x 2^F rows
+  constexpr int COLS = seg_pass_cols(F);
+  constexpr int COL_LOG = 8 + seg_pass_cols_log(F);  // columns per unit, log2
+  constexpr int UNIT_LOG = COL_LOG + F;              // elements per unit, log2
   const uint32_t cnt = meta->big_ge[cls];
   uint64_t u, uend;
   unit_range(big_keys[cnt] >> UNIT_LOG, &u, &uend);
@@ -261,24 +270,24 @@ __global__ __launch_bounds__(kSegThreads) void seg_pass_kernel(
     const int64_t off = offsets[s];
     const uint32_t len = (uint32_t)(offsets[s + 1] - off);
     const ST a = keys.at(off);
-    // unit -> block and column run: a block holds 2^q / 1024 units;
+    // unit -> block and column run: a block holds 2^(q - COL_LOG) units;
     // segment-local indices fit 32 bits (segments hold < 2^31 keys)
     const uint32_t lu = (uint32_t)(lk >> UNIT_LOG);
-    const int upb_log = q - 10;
+    const int upb_log = q - COL_LOG;
     const uint32_t blk = (lu >> upb_log) << (q + F);
-    const uint32_t c0 = (lu & ((1u << upb_log) - 1u)) << 10;
-    typename ST::E x[4 * ROWS];
+    const uint32_t c0 = (lu & ((1u << upb_log) - 1u)) << COL_LOG;
+    typename ST::E x[COLS * ROWS];
     static_for<0, ROWS>([&](auto RHO) {
-      static_for<0, 4>([&](auto J) {
+      static_for<0, COLS>([&](auto J) {
         const uint32_t idx = seg_pass_index<F, MIRROR, RHO, J>(blk, c0, q);
-        x[4 * RHO + J] = idx < len ? cd.enc(a.get(idx)) : ST::kPadE;
+        x[COLS * RHO + J] = idx < len ? cd.enc(a.get(idx)) : ST::kPadE;
       });
     });
-    pass_steps<F, MIRROR>(x);
+    pass_steps<F, MIRROR, COLS>(x);
     static_for<0, ROWS>([&](auto RHO) {
-      static_for<0, 4>([&](auto J) {
+      static_for<0, COLS>([&](auto J) {
         const uint32_t idx = seg_pass_index<F, MIRROR, RHO, J>(blk, c0, q);
-        if (idx < len) a.put(idx, cd.dec(x[4 * RHO + J]));
+        if (idx < len) a.put(idx, cd.dec(x[COLS * RHO + J]));
       });
     });
   }
@@ -314,6 +323,9 @@ void seg_run(ST keys, CD cd, const SegLaunch& l, const int64_t* offsets, const S
       if (l.f == 1) { BITONIC_SEG_PASS(1) }
       else if (l.f == 2) { BITONIC_SEG_PASS(2) }
       else if (l.f == 3) { BITONIC_SEG_PASS(3) }
+      else if (l.f == 4) { BITONIC_SEG_PASS(4) }
+      else if (l.f == 5) { BITONIC_SEG_PASS(5) }
+      static_assert(kSegFuseMax == 5, "one instantiation per fused step count");
 #undef BITONIC_SEG_PASS
       break;
     }

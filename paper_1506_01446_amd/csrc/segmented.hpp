@@ -11,7 +11,7 @@ namespace bitonic {
 constexpr int kTileRegLogSeg = 5;  // 32 keys per thread
 constexpr int kSegSmallMaxLog2 = 13;  // segments of up to 2^13 keys are "small"
 constexpr int kSmallClasses = 9;   // classes 13, 12, ..., 6 and "<= 5"
-constexpr int kSegFuseMax = 3;
+constexpr int kSegFuseMax = 5;  // most steps per big-segment pass
 
 // Written by the prep kernel, read by the others (device memory).
 struct SegMeta {
@@ -34,7 +34,7 @@ struct SegScratch {
   uint64_t* big_tiles;   // nseg + 1: exclusive prefix of 2^13-key tiles
 };
 
-inline size_t seg_scratch_bytes(int64_t nseg) {
+constexpr size_t seg_scratch_bytes(int64_t nseg) {
   const size_t n = (size_t)nseg + 1;
   return 1024 + 2 * ((4 * n + 255) & ~size_t(255)) + 2 * ((8 * n + 255) & ~size_t(255));
 }

@@ -46,6 +46,8 @@ def test_argument_errors_are_synchronous(lib):
     assert lib.bitonic_sort_segmented_i32(None, None, -1, 1, None) == -1
     assert lib.bitonic_sort_segmented_i32(None, None, 0, 1, None) == 0
     assert lib.bitonic_sort_segmented_i32(None, None, 3, 1, None) == -1
+    assert lib.bitonic_set_tuning_value(b"seg_fuse", 0) == -1
+    assert lib.bitonic_set_tuning_value(b"seg_fuse", 6) == -1
     assert lib.bitonic_sort_segmented_bounded_i32(None, None, 3, -1, 1, None) == -1
     assert lib.bitonic_keygen_i32(None, -1, 0, 0, None) == -1
     assert lib.bitonic_set_tuning(99, 0, 0) == -1
@@ -279,7 +281,7 @@ def test_plan_shapes_8byte(lib, layout, unit):
 def test_plan_shapes_segmented(lib, layout, unit):
     """The segmented planner, for a longest segment of 1..2^31 elements:
     prep, the small-segment kernel, and for segments past 2^13 elements the
-    tile sort and per phase its passes (at most three steps each) and merge."""
+    tile sort and per phase its passes (at most "seg_fuse" steps each) and merge."""
     for k in range(0, 32):
         n = 2**k
         sh = B.bitonic_plan_shapes(n, layout)
@@ -292,6 +294,7 @@ def test_plan_shapes_segmented(lib, layout, unit):
         merges = [s for s in sh if s["kind"] == "tile_merge"]
         passes = [s for s in sh if s["kind"] == "global_pass"]
         assert len(merges) == k - 13
-        assert all(s["fuse"] <= 3 for s in passes)
+        assert all(s["fuse"] <= B.bitonic_get_tuning_value("seg_fuse") for s in passes)
         # every phase p > 13 performs steps on bits p-1 .. 13 exactly once
         assert sum(s["fuse"] for s in passes) == sum(p - 13 for p in range(14, k + 1))
+

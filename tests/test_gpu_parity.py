@@ -324,6 +324,26 @@ def test_segmented_big_classes_unaligned():
         assert np.array_equal(got, want), ("bounded", asc)
 
 
+@pytest.mark.parametrize("seg_fuse", [1, 2, 3, 4, 5])
+def test_segmented_fuse_depths(seg_fuse):
+    """Big-segment passes of 1..5 fused steps (4, 4, 4, 2 and 1 columns per
+    thread) over classes 14..20 at an unaligned start, both directions."""
+    lens = np.array([(1 << 14) + 3, (1 << 16) - 1, 1 << 17, (1 << 18) + 1, 9, (1 << 19) - 7,
+                     (1 << 20) - 1, 0, 8192], dtype=np.int64)
+    off = W.offsets_from_lengths(lens) + 1
+    keys = W.uniform_i32(43 + seg_fuse, int(off[-1]) + 2)
+    saved = B.bitonic_get_tuning_value("seg_fuse")
+    try:
+        B.bitonic_set_tuning_value("seg_fuse", seg_fuse)
+        for asc in (True, False):
+            want = keys.copy()
+            want[off[0]:off[-1]] = O.sort_segmented_i32(keys[off[0]:off[-1]], off - off[0], asc)
+            got = gpu_sort_segmented(keys, off, asc, max_seg_len=int(lens.max()))
+            assert np.array_equal(got, want), (seg_fuse, asc)
+    finally:
+        B.bitonic_set_tuning_value("seg_fuse", saved)
+
+
 def test_segmented_pass_grid_extremes():
     """The big-segment kernels split their units into one contiguous range per
     workgroup: with 1 pass workgroup per CU a range spans many segments, with

@@ -303,6 +303,37 @@ def test_segmented_pairs_edge_lengths():
             assert np.array_equal(gk, wk) and np.array_equal(gv, wv), (asc, bound)
 
 
+@pytest.mark.parametrize("seg_fuse", [3, 4, 5])
+def test_segmented_8_byte_fuse_depths(seg_fuse):
+    """Big-segment passes of 3..5 fused steps on 8-byte elements (pairs and
+    int64 keys), classes 14..19 at an unaligned start."""
+    lens = [(1 << 14) + 1, 70001, (1 << 17) + 3, 5, (1 << 19) - 9, 0]
+    off = np.concatenate([[3], 3 + np.cumsum(lens)]).astype(np.int64)
+    n = int(off[-1]) + 5
+    keys = (W.uniform_i32(W.SEED_BASE + 122, n).astype(np.int64) % 1001 - 500).astype(np.int32)
+    values = W.uniform_i32(W.SEED_BASE + 123, n)
+    k64 = W.uniform_i64(W.SEED_BASE + 124, n)
+    saved = B.bitonic_get_tuning_value("seg_fuse")
+    try:
+        B.bitonic_set_tuning_value("seg_fuse", seg_fuse)
+        for asc in (True, False):
+            print(f"[case] segmented 8-byte seg_fuse={seg_fuse} asc={asc}", flush=True)
+            gk, gv = _seg_pairs_gpu(keys, values, off, asc, max_seg_len=max(lens))
+            wk, wv = _seg_pairs_oracle(keys, values, off, asc)
+            assert np.array_equal(gk, wk) and np.array_equal(gv, wv), (seg_fuse, asc)
+            t = torch.from_numpy(k64.copy()).cuda()
+            B.bitonic_sort_segmented_keys(t, torch.from_numpy(off).cuda(), asc, "int64",
+                                          max_seg_len=max(lens))
+            torch.cuda.synchronize()
+            want = k64.copy()
+            for a, b in zip(off[:-1], off[1:]):
+                if b > a:
+                    want[a:b] = O.sort_keys64(k64[a:b], O.KEY_I64, asc)
+            assert np.array_equal(t.cpu().numpy(), want), ("int64", seg_fuse, asc)
+    finally:
+        B.bitonic_set_tuning_value("seg_fuse", saved)
+
+
 def test_segmented_pairs_argsort_workload():
     """The 8192-segment batched workload as a per-segment argsort: values
     0..len-1 in every segment come out as numpy's stable argsort."""
