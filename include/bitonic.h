@@ -151,7 +151,8 @@ int bitonic_sort_pairs(void* keys, int32_t* values, int64_t n, int key_type, int
  * enqueues only the phases needed.  Bad offsets are undefined behaviour.
  * Calls on a stream that is being captured into a graph are refused
  * (BITONIC_EINVAL): the graph would share the stream's scratch buffer with
- * later eager calls; capture bitonic_graph_capture_segmented_i32 instead.
+ * later eager calls; capture bitonic_graph_capture_segmented_i32 or
+ * bitonic_sort_segmented_noalloc_i32 instead.
  * Returns BITONIC_OK, BITONIC_EINVAL, BITONIC_ENOMEM (scratch), BITONIC_EDEVICE
  * or BITONIC_ELAUNCH.
  */
@@ -170,6 +171,31 @@ int bitonic_sort_segmented_i32(int32_t* keys, const int64_t* offsets,
  * bitonic_sort_segmented_i32 it refuses a capturing stream.
  */
 int bitonic_sort_segmented_bounded_i32(int32_t* keys, const int64_t* offsets,
+                                       int64_t nseg, int64_t max_seg_len,
+                                       int ascending, void* stream);
+
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops that must not call hipMalloc): the segmented sort
+ * of bitonic_sort_segmented_bounded_i32 with the same launch sequence and
+ * kernels, whose scratch (the segment classification and prefix tables) is a
+ * file-scope device array of 6 MiB + 1 KiB that each GPU the library runs on
+ * holds until the process ends.  The call allocates and frees nothing, never
+ * blocks, and may be captured into a HIP graph.
+ *   keys, offsets, ascending, stream  as for bitonic_sort_segmented_bounded_i32
+ *   nseg         0 <= nseg <= 262143 (2^18 - 1); larger tables return
+ *                BITONIC_EUNSUPPORTED with nothing enqueued
+ *   max_seg_len  bound on the segment length, 1 .. 2^31, required when
+ *                nseg > 0 (BITONIC_EINVAL otherwise)
+ * Every call on one GPU uses that GPU's one array, which keeps the last
+ * call's contents (each call's first kernel rewrites what it reads): calls
+ * that overlap on one GPU (on different streams, or replays of captured
+ * graphs that are not ordered with each other or with eager calls) race and
+ * give undefined results; calls ordered on one stream do not.
+ * Returns BITONIC_OK, BITONIC_EINVAL, BITONIC_EUNSUPPORTED, BITONIC_EDEVICE
+ * (the array's address could not be taken) or BITONIC_ELAUNCH.
+ */
+int bitonic_sort_segmented_noalloc_i32(int32_t* keys, const int64_t* offsets,
                                        int64_t nseg, int64_t max_seg_len,
                                        int ascending, void* stream);
 

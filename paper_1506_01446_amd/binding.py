@@ -57,6 +57,8 @@ def load() -> ctypes.CDLL:
                                        ctypes.c_int),
         "bitonic_sort_segmented_bounded_i32": ([vp, vp, ctypes.c_int64, ctypes.c_int64,
                                                ctypes.c_int, vp], ctypes.c_int),
+        "bitonic_sort_segmented_noalloc_i32": ([vp, vp, ctypes.c_int64, ctypes.c_int64,
+                                               ctypes.c_int, vp], ctypes.c_int),
         "bitonic_network_phases_i32": ([vp, ctypes.c_int64, ctypes.c_int, ctypes.c_int,
                                         ctypes.POINTER(bitonic_plan), vp], ctypes.c_int),
         "bitonic_plan_passes": ([ctypes.c_int64, ctypes.POINTER(bitonic_plan)],
@@ -347,6 +349,18 @@ def bitonic_sort_segmented_i32(keys, offsets, ascending: bool = True, stream=Non
                load().bitonic_sort_segmented_bounded_i32(kp, op, nseg, int(max_seg_len),
                                                          int(bool(ascending)),
                                                          _stream(stream)))
+
+
+def bitonic_sort_segmented_noalloc_i32(keys, offsets, max_seg_len: int, ascending: bool = True,
+                                       stream=None) -> None:
+    """The allocation-free segmented sort (a library-owned device array as
+    scratch; at most 2^18 - 1 segments; calls overlapping on one GPU race)."""
+    kp = _keys_ptr(keys)
+    op = _keys_ptr(offsets, "int64")
+    _check("bitonic_sort_segmented_noalloc_i32",
+           load().bitonic_sort_segmented_noalloc_i32(kp, op, max(offsets.numel() - 1, 0),
+                                                     int(max_seg_len), int(bool(ascending)),
+                                                     _stream(stream)))
 
 
 def bitonic_plan_tile_log2(n: int, plan=None) -> int:

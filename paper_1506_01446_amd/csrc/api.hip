@@ -281,7 +281,8 @@ static ScratchCache<HipAlloc> g_scratch;
 // would bind the graph to the stream's shared, growable buffer, so that its
 // replays and later eager calls on other streams could race on it: such
 // calls are refused (BITONIC_EINVAL).  Graphs take
-// bitonic_graph_capture_segmented_i32 (a buffer of their own).
+// bitonic_graph_capture_segmented_i32 (a buffer of their own) or the
+// allocation-free entry point.
 static bool stream_is_capturing(hipStream_t st) {
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   return hipStreamIsCapturing(st, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone;
@@ -774,6 +775,27 @@ int bitonic_sort_segmented_pairs(void* keys, int32_t* values, const int64_t* off
   if (key_type < BITONIC_KEY_I32 || key_type > BITONIC_KEY_F32) return BITONIC_EINVAL;
   if (nseg > 0 && values == nullptr) return BITONIC_EINVAL;
   return sort_segmented(keys, values, offsets, nseg, max_seg_len, key_type, ascending, stream);
+}
+
+int bitonic_sort_segmented_noalloc_i32(int32_t* keys, const int64_t* offsets, int64_t nseg,
+                                       int64_t max_seg_len, int ascending, void* stream) {
+  if (nseg < 0 || max_seg_len < 0) return BITONIC_EINVAL;
+  if (nseg > kNoAllocMaxSegments || max_seg_len > (int64_t(1) << 31)) return BITONIC_EUNSUPPORTED;
+  if (nseg == 0) return BITONIC_OK;
+  if (max_seg_len < 1 || keys == nullptr || offsets == nullptr) return BITONIC_EINVAL;
+  if ((reinterpret_cast<uintptr_t>(keys) & 3u) != 0) return BITONIC_EINVAL;
+  int dev = 0;
+  int rc = current_device(&dev);
+  if (rc) return rc;
+  void* base = nullptr;
+  if (noalloc_scratch(dev, &base) != 0) return BITONIC_EDEVICE;
+  (void)hipGetLastError();
+  SegData d{};
+  d.keys = keys;
+  d.cd = make_codec(BITONIC_KEY_I32, ascending != 0);
+  d.cd64 = make_pair_codec(BITONIC_KEY_I32, ascending != 0);
+  enqueue_segmented(d, offsets, nseg, max_seg_len, base, device_cus(dev), (hipStream_t)stream);
+  return finish_launches();
 }
 
 int bitonic_sort_segmented_i32(int32_t* keys, const int64_t* offsets, int64_t nseg,

@@ -39,6 +39,16 @@ constexpr size_t seg_scratch_bytes(int64_t nseg) {
   return 1024 + 2 * ((4 * n + 255) & ~size_t(255)) + 2 * ((8 * n + 255) & ~size_t(255));
 }
 
+// The allocation-free entry point's scratch (noalloc.hip): a file-scope
+// device array holding the segment table of up to kNoAllocMaxSegments
+// segments (seg_scratch_bytes(2^18 - 1) = 6 MiB + 1 KiB).
+constexpr int64_t kNoAllocMaxSegments = (int64_t(1) << 18) - 1;
+constexpr size_t kNoAllocScratchBytes = 1024 + (size_t(24) << 18);
+
+// Device address of that array on device `dev` (the current device), taken
+// on the first call per device; 0 on success, -1 on a HIP error.
+int noalloc_scratch(int dev, void** out);
+
 inline SegScratch seg_scratch_carve(void* base, int64_t nseg) {
   const size_t n = (size_t)nseg + 1;
   char* p = static_cast<char*>(base);

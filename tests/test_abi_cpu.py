@@ -298,3 +298,14 @@ def test_plan_shapes_segmented(lib, layout, unit):
         # every phase p > 13 performs steps on bits p-1 .. 13 exactly once
         assert sum(s["fuse"] for s in passes) == sum(p - 13 for p in range(14, k + 1))
 
+
+def test_noalloc_argument_errors(lib):
+    """The allocation-free segmented sort checks its sizes before it takes
+    its scratch array's address (no device is touched here)."""
+    assert lib.bitonic_sort_segmented_noalloc_i32(None, None, 0, 0, 1, None) == 0
+    assert lib.bitonic_sort_segmented_noalloc_i32(None, None, -1, 8, 1, None) == -1
+    assert lib.bitonic_sort_segmented_noalloc_i32(None, None, 2**18, 8, 1, None) == -4
+    assert lib.bitonic_sort_segmented_noalloc_i32(None, None, 3, 2**31 + 1, 1, None) == -4
+    assert lib.bitonic_sort_segmented_noalloc_i32(None, None, 3, 0, 1, None) == -1
+    assert lib.bitonic_sort_segmented_noalloc_i32(None, 8, 3, 8, 1, None) == -1
+    assert lib.bitonic_sort_segmented_noalloc_i32(6, 8, 3, 8, 1, None) == -1   # misaligned
