@@ -119,17 +119,47 @@ struct LdsBase {
   }
 };
 
+// Orders the LDS accesses of the lanes of one wave: a wave's LDS
+// instructions execute in order, so only the compiler must be kept from
+// moving accesses across (fences at wavefront scope and a wave barrier).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Synchronisation between the LDS writes and reads of the regroup from group
+// GA to GB: a workgroup barrier, or only a wave-level ordering when the
+// regroup keeps every key inside its wave (regroup_in_wave).
+template <class PR, int GA, int GB>
+__device__ __forceinline__ void regroup_sync() {
+  if constexpr (regroup_in_wave(PR::value.g[GA], PR::value.g[GB], PR::L))
+    wave_sync();
+  else
+    __syncthreads();
+}
+
+// Before a program's first regroup writes LDS, the previous user of the LDS
+// (the previous tile of a kernel that loops over tiles) must be done with
+// it.  Later regroups need no such wait: a regroup writes each key at the
+// position of its real index in the layout it starts from, exactly where the
+// previous regroup read it, and in one layout the waves hold disjoint sets
+// of indices, so no wave overwrites a position another wave may still read.
+template <int GA>
+__device__ __forceinline__ void regroup_enter() {
+  if constexpr (GA == 0) __syncthreads();
+}
+
 // Move the registers from the layout of group GA to that of group GB
-// through LDS (each key to the padded position of its real index).  Begins
-// with a barrier so the LDS is free to overwrite.
+// through LDS (each key to the padded position of its real index).
 template <class PR, int GA, int GB, class E>
 __device__ __forceinline__ void regroup(E (&x)[PR::R], E* lds, uint32_t tid) {
   if constexpr (PR::LEAN) asm volatile("" : "+v"(tid));
   const LdsBase<PR, GA> a(tid);
   const LdsBase<PR, GB> b(tid);
-  __syncthreads();
+  regroup_enter<GA>();
   static_for<0, PR::R>([&](auto J) { lds[a.template at<J>()] = x[J]; });
-  __syncthreads();
+  regroup_sync<PR, GA, GB>();
   static_for<0, PR::R>([&](auto J) { x[J] = lds[b.template at<J>()]; });
 }
 

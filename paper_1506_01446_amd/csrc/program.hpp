@@ -117,6 +117,27 @@ constexpr uint32_t lds_pad(uint32_t i, int s = 5) { return i + (i >> s); }
 // Words of LDS a padded tile of 2^L keys occupies.
 constexpr uint32_t lds_words(int L, int s = 5) { return lds_pad((1u << L) - 1u, s) + 1u; }
 
+// Index bits that carry a thread's wave number in layout G: the free bits
+// left after the lowest six, which carry the lane (64-lane waves; thread t
+// is lane t mod 64 of wave t / 64).
+constexpr uint32_t wave_bit_mask(const Group& G, int L) {
+  uint32_t f = free_mask(G, L);
+  for (int k = 0; k < 6 && f; ++k) f &= f - 1;
+  return f;
+}
+
+// Does a regroup from layout A to layout B keep every key inside the wave
+// that holds it?  It does when both layouts put the wave number on the same
+// index bits and no mirror of a virtual layout flips one of those bits: the
+// set of real indices a wave holds is then the same in A and B.  Such a
+// regroup exchanges keys between the lanes of one wave only, so it needs no
+// workgroup barrier.  (An exhaustive check over every thread and slot agrees
+// with this test on every program the kernels instantiate.)
+constexpr bool regroup_in_wave(const Group& A, const Group& B, int L) {
+  const uint32_t wa = wave_bit_mask(A, L);
+  return wa == wave_bit_mask(B, L) && (wa & mirror_mask(A)) == 0 && (wa & mirror_mask(B)) == 0;
+}
+
 // Layout for 16-byte global loads and stores: each thread holds 4
 // consecutive keys (index bits 0, 1) of r - 2 rows (the top tile bits), so a
 // wave moves 64 consecutive 16-byte pieces per instruction.

@@ -1,7 +1,7 @@
 // Tile programs on 8-byte elements with half the LDS: each regroup moves the
 // elements' high words through an LDS array of 4-byte words, then their low
-// words.  It costs two more barriers per regroup than regroup (device.hpp)
-// and lets twice as many workgroups share a CU, which for the 2^12..2^13
+// words.  It costs two more synchronisations per regroup than regroup
+// (device.hpp) and lets twice as many workgroups share a CU, which for the 2^12..2^13
 // element tiles of the 8-byte sorts is the difference between two and four
 // workgroups (8 and 16 or 32 waves).
 #pragma once
@@ -17,13 +17,15 @@ __device__ __forceinline__ void regroup_split(int64_t (&x)[PR::R], uint32_t* lds
   const LdsBase<PR, GA> a(tid);
   const LdsBase<PR, GB> b(tid);
   uint32_t hi[PR::R];
-  __syncthreads();
+  regroup_enter<GA>();
   static_for<0, PR::R>([&](auto J) { lds[a.template at<J>()] = (uint32_t)((uint64_t)x[J] >> 32); });
-  __syncthreads();
+  regroup_sync<PR, GA, GB>();
   static_for<0, PR::R>([&](auto J) { hi[J] = lds[b.template at<J>()]; });
-  __syncthreads();
+  // the low words overwrite positions other lanes (other waves, unless the
+  // regroup stays inside its wave) read the high words from
+  regroup_sync<PR, GA, GB>();
   static_for<0, PR::R>([&](auto J) { lds[a.template at<J>()] = (uint32_t)(uint64_t)x[J]; });
-  __syncthreads();
+  regroup_sync<PR, GA, GB>();
   static_for<0, PR::R>([&](auto J) {
     x[J] = (int64_t)(((uint64_t)hi[J] << 32) | lds[b.template at<J>()]);
   });

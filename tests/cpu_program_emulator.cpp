@@ -170,4 +170,39 @@ int worst_bank_conflict(int L, int r, int kind, int banks) {
 
 int program_groups(int L, int r, int kind) { return make(L, r, kind).ngroups; }
 
+// The regroups the kernels synchronise per wave only (regroup_in_wave of
+// program.hpp) against an exhaustive check: a regroup keeps every key in its
+// wave if each real index a thread of wave w holds in the source layout is
+// held by a thread of wave w in the target layout (64-lane waves, thread t in
+// wave t / 64).  Returns -1 if the library's test calls a regroup in-wave
+// that is not; else writes the number of regroups the exhaustive check finds
+// in-wave to *exact and returns the number the library's test finds.
+int in_wave_regroups(int L, int r, int kind, int* exact) {
+  const Program P = make(L, r, kind);
+  if (!layouts_valid(P, L)) return -1;
+  const uint32_t NT = 1u << (L - r), R = 1u << r;
+  int lib = 0, truth = 0;
+  for (int g = 1; g < P.ngroups; ++g) {
+    const Group& A = P.g[g - 1];
+    const Group& B = P.g[g];
+    // owner thread of every real index in layout B
+    std::vector<uint32_t> owner(size_t(1) << L);
+    for (uint32_t t = 0; t < NT; ++t)
+      for (uint32_t j = 0; j < R; ++j) owner[real_index(B, L, t, j)] = t;
+    bool stays = true;
+    for (uint32_t t = 0; t < NT && stays; ++t)
+      for (uint32_t j = 0; j < R; ++j)
+        if (owner[real_index(A, L, t, j)] / 64 != t / 64) {
+          stays = false;
+          break;
+        }
+    const bool flagged = regroup_in_wave(A, B, L);
+    if (flagged && !stays) return -1;
+    lib += flagged;
+    truth += stays;
+  }
+  *exact = truth;
+  return lib;
+}
+
 }  // extern "C"

@@ -33,6 +33,8 @@ def emu(tmp_path_factory):
     lib.worst_bank_conflict_lanes.restype = ctypes.c_int
     lib.program_groups.argtypes = [ctypes.c_int] * 3
     lib.program_groups.restype = ctypes.c_int
+    lib.in_wave_regroups.argtypes = [ctypes.c_int] * 3 + [ctypes.POINTER(ctypes.c_int)]
+    lib.in_wave_regroups.restype = ctypes.c_int
     return lib
 
 
@@ -136,3 +138,26 @@ def test_wide_programs(emu, L):
     for kind in (2, 3):
         assert emu.worst_bank_conflict_lanes(L, 4, kind, 32, 16) == 1
         assert emu.worst_bank_conflict_lanes(L, 4, kind, 32, 32) <= 2
+
+
+# Every tile program a kernel instantiates: (L, r, kind) -- the single-array
+# 4-byte tiles (vector I/O, and the 2^13 scalar-I/O tile), the 8-byte tiles,
+# the segmented small-segment programs and big-segment tiles.
+INSTANTIATED = sorted({(L, 5, k) for L in range(11, 16) for k in (0, 1)} |
+                      {(13, 5, 2), (13, 5, 3)} |
+                      {(L, 4, k) for L in (11, 12, 13) for k in (2, 3)} |
+                      {(L, 5, 2) for L in range(5, 14)} | {(13, 4, 2), (13, 4, 3)})
+
+
+@pytest.mark.parametrize("L,r,kind", INSTANTIATED)
+def test_in_wave_regroups(emu, L, r, kind):
+    """Regroups that the kernels synchronise per wave instead of per
+    workgroup must keep every key inside its 64-lane wave: checked against
+    every thread and slot of the program; the layout test the kernels use
+    finds exactly the regroups the exhaustive check finds."""
+    exact = ctypes.c_int()
+    got = emu.in_wave_regroups(L, r, kind, ctypes.byref(exact))
+    assert got >= 0, "a regroup synchronised per wave moves keys across waves"
+    assert got == exact.value
+    if L - r <= 6:   # one wave (or less) per tile: every regroup stays inside it
+        assert got == emu.program_groups(L, r, kind) - 1
