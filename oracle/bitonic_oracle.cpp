@@ -62,6 +62,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <functional>
+#include <thread>
 #include <vector>
 
 namespace {
@@ -110,6 +111,36 @@ enum { ORACLE_STANDARD = 0, ORACLE_FLIP = 1, ORACLE_FLIP_VIRTUAL = 2 };
 int oracle_sort_i32(int32_t* keys, int64_t n, int ascending) {
   if (n < 0 || (n > 0 && keys == nullptr)) return -1;
   std::sort(keys, keys + n);
+  if (!ascending) std::reverse(keys, keys + n);
+  return 0;
+}
+
+// The same sort on `threads` host threads, as a CPU baseline on all cores
+// (section 5 compares against one CPU thread; this is context beyond it):
+// std::sort of `threads` contiguous chunks in parallel, then pairwise
+// std::inplace_merge of neighbouring runs, each level's merges in parallel.
+// The result is the ascending (or reversed) order, as oracle_sort_i32.
+int oracle_sort_i32_parallel(int32_t* keys, int64_t n, int ascending, int threads) {
+  if (n < 0 || (n > 0 && keys == nullptr) || threads < 1) return -1;
+  if (threads > 256) threads = 256;
+  const int64_t parts = n < threads ? 1 : threads;
+  std::vector<int64_t> cut(parts + 1);
+  for (int64_t i = 0; i <= parts; ++i) cut[i] = n * i / parts;
+  {
+    std::vector<std::thread> pool;
+    for (int64_t i = 0; i < parts; ++i)
+      pool.emplace_back([&, i] { std::sort(keys + cut[i], keys + cut[i + 1]); });
+    for (auto& t : pool) t.join();
+  }
+  for (int64_t width = 1; width < parts; width *= 2) {
+    std::vector<std::thread> pool;
+    for (int64_t i = 0; i + width < parts; i += 2 * width) {
+      const int64_t a = cut[i], m = cut[i + width];
+      const int64_t b = cut[std::min<int64_t>(i + 2 * width, parts)];
+      pool.emplace_back([=] { std::inplace_merge(keys + a, keys + m, keys + b); });
+    }
+    for (auto& t : pool) t.join();
+  }
   if (!ascending) std::reverse(keys, keys + n);
   return 0;
 }

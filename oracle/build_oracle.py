@@ -29,7 +29,7 @@ MUTANTS = {
 
 
 def _compile(out: str, extra: list[str]) -> str:
-    cmd = ["g++", "-O2", "-std=c++17", "-shared", "-fPIC", "-o", out + ".tmp",
+    cmd = ["g++", "-O2", "-std=c++17", "-shared", "-fPIC", "-pthread", "-o", out + ".tmp",
            SRC] + extra
     subprocess.run(cmd, check=True)
     os.replace(out + ".tmp", out)

@@ -39,6 +39,8 @@ def _bind(lib: ctypes.CDLL) -> ctypes.CDLL:
     p64 = ctypes.POINTER(ctypes.c_int64)
     lib.oracle_sort_i32.argtypes = [p32, ctypes.c_int64, ctypes.c_int]
     lib.oracle_sort_i32.restype = ctypes.c_int
+    lib.oracle_sort_i32_parallel.argtypes = [p32, ctypes.c_int64, ctypes.c_int, ctypes.c_int]
+    lib.oracle_sort_i32_parallel.restype = ctypes.c_int
     lib.oracle_sort_segmented_i32.argtypes = [p32, p64, ctypes.c_int64, ctypes.c_int]
     lib.oracle_sort_segmented_i32.restype = ctypes.c_int
     lib.oracle_bitonic_i32.argtypes = [p32, ctypes.c_int64, ctypes.c_int, ctypes.c_int,
@@ -109,6 +111,16 @@ def sort_i32(keys, ascending: bool = True, lib=None) -> np.ndarray:
 
 KEY_I32, KEY_U32, KEY_F32 = 0, 1, 2
 _KEY_DTYPES = {KEY_I32: np.int32, KEY_U32: np.uint32, KEY_F32: np.float32}
+
+
+def sort_i32_parallel(keys, ascending: bool = True, threads: int = 1, lib=None) -> np.ndarray:
+    """sort_i32 on `threads` host threads (chunks sorted in parallel, then
+    merged pairwise): a CPU baseline on all cores."""
+    lib = lib or load()
+    x = _keys(keys)
+    if lib.oracle_sort_i32_parallel(_p32(x), x.size, int(bool(ascending)), int(threads)):
+        raise ValueError("oracle_sort_i32_parallel rejected its arguments")
+    return x
 
 
 def sort_keys(keys, key_type: int, ascending: bool = True, lib=None) -> np.ndarray:

@@ -237,3 +237,20 @@ def test_bad_arguments(oracle_lib):
         O.sort_segmented_i32([1, 2, 3], [0, 5])
     with pytest.raises(ValueError):
         O.step_pairs(8, O.STANDARD, 4, 1)
+
+
+@pytest.mark.parametrize("threads", [1, 2, 3, 7, 16])
+def test_parallel_sort_baseline(oracle_lib, threads):
+    """The all-cores CPU baseline (chunks sorted in parallel, merged pairwise)
+    gives numpy's sort: sizes below, at and above the thread count, ragged
+    chunks, both directions."""
+    from oracle import oracle as O
+    for n in (0, 1, 2, threads - 1, threads, threads + 1, 1000, 65537, 300001):
+        if n < 0:
+            continue
+        keys = W.uniform_i32(n + 31 * threads, n)
+        keys[: n // 3] = keys[n // 3: 2 * (n // 3)] if n >= 3 else keys[: n // 3]  # duplicates
+        for asc in (True, False):
+            got = O.sort_i32_parallel(keys, asc, threads)
+            want = np.sort(keys) if asc else np.sort(keys)[::-1]
+            assert np.array_equal(got, want), (n, threads, asc)
