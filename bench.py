@@ -19,14 +19,22 @@ Printed JSON line (one line, rank 0):
                the HBM bytes per launch from the committed rocprofv3 counter
                summary (profiles/sort_n<n>_hbm_traffic.txt), null when the
                kernel sources changed since those counters were taken
-  cpu_baseline the CPU oracle (std::sort, one thread) on a bounded sample
-  extra        per-kernel table; n = 10,000,000; per-repetition medians and
-               p90 (warm and cold) at 2^24 and 2^26; the 8-byte sorts (int64
-               keys, key-value pairs) at 2^24; batched vs looped segmented
-               sorting and the batched per-segment argsort; serving latency;
-               the oracle's scalar network as a second CPU context figure
+  cpu_baseline the CPU oracle's sort on all the host threads this process may
+               use (chunks std::sort-ed in parallel, merged pairwise) on a
+               bounded sample, with the one-thread std::sort and the one-thread
+               scalar bitonic network at n = 2^24 beside it (context: the
+               paper's CPU QuickSort and BitonicSort columns), the host CPU
+               model and thread counts
+  extra        per-kernel table; the same table at n = 2^26 and 2^28 (arrays
+               past the 256 MB Infinity Cache, so every pass streams HBM);
+               the cost of a dependent launch; n = 10,000,000; per-repetition
+               medians and p90 (warm and cold) at 2^24 and 2^26; the 8-byte
+               sorts (int64 keys, key-value pairs) at 2^24; batched vs looped
+               segmented sorting (the batched call eager with the exact bound,
+               eager without a bound, and replayed from a captured HIP graph)
+               and the batched per-segment argsort; serving latency over 60 s
                (each part can be switched off: --no-extra, --no-batched,
-               --serve-seconds 0, --no-cpu)
+               --no-hbm-true, --serve-seconds 0, --no-cpu)
 
 python bench.py --ablation   re-measures the paper's Table 1 (Basic, Semi,
                              Optimized plans for n = 2^17 .. 2^28)
@@ -61,7 +69,9 @@ def parse():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the n = 10^7 run (profiles of the n-key sort alone)")
-    ap.add_argument("--serve-seconds", type=float, default=10.0)
+    ap.add_argument("--serve-seconds", type=float, default=60.0)
+    ap.add_argument("--no-hbm-true", action="store_true",
+                    help="skip the per-kernel tables at n = 2^26 and 2^28")
     ap.add_argument("--out", default="")
     ap.add_argument("--ablation", action="store_true",
                     help="the paper's Table 1 layout on this GPU: Basic, Semi and "
@@ -321,36 +331,85 @@ def batched_pairs(torch, B, W, reps=7):
             "first_segment_is_stable_argsort": ok}
 
 
-def cpu_network_context(n=1 << 20):
-    """The oracle's scalar flip network (one thread) at a bounded size: the
-    analogue of the paper's CPU bitonic-sort column, as context only."""
-    from oracle import oracle as O
-    from paper_1506_01446_amd import workloads as W
-    keys = W.uniform_i32(W.SEED_BASE + 2, n)
-    t0 = time.perf_counter()
-    O.bitonic_i32(keys, True, O.FLIP_VIRTUAL)
-    dt = time.perf_counter() - t0
-    return {"value": round(n / dt / 1e9, 5), "unit": "Gkeys/s", "cores": 1,
-            "kind": "oracle scalar network", "sample": f"one sort of n={n} uniform int32, "
-                                                        f"{dt:.2f} s"}
+def host_cpu():
+    """Host CPU model, logical CPUs, and the threads this process may use
+    (its affinity set, capped by OMP_NUM_THREADS when that is set)."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    avail = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    cap = os.environ.get("OMP_NUM_THREADS")
+    threads = min(avail, int(cap)) if cap and cap.isdigit() and int(cap) > 0 else avail
+    return {"model": model, "nproc": os.cpu_count(), "affinity": avail, "threads": threads}
+
+
+def _time_reps(fn, max_reps, budget_s):
+    reps, total = 0, 0.0
+    while reps < max_reps and total < budget_s:
+        t0 = time.perf_counter()
+        fn()
+        total += time.perf_counter() - t0
+        reps += 1
+    return reps, total
 
 
 def cpu_baseline(n):
-    """The CPU oracle as it stands (std::sort, one thread) on a bounded
-    sample of the same workload."""
+    """The CPU oracle as it stands on a bounded sample of the same workload:
+    its sort on all the host threads this process may use (the reported
+    baseline), its one-thread std::sort (the paper's CPU QuickSort column),
+    and its one-thread scalar flip network (the paper's CPU BitonicSort
+    column), all on the same n-key uniform array."""
     from oracle import oracle as O
     from paper_1506_01446_amd import workloads as W
+    host = host_cpu()
     keys = W.uniform_i32(W.SEED_BASE + 2, n)
-    reps, total = 0, 0.0
-    while reps < 40 and total < 12.0:
-        t0 = time.perf_counter()
-        O.sort_i32(keys, True)
-        total += time.perf_counter() - t0
-        reps += 1
-    return {"value": round(n * reps / total / 1e9, 5), "unit": "Gkeys/s", "cores": 1,
+    th = host["threads"]
+    reps_p, tp = _time_reps(lambda: O.sort_i32_parallel(keys, True, th), 40, 4.0)
+    reps_1, t1 = _time_reps(lambda: O.sort_i32(keys, True), 20, 8.0)
+    reps_n, tn = _time_reps(lambda: O.bitonic_i32(keys, True, O.FLIP_VIRTUAL), 1, 1.0)
+    return {"value": round(n * reps_p / tp / 1e9, 5), "unit": "Gkeys/s", "cores": th,
             "kind": "oracle",
-            "sample": f"{reps} x std::sort (oracle_sort_i32, one thread) of the same "
-                      f"n={n} uniform int32 array, {total:.1f} s"}
+            "sample": f"{reps_p} x oracle_sort_i32_parallel ({th} threads: chunks std::sort-ed "
+                      f"in parallel, merged pairwise) of the same n={n} uniform int32 array, "
+                      f"{tp:.1f} s",
+            "host": host,
+            "single_thread_std_sort": {"value": round(n * reps_1 / t1 / 1e9, 5),
+                                       "unit": "Gkeys/s", "cores": 1,
+                                       "sample": f"{reps_1} x oracle_sort_i32, {t1:.1f} s"},
+            "single_thread_network": {"value": round(n * reps_n / tn / 1e9, 5),
+                                      "unit": "Gkeys/s", "cores": 1,
+                                      "sample": f"{reps_n} x oracle scalar flip network "
+                                                f"(virtual padding), {tn:.1f} s"}}
+
+
+def launch_gap(torch, B, count=200):
+    """Cost of one dependent launch: `count` back-to-back launches of a
+    one-workgroup kernel (the input generator writing 64 keys) on one
+    stream, timed with HIP events, per launch."""
+    buf = torch.empty(64, dtype=torch.int32, device="cuda")
+    ev = B.HipEvents(2)
+    rt = ev.rt
+    rt.hipEventRecord.argtypes = [B.ctypes.c_void_p, B.ctypes.c_void_p]
+    stream = torch.cuda.current_stream().cuda_stream
+    lib = B.load()
+    best = None
+    for _ in range(3):
+        torch.cuda.synchronize()
+        rt.hipEventRecord(ev.ev[0], stream)
+        for i in range(count):
+            lib.bitonic_keygen_i32(buf.data_ptr(), 64, i, 0, stream)
+        rt.hipEventRecord(ev.ev[1], stream)
+        torch.cuda.synchronize()
+        us = ev.elapsed_ms(0, 1) * 1e3 / count
+        best = us if best is None else min(best, us)
+    ev.close()
+    return round(best, 2)
 
 
 def batched_vs_looped(torch, B, W):
@@ -380,8 +439,21 @@ def batched_vs_looped(torch, B, W):
             best = ms if best is None else min(best, ms)
         return best
 
+    mx = int((off[1:] - off[:-1]).max())
     B.bitonic_sort_segmented_i32(buf, offs, True)
-    batched_ms = timed(lambda: B.bitonic_sort_segmented_i32(buf, offs, True), 5)
+    eager_unbounded_ms = timed(lambda: B.bitonic_sort_segmented_i32(buf, offs, True), 5)
+    B.bitonic_sort_segmented_i32(buf, offs, True, max_seg_len=mx)
+    eager_bounded_ms = timed(lambda: B.bitonic_sort_segmented_i32(buf, offs, True,
+                                                                  max_seg_len=mx), 5)
+    graph = B.bitonic_graph_capture_segmented_i32(buf, offs, mx, True)
+    graph.launch()
+    batched_ms = timed(graph.launch, 7)      # the batched sort as replayed from a HIP graph
+    torch.cuda.synchronize()
+    buf.copy_(src)
+    graph.launch()
+    torch.cuda.synchronize()
+    graph_out = buf.clone()
+    graph.close()
     ok = True
     lib = B.load()
     ptrs = [(buf.data_ptr() + 4 * int(off[s]), int(off[s + 1] - off[s]))
@@ -409,9 +481,10 @@ def batched_vs_looped(torch, B, W):
         del g
     except Exception as e:  # graph capture is an optional comparison
         log(f"[bench] looped graph capture skipped: {e}")
-    # check the batched result once more against the looped one
+    # check the batched results (eager and replayed) against the looped one
     buf.copy_(src)
     B.bitonic_sort_segmented_i32(buf, offs, True)
+    ok &= bool(torch.equal(buf, graph_out))
     ref = src.clone()
     for s_ in range(0, len(off) - 1, 97):
         B.bitonic_sort_i32(ref[off[s_]:off[s_ + 1]], True)
@@ -419,9 +492,17 @@ def batched_vs_looped(torch, B, W):
     torch.cuda.synchronize()
     ev.close()
     best_loop = min(x for x in (looped_ms, graph_ms) if x is not None)
-    return {"segments": len(off) - 1, "keys": total,
+    return {"segments": len(off) - 1, "keys": total, "max_segment": mx,
             "batched_ms": round(batched_ms, 3),
             "batched_gkeys_s": round(total / batched_ms / 1e6, 3),
+            "batched_timing": "HIP graph replay of bitonic_sort_segmented_i32's launches "
+                              "with the exact bound",
+            "eager_bounded_ms": round(eager_bounded_ms, 3),
+            "eager_unbounded_ms": round(eager_unbounded_ms, 3),
+            "unbounded_bound": B.bitonic_segmented_default_bound(buf),
+            "unbounded_launches": len(B.bitonic_plan_shapes(
+                B.bitonic_segmented_default_bound(buf), "seg_keys32")),
+            "bounded_launches": len(B.bitonic_plan_shapes(mx, "seg_keys32")),
             "looped_eager_ms": round(looped_ms, 3),
             "looped_graph_ms": None if graph_ms is None else round(graph_ms, 3),
             "looped_gkeys_s": round(total / best_loop / 1e6, 3),
@@ -523,7 +604,25 @@ def main():
              "paper_k10_context": {"mkeys_s_at_2_24": round(PAPER_K10_MKEYS_2_24, 1),
                                    "this_over_paper": round(gkeys * 1e3 / PAPER_K10_MKEYS_2_24,
                                                             1)}}
+    extra["launch_gap_us"] = launch_gap(torch, B)
+    log(f"[bench] dependent launch: {extra['launch_gap_us']} us")
     del src
+    if not args.no_hbm_true:
+        extra["hbm_true"] = {}
+        for k in (26, 28):
+            nk = 1 << k
+            srck = torch.empty(nk, dtype=torch.int32, device="cuda")
+            B.bitonic_keygen_i32(srck, W.SEED_BASE + k)
+            msk, _, okk = time_sorts(torch, B, srck, 3, 1, plan)
+            rk = kernel_table(torch, B, srck, plan, repeats=5)
+            pk = B.bitonic_plan_passes(nk, plan)
+            extra["hbm_true"][f"n{nk}"] = {
+                "ms": round(msk, 3), "gkeys_s": round(nk / (msk * 1e-3) / 1e9, 3),
+                "passes": pk, "sorted_check": okk,
+                "whole_sort_hbm_frac": round(8.0 * nk * pk / (msk * 1e-3) / 1e12 / 8.0, 4),
+                "kernels": rk}
+            log(f"[bench] n=2^{k}: {msk:.3f} ms; kernels {json.dumps(rk)}")
+            del srck
     if not args.no_extra:
         n2 = 10_000_000
         src2 = torch.from_numpy(W.uniform_i32(W.SEED_BASE + 3, n2)).cuda()
@@ -548,7 +647,7 @@ def main():
         log(f"[bench] protocol: {json.dumps(extra['protocol'])}")
     cpu = None if args.no_cpu else cpu_baseline(n)
     if cpu is not None:
-        extra["cpu_network"] = cpu_network_context()
+        log(f"[bench] cpu baseline: {json.dumps(cpu)}")
 
     line = {"metric": "Gkeys/s int32 at n=2^24 (%HBM peak); batched vs looped Gkeys/s; p99 ms",
             "value": round(gkeys, 3), "unit": "Gkeys/s", "n_gpus": 1, "steps": args.steps,

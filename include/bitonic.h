@@ -160,6 +160,17 @@ int bitonic_sort_segmented_i32(int32_t* keys, const int64_t* offsets,
                                int64_t nseg, int ascending, void* stream);
 
 /*
+ * The bound on the segment length that the segmented sorts take when the
+ * caller gives none (max_seg_len 0): the number of key_bytes-byte keys (4 or
+ * 8) from `keys` to the end of the device allocation holding them, at most
+ * 2^31 (2^31 where the allocation is unknown).  Host-side; nothing is
+ * enqueued.  -1 for a NULL pointer or another key size.  The merge phases
+ * enqueued are those up to ceil(log2 bound) (bitonic_plan_shapes with a
+ * segmented layout and n = bound lists the launches).
+ */
+int64_t bitonic_segmented_default_bound(const void* keys, int key_bytes);
+
+/*
  * As bitonic_sort_segmented_i32, with a host-side bound: every segment holds
  * at most max_seg_len keys (0 = unknown: then the bound of
  * bitonic_sort_segmented_i32 is taken).  The bound fixes how many merge

@@ -59,6 +59,7 @@ def load() -> ctypes.CDLL:
                                                ctypes.c_int, vp], ctypes.c_int),
         "bitonic_sort_segmented_noalloc_i32": ([vp, vp, ctypes.c_int64, ctypes.c_int64,
                                                ctypes.c_int, vp], ctypes.c_int),
+        "bitonic_segmented_default_bound": ([vp, ctypes.c_int], ctypes.c_int64),
         "bitonic_network_phases_i32": ([vp, ctypes.c_int64, ctypes.c_int, ctypes.c_int,
                                         ctypes.POINTER(bitonic_plan), vp], ctypes.c_int),
         "bitonic_plan_passes": ([ctypes.c_int64, ctypes.POINTER(bitonic_plan)],
@@ -361,6 +362,12 @@ def bitonic_sort_segmented_noalloc_i32(keys, offsets, max_seg_len: int, ascendin
            load().bitonic_sort_segmented_noalloc_i32(kp, op, max(offsets.numel() - 1, 0),
                                                      int(max_seg_len), int(bool(ascending)),
                                                      _stream(stream)))
+
+
+def bitonic_segmented_default_bound(keys) -> int:
+    """The segment-length bound the segmented sorts take for ``keys`` when
+    no bound is given (end of the keys' device allocation, at most 2^31)."""
+    return int(load().bitonic_segmented_default_bound(keys.data_ptr(), keys.element_size()))
 
 
 def bitonic_plan_tile_log2(n: int, plan=None) -> int:

@@ -777,6 +777,11 @@ int bitonic_sort_segmented_pairs(void* keys, int32_t* values, const int64_t* off
   return sort_segmented(keys, values, offsets, nseg, max_seg_len, key_type, ascending, stream);
 }
 
+int64_t bitonic_segmented_default_bound(const void* keys, int key_bytes) {
+  if (keys == nullptr || (key_bytes != 4 && key_bytes != 8)) return -1;
+  return allocation_bound(keys, key_bytes);
+}
+
 int bitonic_sort_segmented_noalloc_i32(int32_t* keys, const int64_t* offsets, int64_t nseg,
                                        int64_t max_seg_len, int ascending, void* stream) {
   if (nseg < 0 || max_seg_len < 0) return BITONIC_EINVAL;

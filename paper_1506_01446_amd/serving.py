@@ -10,7 +10,12 @@ described by a CSR offset table, sorted with one segmented launch sequence
 different streams overlap on the device; a request that arrives while others
 run is admitted as soon as a slot and memory free up (continuous batching,
 not a queue drained between batches).  A request larger than the whole
-budget is rejected.
+budget is rejected.  Every batch, also one of a single request, goes through
+the segmented sort (`pack_single=False` sends single requests to the
+single-array sort instead).  A watchdog fails the requests of a batch that
+has not completed `watchdog_s` seconds after its launch and retires its slot
+and memory for good (the device may still be writing them), so one stuck
+batch does not stall the loop.
 
 Latency of a request = time its batch is seen complete by the host minus its
 scheduled arrival time; throughput = keys sorted / wall time.
@@ -97,6 +102,7 @@ class Batch:
     region: tuple             # (start, size) in the arena
     admitted: float
     handle: object = None
+    launched: float = 0.0
 
 
 class FakeExecutor:
@@ -104,10 +110,12 @@ class FakeExecutor:
     `latency_s + keys / rate` of (virtual) time."""
 
     def __init__(self, rate_keys_per_s: float = 1e9, latency_s: float = 1e-4,
-                 fail_batches: set | None = None, clock=None):
+                 fail_batches: set | None = None, clock=None, hang_batches: set | None = None):
         self.rate = rate_keys_per_s
         self.latency = latency_s
         self.fail = set(fail_batches or ())
+        self.hang = set(hang_batches or ())   # batches that never complete
+        self.abandoned = []
         self.clock = clock
         self.inflight_peak = 0
         self._inflight = 0
@@ -123,13 +131,18 @@ class FakeExecutor:
         for r, a, b in zip(batch.requests, batch.offsets[:-1], batch.offsets[1:]):
             k = np.sort(W.uniform_i32(r.key_seed, r.length))
             outs.append(k if ascending else k[::-1].copy())
-        return {"ready": now + self.latency + total / self.rate, "outs": outs}
+        ready = float("inf") if batch.bid in self.hang else now + self.latency + total / self.rate
+        return {"ready": ready, "outs": outs, "bid": batch.bid}
 
     def poll(self, handle, now: float) -> bool:
         done = now >= handle["ready"]
         if done:
             self._inflight -= 1
         return done
+
+    def abandon(self, handle) -> None:
+        self._inflight -= 1
+        self.abandoned.append(handle["bid"])
 
     def result(self, handle, i: int) -> np.ndarray:
         return handle["outs"][i]
@@ -139,7 +152,8 @@ class GpuExecutor:
     """The HIP library on one GPU: one stream per in-flight slot, keys
     generated on the device into the arena, one segmented sort per batch."""
 
-    def __init__(self, capacity_keys: int, slots: int, max_segments: int, keep_results=False):
+    def __init__(self, capacity_keys: int, slots: int, max_segments: int, keep_results=False,
+                 pack_single: bool = True):
         import torch
 
         from . import binding as B
@@ -154,6 +168,8 @@ class GpuExecutor:
         self.off_host = [torch.empty(max_segments + 1, dtype=torch.int64, pin_memory=True)
                          for _ in range(slots)]
         self.keep = keep_results
+        self.pack_single = pack_single
+        self.segmented_batches = 0
         self.lib = B.load()
 
     def submit(self, batch: Batch, now: float, ascending: bool):
@@ -175,13 +191,14 @@ class GpuExecutor:
             if rc:
                 raise B.BitonicError("bitonic_keygen_i32", rc)
         max_len = max(r.length for r in batch.requests)
-        if nseg == 1 and max_len > 1:
+        if nseg == 1 and max_len > 1 and not self.pack_single:
             rc = self.lib.bitonic_sort_i32(base, max_len, int(ascending), sp)
             name = "bitonic_sort_i32"
         else:
             rc = self.lib.bitonic_sort_segmented_bounded_i32(base, od.data_ptr(), nseg,
                                                              max(max_len, 1), int(ascending), sp)
             name = "bitonic_sort_segmented_bounded_i32"
+            self.segmented_batches += 1
         if rc:
             raise B.BitonicError(name, rc)
         ev = torch.cuda.Event()
@@ -194,6 +211,11 @@ class GpuExecutor:
             return True
         return False
 
+    def abandon(self, handle) -> None:
+        """A batch the watchdog gave up on: its stream (and slot) is not
+        reused, since work queued behind it would wait for it."""
+        self.abandoned = getattr(self, "abandoned", []) + [handle["slot"]]
+
     def result(self, handle, i: int) -> np.ndarray:
         a = handle["start"] + int(handle["offsets"][i])
         b = handle["start"] + int(handle["offsets"][i + 1])
@@ -203,10 +225,16 @@ class GpuExecutor:
 class Server:
     def __init__(self, executor, budget_keys: int, max_inflight: int = 3,
                  max_batch_keys: int = 1 << 26, max_batch_segments: int = 1024,
-                 ascending: bool = True, collect_results: bool = False):
+                 ascending: bool = True, collect_results: bool = False,
+                 watchdog_s: float = 10.0):
         self.ex = executor
         self.arena = Arena(budget_keys)
         self.max_inflight = max_inflight
+        self.watchdog_s = watchdog_s
+        self.timed_out: list[Request] = []
+        self.queue_samples = 0
+        self.queue_sum = 0
+        self.queue_peak = 0
         self.max_batch_keys = max_batch_keys
         self.max_batch_segments = max_batch_segments
         self.ascending = ascending
@@ -256,6 +284,7 @@ class Server:
                 self.arena.free(*b.region)
                 self.failed.extend(b.requests)
                 continue
+            b.launched = now
             self.inflight.append(b)
             self.inflight_peak = max(self.inflight_peak, len(self.inflight))
 
@@ -268,6 +297,12 @@ class Server:
                     self.completions.append(Completion(r.rid, r.arrival, b.admitted, now,
                                                        r.length, b.bid, res))
                 self.arena.free(*b.region)
+            elif now - b.launched > self.watchdog_s:
+                # never completed: fail its requests; its memory and slot stay
+                # retired (the device may still write them)
+                self.ex.abandon(b.handle)
+                self.timed_out.extend(b.requests)
+                self.max_inflight -= 1
             else:
                 still.append(b)
         self.inflight = still
@@ -291,6 +326,15 @@ class Server:
                 i += 1
             self._reap(now)
             self._admit(now)
+            if self.max_inflight <= 0:        # every slot retired by the watchdog
+                self.timed_out.extend(self.pending)
+                self.pending.clear()
+                self.timed_out.extend(requests[i:])
+                i = n
+            q = len(self.pending)
+            self.queue_samples += 1
+            self.queue_sum += q
+            self.queue_peak = max(self.queue_peak, q)
             if i < n and not self.pending and not self.inflight:
                 wait = requests[i].arrival - clock()
                 if wait > 0:
@@ -305,7 +349,10 @@ class Server:
         keys = sum(c.length for c in self.completions)
         pct = (lambda q: float(np.percentile(lat, q))) if len(lat) else (lambda q: None)
         return {"requests": len(self.completions), "rejected": len(self.rejected),
-                "failed": len(self.failed), "batches": self.batches,
+                "failed": len(self.failed), "timed_out": len(self.timed_out),
+                "batches": self.batches,
+                "queue_depth_peak": self.queue_peak,
+                "queue_depth_mean": round(self.queue_sum / max(1, self.queue_samples), 3),
                 "mean_batch": round(len(self.completions) / max(1, self.batches), 2),
                 "inflight_peak": self.inflight_peak,
                 "arena_peak_keys": self.arena.peak,
@@ -322,19 +369,21 @@ def make_requests(duration_s: float, rate: float, seed: int, min_log2=8.0, max_l
     return [Request(i, float(a), int(n), int(s)) for i, (a, n, s) in enumerate(zip(t, lens, seeds))]
 
 
-def run_gpu(duration_s: float = 10.0, rate: float = 2000.0, budget_bytes: int = 32 << 30,
-            slots: int = 3, seed: int = W.SEED_BASE + 30) -> dict:
+def run_gpu(duration_s: float = 60.0, rate: float = 2000.0, budget_bytes: int = 32 << 30,
+            slots: int = 3, seed: int = W.SEED_BASE + 30, pack_single: bool = True) -> dict:
     """The serving workload: Poisson arrivals at `rate`, lengths log-uniform
     in [2^8, 2^22], keys uniform; `budget_bytes` of HBM for keys."""
     reqs = make_requests(duration_s, rate, seed)
     budget = budget_bytes // 4
-    ex = GpuExecutor(budget, slots, max_segments=1024)
+    ex = GpuExecutor(budget, slots, max_segments=1024, pack_single=pack_single)
     # warm the kernels and the per-stream scratch once before the clock starts
     warm = Server(ex, budget, max_inflight=slots)
     warm.run([Request(-1 - k, 0.0, 1 << 20, 7 + k) for k in range(slots * 2)])
     srv = Server(ex, budget, max_inflight=slots)
+    ex.segmented_batches = 0
     out = srv.run(reqs)
-    out.update({"duration_s": duration_s, "rate_per_s": rate, "budget_bytes": budget_bytes,
+    out.update({"segmented_batches": ex.segmented_batches,
+                "duration_s": duration_s, "rate_per_s": rate, "budget_bytes": budget_bytes,
                 "streams": slots, "offered_gkeys_s":
                 round(sum(r.length for r in reqs) / duration_s / 1e9, 4)})
     return out

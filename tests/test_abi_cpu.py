@@ -309,3 +309,8 @@ def test_noalloc_argument_errors(lib):
     assert lib.bitonic_sort_segmented_noalloc_i32(None, None, 3, 0, 1, None) == -1
     assert lib.bitonic_sort_segmented_noalloc_i32(None, 8, 3, 8, 1, None) == -1
     assert lib.bitonic_sort_segmented_noalloc_i32(6, 8, 3, 8, 1, None) == -1   # misaligned
+
+
+def test_segmented_default_bound_arguments(lib):
+    assert lib.bitonic_segmented_default_bound(None, 4) == -1
+    assert lib.bitonic_segmented_default_bound(64, 2) == -1

@@ -344,6 +344,21 @@ def test_segmented_fuse_depths(seg_fuse):
         B.bitonic_set_tuning_value("seg_fuse", saved)
 
 
+def test_segmented_default_bound():
+    """Without a bound the segmented sort bounds segments by the end of the
+    keys' allocation (no device read, no wait): at least the keys it was
+    given, at most 2^31, and the unbounded call sorts as the bounded one."""
+    keys, off = W.batched_workload(nseg=500, seed=15, max_log2=17)
+    t = torch.from_numpy(keys.copy()).cuda()
+    bound = B.bitonic_segmented_default_bound(t)
+    assert t.numel() <= bound <= 2**31
+    if bound < 2**31:
+        assert B.bitonic_segmented_default_bound(t[100:]) == bound - 100
+    for asc in (True, False):
+        got = gpu_sort_segmented(keys, off, asc)
+        assert np.array_equal(got, O.sort_segmented_i32(keys, off, asc)), asc
+
+
 def test_segmented_pass_grid_extremes():
     """The big-segment kernels split their units into one contiguous range per
     workgroup: with 1 pass workgroup per CU a range spans many segments, with

@@ -28,12 +28,17 @@ def _alone(r):
 
 
 def test_serving_results_alone_and_in_mix():
-    reqs = S.make_requests(0.6, 600, W.SEED_BASE + 30, min_log2=8, max_log2=18)
+    """The serving workload's length range (2^8 .. 2^22 keys): every request,
+    packed into segmented batches, equals the oracle's sort and the same
+    request sorted alone by the single-array entry point."""
+    reqs = S.make_requests(0.5, 600, W.SEED_BASE + 30, min_log2=8, max_log2=22)
+    assert max(r.length for r in reqs) > (1 << 21)
     ex = S.GpuExecutor(1 << 26, slots=3, max_segments=256)
     srv = S.Server(ex, 1 << 26, max_inflight=3, max_batch_segments=32, collect_results=True)
     rep = srv.run(reqs)
     print(f"[serving] {rep}", flush=True)
     assert rep["requests"] == len(reqs) and rep["failed"] == 0 and rep["rejected"] == 0
+    assert rep["timed_out"] == 0 and ex.segmented_batches == rep["batches"]
     by = {r.rid: r for r in reqs}
     for c in srv.completions:
         r = by[c.rid]

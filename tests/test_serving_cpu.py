@@ -100,3 +100,36 @@ def test_report_fields():
     for k in ("p50_ms", "p99_ms", "gkeys_s", "batches", "inflight_peak"):
         assert k in rep
     assert rep["p99_ms"] >= rep["p50_ms"] >= 0
+
+
+def test_watchdog_fails_stuck_batch_and_continues():
+    """A batch that never completes: the watchdog fails its requests after
+    watchdog_s, retires its slot and memory, and the loop serves the rest."""
+    reqs = [S.Request(i, 0.001 * i, 1000, i) for i in range(8)]
+    clk = VClock()
+    ex = S.FakeExecutor(1e9, 1e-4, hang_batches={2})
+    srv = S.Server(ex, 1 << 20, max_inflight=2, max_batch_segments=1, collect_results=True,
+                   watchdog_s=0.05)
+    rep = srv.run(reqs, clock=clk.now, sleep=clk.sleep)
+    assert [r.rid for r in srv.timed_out] == [2] and rep["timed_out"] == 1
+    assert ex.abandoned == [2]
+    assert sorted(c.rid for c in srv.completions) == [0, 1, 3, 4, 5, 6, 7]
+    assert srv.arena.used == 1024        # the stuck batch's region stays retired
+    for c in srv.completions:
+        assert np.array_equal(c.result, np.sort(W.uniform_i32(c.rid, 1000)))
+
+
+def test_watchdog_every_slot_stuck_ends_the_run():
+    """If every slot is retired the loop ends, failing what is left."""
+    reqs = [S.Request(i, 0.0, 100, i) for i in range(5)]
+    clk = VClock()
+    ex = S.FakeExecutor(1e9, 1e-4, hang_batches={0, 1})
+    srv = S.Server(ex, 1 << 20, max_inflight=2, max_batch_segments=1, watchdog_s=0.01)
+    rep = srv.run(reqs, clock=clk.now, sleep=clk.sleep)
+    assert rep["requests"] == 0 and rep["timed_out"] == 5
+
+
+def test_queue_depth_reported():
+    reqs = [S.Request(i, 0.0, 1 << 14, i) for i in range(20)]
+    _, _, rep = _serve(reqs, rate=1e8, latency=1e-3, inflight=1, max_batch_segments=2)
+    assert rep["queue_depth_peak"] >= 10 and rep["queue_depth_mean"] > 0
