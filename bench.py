@@ -54,6 +54,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+TUNING_FILE = os.path.join(ROOT, "paper_1506_01446_amd", "tuning", "mi355x.txt")
 PAPER_K10_MKEYS_2_24 = 2**24 / 56.27e-3 / 1e6   # section 5, table 1 (context only)
 
 
@@ -72,6 +73,8 @@ def parse():
     ap.add_argument("--serve-seconds", type=float, default=60.0)
     ap.add_argument("--no-hbm-true", action="store_true",
                     help="skip the per-kernel tables at n = 2^26 and 2^28")
+    ap.add_argument("--tuning", default=TUNING_FILE,
+                    help="plan table to load (bitonic_load_tuning); '' for the built-in plans")
     ap.add_argument("--out", default="")
     ap.add_argument("--ablation", action="store_true",
                     help="the paper's Table 1 layout on this GPU: Basic, Semi and "
@@ -556,6 +559,11 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     B.load()
     log(f"[bench] device {torch.cuda.get_device_name(0)}; {B.bitonic_version()}")
+    tuning = None
+    if args.tuning and os.path.exists(args.tuning):
+        rc = B.load().bitonic_load_tuning(args.tuning.encode())
+        tuning = {"file": os.path.relpath(args.tuning, ROOT), "status": B.STATUS.get(rc, rc)}
+        log(f"[bench] tuning {tuning}")
     plan = ("optimized", args.tile, args.fuse)
     n = args.n
     src = torch.from_numpy(W.uniform_i32(W.SEED_BASE + 2, n)).cuda()
@@ -659,7 +667,8 @@ def main():
                        "n": n, "plan": {"kind": "optimized",
                                         "tile_log2": B.bitonic_plan_tile_log2(n, plan),
                                         "fuse": args.fuse or B.bitonic_get_tuning_value("fuse")},
-                       "passes": passes, "parallelism": "single GPU"},
+                       "passes": passes, "parallelism": "single GPU",
+                       "tuning": tuning},
             "roofline": roofline, "cpu_baseline": cpu, "extra": extra}
     s = json.dumps(line)
     print(s, flush=True)

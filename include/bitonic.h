@@ -418,12 +418,23 @@ int bitonic_sort_plan_launches_i32(int32_t* keys, int64_t n, int ascending,
  * "merge_blocks_per_cu" (as in bitonic_plan), "seg_blocks_per_cu" (1..16, workgroups per compute unit of
  * the persistent small-segment kernel), "seg_pass_blocks_per_cu" (1..32,
  * workgroups per compute unit of the big-segment passes, default 8),
- * "seg_fuse" (1..5, steps per big-segment pass, default 5), "wide_tile_log2" (11..13) or
+ * "seg_fuse" (1..5, steps per big-segment pass, default 5), "tile_lane_steps"
+ * (1, the default: the tile sort runs its phases up to 9 as cross-lane
+ * compare-exchanges inside each wave; 0: every phase through LDS regroups),
+ * "wide_tile_log2" (11..13) or
  * "wide_fuse" (1..6) (the 8-byte sorts' plan); bitonic_get_tuning_value
  * reads one.
+ * Size buckets: "tile_log2@k", "fuse@k" and "merge_blocks_per_cu@k" (k =
+ * ceil(log2 n), 0..31) set the 4-byte sort's plan for that size only (0
+ * removes the entry); a bucket's entries take precedence over the global
+ * values, an explicit plan over both.
  * bitonic_load_tuning reads "<name> <value>" lines (the autotuner's output
- * file).  All return BITONIC_OK or BITONIC_EINVAL; they are not thread-safe
- * with concurrent sorts.
+ * file; '#' starts a comment).  A line "cus <count>" ties the file to
+ * devices with that many compute units: on the current device with another
+ * count nothing is applied and BITONIC_EUNSUPPORTED is returned.  The file
+ * named by the environment variable BITONIC_TUNE_FILE, if set, is loaded
+ * once before the first sort.  All return BITONIC_OK or BITONIC_EINVAL; they
+ * are not thread-safe with concurrent sorts.
  */
 int bitonic_set_tuning(int tile_log2, int fuse, int merge_blocks_per_cu);
 int bitonic_set_tuning_value(const char* key, int value);

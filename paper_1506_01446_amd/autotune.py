@@ -1,136 +1,223 @@
 """Autotuner for the bitonic sort library.
 
-python -m paper_1506_01446_amd.autotune [--n 16777216] [--out tuning.txt]
+python -m paper_1506_01446_amd.autotune [--buckets 16,18,20,22,24,26,28]
+        [--reps 5] [--out paper_1506_01446_amd/tuning/mi355x.txt]
+        [--log profiles/autotune_mi355x.txt]
 
-Searches, on the GPU, the plan parameters that do not change the result:
-  tile_log2            keys per on-chip tile (2^12 .. 2^15)
-  fuse                 long-stride steps fused per HBM pass (5 .. 8)
-  merge_blocks_per_cu  tile-merge workgroups per compute unit (-1: one tile each)
-for the single-array sort of n keys, and
-  seg_blocks_per_cu    workgroups per compute unit of the persistent
-                       small-segment kernel
-  seg_pass_blocks_per_cu  workgroups per compute unit of the big-segment
-                       passes
-on the batched segmented workload.  Every candidate is timed with HIP events
-over fresh copies of the same seeded input (median of several runs) and its
-output checked sorted; the fastest are written as "<name> <value>" lines that
-bitonic_load_tuning reads.
+Searches, on the GPU, the plan parameters that do not change the result
+(the paper leaves the shared-memory tile and the register fusion depth open,
+sections 4.1 and 4.2):
+  per size bucket k (n = 2^k keys, single-array 4-byte sort)
+    tile_log2            keys per on-chip tile (2^12 .. 2^15)
+    fuse                 long-stride steps fused per HBM pass (4 .. 8)
+    merge_blocks_per_cu  tile-merge workgroups per compute unit (-1: one
+                         tile each)
+  segmented sort (the 8192-segment batched workload, and a table of 64
+  segments of the serving workload's lengths, 2^8 .. 2^22 keys)
+    seg_blocks_per_cu       small-segment kernel workgroups per compute unit
+    seg_pass_blocks_per_cu  big-segment pass workgroups per compute unit
+    seg_fuse                steps per big-segment pass (3 .. 5)
+  8-byte sorts (int64 keys at n = 2^24)
+    wide_tile_log2, wide_fuse
+Every candidate is timed with HIP events over fresh copies of the same seeded
+input (median of `reps` runs) and its output checked sorted.  The winners are
+written as "<name> <value>" lines (bucket entries as "name@k") under a
+"cus <count>" line, which bitonic_load_tuning reads; every timing goes to the
+log, one JSON object per line.
 """
 from __future__ import annotations
 
 import argparse
+import datetime
 import itertools
 import json
+import os
 import statistics
 import sys
 
 from . import binding as B
 from . import workloads as W
 
+HERE = os.path.dirname(os.path.abspath(__file__))
+DEFAULT_OUT = os.path.join(HERE, "tuning", "mi355x.txt")
 
-def _time_plain(torch, src, plan, reps: int) -> float:
+
+def _events(torch):
     ev = B.HipEvents(2)
     rt = ev.rt
     rt.hipEventRecord.argtypes = [B.ctypes.c_void_p, B.ctypes.c_void_p]
-    st = torch.cuda.current_stream().cuda_stream
+    return ev, rt, torch.cuda.current_stream().cuda_stream
+
+
+def _median_ms(torch, reset, run, reps: int) -> float:
+    ev, rt, st = _events(torch)
+    reset()
+    run()
     times = []
-    buf = src.clone()
-    B.bitonic_sort_plan_i32(buf, True, plan)  # warm
     for _ in range(reps):
-        buf.copy_(src)
+        reset()
         torch.cuda.synchronize()
         rt.hipEventRecord(ev.ev[0], st)
-        B.bitonic_sort_plan_i32(buf, True, plan)
+        run()
         rt.hipEventRecord(ev.ev[1], st)
         torch.cuda.synchronize()
         times.append(ev.elapsed_ms(0, 1))
-    ok = bool((buf[1:] >= buf[:-1]).all().item())
     ev.close()
-    if not ok:
+    return statistics.median(times)
+
+
+def _time_plain(torch, src, buf, plan, reps: int) -> float:
+    ms = _median_ms(torch, lambda: buf.copy_(src),
+                    lambda: B.bitonic_sort_plan_i32(buf, True, plan), reps)
+    if not bool((buf[1:] >= buf[:-1]).all().item()):
         raise RuntimeError(f"plan {plan} produced unsorted output")
-    return statistics.median(times)
+    return ms
 
 
-def _time_segmented(torch, keys, offs, max_len, reps: int) -> float:
-    ev = B.HipEvents(2)
-    rt = ev.rt
-    rt.hipEventRecord.argtypes = [B.ctypes.c_void_p, B.ctypes.c_void_p]
-    st = torch.cuda.current_stream().cuda_stream
-    buf = keys.clone()
-    B.bitonic_sort_segmented_i32(buf, offs, True, max_seg_len=max_len)
-    times = []
-    for _ in range(reps):
-        buf.copy_(keys)
-        torch.cuda.synchronize()
-        rt.hipEventRecord(ev.ev[0], st)
-        B.bitonic_sort_segmented_i32(buf, offs, True, max_seg_len=max_len)
-        rt.hipEventRecord(ev.ev[1], st)
-        torch.cuda.synchronize()
-        times.append(ev.elapsed_ms(0, 1))
-    ev.close()
-    return statistics.median(times)
+def _segment_tables(torch):
+    """The batched workload and a serving-sized table, on the device."""
+    keys, off = W.batched_workload()
+    lens = W.segment_lengths(W.SEED_BASE + 40, 64, 14.0)
+    lens = (lens * 256).clip(256, 1 << 22)            # 2^8 .. 2^22 keys
+    off2 = W.offsets_from_lengths(lens)
+    keys2 = W.uniform_i32(W.SEED_BASE + 41, int(off2[-1]))
+    out = []
+    for k, o in ((keys, off), (keys2, off2)):
+        out.append((torch.from_numpy(k).cuda(), torch.from_numpy(o).cuda(),
+                    int((o[1:] - o[:-1]).max())))
+    return out
 
 
-def tune(n: int = 1 << 24, reps: int = 5, quick: bool = False, log=print) -> dict:
+def _time_segmented(torch, tables, reps: int) -> float:
+    total = 0.0
+    for kt, ot, mx in tables:
+        buf = kt.clone()
+        total += _median_ms(torch, lambda: buf.copy_(kt),
+                            lambda: B.bitonic_sort_segmented_i32(buf, ot, True, max_seg_len=mx),
+                            reps)
+    return total
+
+
+def tune(buckets=(16, 18, 20, 22, 24, 26, 28), reps: int = 5, quick: bool = False,
+         log=print) -> dict:
     import torch
     B.load()
-    src = torch.from_numpy(W.uniform_i32(W.SEED_BASE + 2, n)).cuda()
-    tiles = (14,) if quick else (12, 13, 14, 15)
-    fuses = (7, 8) if quick else (5, 6, 7, 8)
+    best = {"cus": torch.cuda.get_device_properties(0).multi_processor_count,
+            "device": torch.cuda.get_device_name(0), "buckets": {}}
+    tiles = (13, 14) if quick else (12, 13, 14, 15)
+    fuses = (7, 8) if quick else (4, 5, 6, 7, 8)
     merges = (2,) if quick else (-1, 1, 2, 4)
-    results = []
-    for t, f, m in itertools.product(tiles, fuses, merges):
-        ms = _time_plain(torch, src, ("optimized", t, f, m), reps)
-        results.append((ms, t, f, m))
-        log(json.dumps({"tile_log2": t, "fuse": f, "merge_blocks_per_cu": m, "ms": round(ms, 4)}))
-    results.sort()
-    best = results[0]
-    keys, off = W.batched_workload()
-    kt = torch.from_numpy(keys).cuda()
-    ot = torch.from_numpy(off).cuda()
-    max_len = int((off[1:] - off[:-1]).max())
+    for k in buckets:
+        n = 1 << k
+        src = torch.empty(n, dtype=torch.int32, device="cuda")
+        B.bitonic_keygen_i32(src, W.SEED_BASE + k)
+        buf = torch.empty_like(src)
+        default_ms = _time_plain(torch, src, buf, None, reps)
+        rows = []
+        for t, f, m in itertools.product(tiles, fuses, merges):
+            if t > k:
+                continue
+            ms = _time_plain(torch, src, buf, ("optimized", t, f, m), reps)
+            rows.append((ms, t, f, m))
+            log(json.dumps({"bucket": k, "tile_log2": t, "fuse": f, "merge_blocks_per_cu": m,
+                            "ms": round(ms, 4)}))
+        rows.sort()
+        ms, t, f, m = rows[0]
+        best["buckets"][k] = {"tile_log2": t, "fuse": f, "merge_blocks_per_cu": m,
+                              "ms": round(ms, 4), "default_ms": round(default_ms, 4)}
+        log(json.dumps({"bucket": k, "best": best["buckets"][k]}))
+        del src, buf
+    tables = _segment_tables(torch)
     seg = []
-    for bpc in ((4,) if quick else (2, 3, 4, 6)):
+    for bpc in ((4,) if quick else (2, 3, 4, 6, 8)):
         B.bitonic_set_tuning_value("seg_blocks_per_cu", bpc)
-        ms = _time_segmented(torch, kt, ot, max_len, reps)
+        ms = _time_segmented(torch, tables[:1], reps)
         seg.append((ms, bpc))
         log(json.dumps({"seg_blocks_per_cu": bpc, "ms": round(ms, 4)}))
     seg.sort()
     B.bitonic_set_tuning_value("seg_blocks_per_cu", seg[0][1])
     segp = []
-    for bpc in ((8,) if quick else (4, 8, 16)):
+    for bpc, sf in itertools.product((8,) if quick else (4, 8, 16), (5,) if quick else (3, 4, 5)):
         B.bitonic_set_tuning_value("seg_pass_blocks_per_cu", bpc)
-        ms = _time_segmented(torch, kt, ot, max_len, reps)
-        segp.append((ms, bpc))
-        log(json.dumps({"seg_pass_blocks_per_cu": bpc, "ms": round(ms, 4)}))
+        B.bitonic_set_tuning_value("seg_fuse", sf)
+        ms = _time_segmented(torch, tables, reps)
+        segp.append((ms, bpc, sf))
+        log(json.dumps({"seg_pass_blocks_per_cu": bpc, "seg_fuse": sf, "ms_both_tables": round(ms, 4)}))
     segp.sort()
     B.bitonic_set_tuning_value("seg_pass_blocks_per_cu", segp[0][1])
-    return {"tile_log2": best[1], "fuse": best[2], "merge_blocks_per_cu": best[3],
-            "seg_blocks_per_cu": seg[0][1], "seg_pass_blocks_per_cu": segp[0][1],
-            "sort_ms": round(best[0], 4), "segmented_ms": round(segp[0][0], 4), "n": n}
+    B.bitonic_set_tuning_value("seg_fuse", segp[0][2])
+    best.update({"seg_blocks_per_cu": seg[0][1], "seg_pass_blocks_per_cu": segp[0][1],
+                 "seg_fuse": segp[0][2], "segmented_ms": round(segp[0][0], 4)})
+    del tables
+    n = 1 << 24
+    k64 = torch.from_numpy(W.uniform_i64(W.SEED_BASE + 2, n)).cuda()
+    buf = torch.empty_like(k64)
+    wide = []
+    for t, f in itertools.product((13,) if quick else (11, 12, 13), (6,) if quick else (4, 5, 6)):
+        plan = ("optimized", t, f)
+        ms = _median_ms(torch, lambda: buf.copy_(k64),
+                        lambda: B.bitonic_sort_wide_plan(buf, None, True, "int64", plan), reps)
+        if not bool((buf[1:] >= buf[:-1]).all().item()):
+            raise RuntimeError(f"8-byte plan {plan} produced unsorted output")
+        wide.append((ms, t, f))
+        log(json.dumps({"wide_tile_log2": t, "wide_fuse": f, "ms": round(ms, 4)}))
+    wide.sort()
+    best.update({"wide_tile_log2": wide[0][1], "wide_fuse": wide[0][2],
+                 "wide_ms": round(wide[0][0], 4)})
+    return best
 
 
-def write_tuning(path: str, best: dict) -> None:
+def write_tuning(path: str, best: dict, command: str = "") -> None:
+    """The tuning file: global values, then per-bucket entries; with "cus"
+    when known.  Accepts the autotuner's result or a plain dict of global
+    values."""
+    os.makedirs(os.path.dirname(os.path.abspath(path)), exist_ok=True)
     with open(path, "w") as f:
-        f.write(f"tile_log2 {best['tile_log2']}\n")
-        f.write(f"fuse {best['fuse']}\n")
-        f.write(f"merge_blocks_per_cu {best['merge_blocks_per_cu']}\n")
-        f.write(f"seg_blocks_per_cu {best['seg_blocks_per_cu']}\n")
-        if "seg_pass_blocks_per_cu" in best:
-            f.write(f"seg_pass_blocks_per_cu {best['seg_pass_blocks_per_cu']}\n")
+        if "device" in best:
+            f.write(f"# bitonic sort plan table, autotuned on {best['device']} "
+                    f"({best['cus']} compute units), {datetime.date.today()}\n")
+        if command:
+            f.write(f"# command: {command}\n")
+        if "cus" in best:
+            f.write(f"cus {best['cus']}\n")
+        for name in ("tile_log2", "fuse", "merge_blocks_per_cu", "seg_blocks_per_cu",
+                     "seg_pass_blocks_per_cu", "seg_fuse", "wide_tile_log2", "wide_fuse"):
+            if name in best:
+                f.write(f"{name} {best[name]}\n")
+        for k, e in sorted(best.get("buckets", {}).items()):
+            f.write(f"# n = 2^{k}: {e['ms']} ms tuned, {e['default_ms']} ms with the built-in plan\n")
+            for name in ("tile_log2", "fuse", "merge_blocks_per_cu"):
+                f.write(f"{name}@{k} {e[name]}\n")
 
 
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
-    ap.add_argument("--n", type=int, default=1 << 24)
+    ap.add_argument("--buckets", default="16,18,20,22,24,26,28")
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--quick", action="store_true")
-    ap.add_argument("--out", default="tuning.txt")
+    ap.add_argument("--out", default=DEFAULT_OUT)
+    ap.add_argument("--log", default="")
     a = ap.parse_args(argv)
-    best = tune(a.n, a.reps, a.quick, log=lambda s: print(s, file=sys.stderr, flush=True))
-    write_tuning(a.out, best)
+    buckets = tuple(int(x) for x in a.buckets.split(",") if x)
+    logf = open(a.log, "w") if a.log else None
+
+    def log(s):
+        print(s, file=sys.stderr, flush=True)
+        if logf:
+            logf.write(s + "\n")
+            logf.flush()
+
+    if logf:
+        logf.write("# autotuner timings (ms, median of --reps runs), one JSON object per line\n")
+        logf.write("# command: python -m paper_1506_01446_amd.autotune " + " ".join(
+            argv if argv is not None else sys.argv[1:]) + "\n")
+    best = tune(buckets, a.reps, a.quick, log=log)
+    write_tuning(a.out, best, "python -m paper_1506_01446_amd.autotune " + " ".join(
+        argv if argv is not None else sys.argv[1:]))
     B.bitonic_load_tuning(a.out)
     print(json.dumps(best))
+    if logf:
+        logf.close()
     return 0
 
 

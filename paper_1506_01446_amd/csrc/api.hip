@@ -17,6 +17,7 @@
 #include <atomic>
 #include <climits>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -37,11 +38,13 @@ static std::atomic<int> g_wide_fuse{6};
 static std::atomic<int> g_seg_bpc{4};    // small-segment workgroups per compute unit
 static std::atomic<int> g_seg_pass_bpc{8};  // big-segment pass workgroups per compute unit
 static std::atomic<int> g_seg_fuse{kSegFuseMax};  // steps per big-segment pass
+static std::atomic<int> g_tile_lane{1};  // tile sort with cross-lane steps (program kind 4)
 
 struct Resolved {
   int kind;
   int tile;
   int fuse;
+  int sort_kind = 0;      // tile-sort program: 0, or 4 with cross-lane steps
   int merge_bpc;          // tile-merge workgroups per compute unit
   uint32_t merge_blocks;  // merge_bpc x compute units (set when enqueueing)
   bool scalar_io = false;  // optimized plan for an array off a 16-byte boundary
@@ -56,12 +59,44 @@ static int default_tile_log2(int64_t n) {
   return k <= 16 ? 12 : (k <= 20 ? 13 : 14);
 }
 
+static int ceil_log2(int64_t n) {
+  int k = 0;
+  while ((int64_t(1) << k) < n) ++k;
+  return k;
+}
+
+// Tuned plans by size bucket k = ceil(log2 n) (tuning keys "tile_log2@k",
+// "fuse@k", "merge_blocks_per_cu@k"; 0 = no entry).  A bucket's entries take
+// precedence over the global tuning values, an explicit plan over both.
+constexpr int kBuckets = 32;
+static std::atomic<int> g_bk_tile[kBuckets];
+static std::atomic<int> g_bk_fuse[kBuckets];
+static std::atomic<int> g_bk_merge[kBuckets];  // -1: one tile per workgroup
+
+// The tuning file named by the environment variable BITONIC_TUNE_FILE, if
+// any, is loaded once, before the first plan is resolved.
+static void load_env_tuning_once() {
+  static std::once_flag once;
+  std::call_once(once, [] {
+    const char* p = std::getenv("BITONIC_TUNE_FILE");
+    if (p && *p) (void)bitonic_load_tuning(p);
+  });
+}
+
 static int resolve(const bitonic_plan* plan, int64_t n, Resolved* r) {
+  load_env_tuning_once();
   r->kind = BITONIC_PLAN_OPTIMIZED;
   r->tile = g_tile_log2.load();
   r->fuse = g_fuse.load();
   r->merge_bpc = g_merge_bpc.load();
   r->merge_blocks = 0;
+  r->sort_kind = g_tile_lane.load() ? 4 : 0;
+  {
+    const int k = n > (int64_t(1) << 31) ? 31 : ceil_log2(n < 1 ? 1 : n);
+    if (const int t = g_bk_tile[k].load()) r->tile = t;
+    if (const int f = g_bk_fuse[k].load()) r->fuse = f;
+    if (const int m = g_bk_merge[k].load()) r->merge_bpc = m > 0 ? m : 0;
+  }
   if (plan) {
     if (plan->kind < BITONIC_PLAN_AUTO || plan->kind > BITONIC_PLAN_OPTIMIZED) return BITONIC_EINVAL;
     if (plan->merge_blocks_per_cu < -1 || plan->merge_blocks_per_cu > 16) return BITONIC_EINVAL;
@@ -79,12 +114,6 @@ static int resolve(const bitonic_plan* plan, int64_t n, Resolved* r) {
   if (r->kind == BITONIC_PLAN_OPTIMIZED && !tile_log2_supported(r->tile)) return BITONIC_EINVAL;
   if (r->fuse < 1 || r->fuse > kFuseMax) return BITONIC_EINVAL;
   return BITONIC_OK;
-}
-
-static int ceil_log2(int64_t n) {
-  int k = 0;
-  while ((int64_t(1) << k) < n) ++k;
-  return k;
 }
 
 // Receives every launch of a plan as it is enqueued (or counted).
@@ -169,7 +198,7 @@ static int64_t enqueue_plain(int32_t* keys, uint32_t n, int K, Codec flip, const
            [&] { launch_tile_scalar(0, keys, n, flip, CX_BOTH, st); });
     else
       emit(tile_shape(BITONIC_LAUNCH_TILE_SORT, K),
-           [&] { launch_tile(K, 0, keys, n, flip, CX_BOTH, 0, st); });
+           [&] { launch_tile(K, r.sort_kind, keys, n, flip, CX_BOTH, 0, st); });
     return launches;
   }
   // The tile sort encodes the keys and the last merge decodes them; the
@@ -183,7 +212,7 @@ static int64_t enqueue_plain(int32_t* keys, uint32_t n, int K, Codec flip, const
     if (r.scalar_io)
       launch_tile_scalar(0, keys, n, flip, CX_ENC, st);
     else
-      launch_tile(L, 0, keys, n, flip, CX_ENC, 0, st);
+      launch_tile(L, r.sort_kind, keys, n, flip, CX_ENC, 0, st);
   });
   for (int p = L + 1; p <= K; ++p) {
     const int nb = p - L;                          // long-stride steps
@@ -452,6 +481,7 @@ static int64_t enqueue_wide(int64_t* k64, int32_t* k32, int32_t* vals, uint32_t 
 }
 
 static int resolve_wide(const bitonic_plan* plan, int* L, int* F) {
+  load_env_tuning_once();
   *L = g_wide_tile_log2.load();
   *F = g_wide_fuse.load();
   if (plan) {
@@ -742,6 +772,7 @@ static int sort_segmented(void* keys_v, int32_t* values, const int64_t* offsets,
       (reinterpret_cast<uintptr_t>(values) & 3u) != 0)
     return BITONIC_EINVAL;
   hipStream_t st = (hipStream_t)stream;
+  load_env_tuning_once();
   int dev = 0;
   int rc = current_device(&dev);
   if (rc) return rc;
@@ -819,8 +850,47 @@ int bitonic_set_tuning(int tile_log2, int fuse, int merge_blocks_per_cu) {
   return BITONIC_OK;
 }
 
+// "name@k": an entry of size bucket k (0..31) for tile_log2, fuse or
+// merge_blocks_per_cu; 0 removes it.
+static int set_bucket_value(const char* name, size_t len, int k, int value) {
+  if (k < 0 || k >= kBuckets) return BITONIC_EINVAL;
+  auto is = [&](const char* s) { return std::strlen(s) == len && !std::strncmp(name, s, len); };
+  if (is("tile_log2")) {
+    if (value && !tile_log2_supported(value)) return BITONIC_EINVAL;
+    g_bk_tile[k].store(value);
+  } else if (is("fuse")) {
+    if (value && (value < 1 || value > kFuseMax)) return BITONIC_EINVAL;
+    g_bk_fuse[k].store(value);
+  } else if (is("merge_blocks_per_cu")) {
+    if (value < -1 || value > 16) return BITONIC_EINVAL;
+    g_bk_merge[k].store(value);
+  } else {
+    return BITONIC_EINVAL;
+  }
+  return BITONIC_OK;
+}
+
+static bool parse_bucket_key(const char* key, size_t* len, int* k) {
+  const char* at = std::strchr(key, '@');
+  if (!at || !at[1]) return false;
+  char* end = nullptr;
+  const long v = std::strtol(at + 1, &end, 10);
+  if (*end != 0 || v < 0 || v >= kBuckets) {
+    *k = -1;
+  } else {
+    *k = (int)v;
+  }
+  *len = (size_t)(at - key);
+  return true;
+}
+
 int bitonic_set_tuning_value(const char* key, int value) {
   if (!key) return BITONIC_EINVAL;
+  {
+    size_t len = 0;
+    int k = 0;
+    if (parse_bucket_key(key, &len, &k)) return set_bucket_value(key, len, k, value);
+  }
   if (!std::strcmp(key, "tile_log2")) {
     if (value == 0) {  // back to the library's choice by n
       g_tile_log2.store(0);
@@ -846,6 +916,11 @@ int bitonic_set_tuning_value(const char* key, int value) {
     g_seg_fuse.store(value);
     return BITONIC_OK;
   }
+  if (!std::strcmp(key, "tile_lane_steps")) {
+    if (value < 0 || value > 1) return BITONIC_EINVAL;
+    g_tile_lane.store(value);
+    return BITONIC_OK;
+  }
   if (!std::strcmp(key, "wide_tile_log2")) {
     if (value < kWideTileMinLog2 || value > kWideTileMaxLog2) return BITONIC_EINVAL;
     g_wide_tile_log2.store(value);
@@ -861,12 +936,26 @@ int bitonic_set_tuning_value(const char* key, int value) {
 
 int bitonic_get_tuning_value(const char* key, int* value) {
   if (!key || !value) return BITONIC_EINVAL;
+  {
+    size_t len = 0;
+    int k = 0;
+    if (parse_bucket_key(key, &len, &k)) {
+      if (k < 0) return BITONIC_EINVAL;
+      auto is = [&](const char* s) { return std::strlen(s) == len && !std::strncmp(key, s, len); };
+      if (is("tile_log2")) *value = g_bk_tile[k].load();
+      else if (is("fuse")) *value = g_bk_fuse[k].load();
+      else if (is("merge_blocks_per_cu")) *value = g_bk_merge[k].load();
+      else return BITONIC_EINVAL;
+      return BITONIC_OK;
+    }
+  }
   if (!std::strcmp(key, "tile_log2")) *value = g_tile_log2.load();
   else if (!std::strcmp(key, "fuse")) *value = g_fuse.load();
   else if (!std::strcmp(key, "merge_blocks_per_cu")) *value = g_merge_bpc.load() ? g_merge_bpc.load() : -1;
   else if (!std::strcmp(key, "seg_blocks_per_cu")) *value = g_seg_bpc.load();
   else if (!std::strcmp(key, "seg_pass_blocks_per_cu")) *value = g_seg_pass_bpc.load();
   else if (!std::strcmp(key, "seg_fuse")) *value = g_seg_fuse.load();
+  else if (!std::strcmp(key, "tile_lane_steps")) *value = g_tile_lane.load();
   else if (!std::strcmp(key, "wide_tile_log2")) *value = g_wide_tile_log2.load();
   else if (!std::strcmp(key, "wide_fuse")) *value = g_wide_fuse.load();
   else return BITONIC_EINVAL;
@@ -877,14 +966,44 @@ int bitonic_load_tuning(const char* path) {
   if (!path) return BITONIC_EINVAL;
   FILE* f = std::fopen(path, "r");
   if (!f) return BITONIC_EINVAL;
-  char key[64];
-  int val;
+  // "<name> <value>" lines; '#' starts a comment.  A "cus <count>" line ties
+  // the file to devices with that many compute units: on another device
+  // nothing in the file is applied.
+  struct Entry {
+    char key[64];
+    int value;
+  };
+  std::vector<Entry> entries;
+  char line[256];
   int rc = BITONIC_OK;
-  while (std::fscanf(f, "%63s %d", key, &val) == 2) {
-    const int r = bitonic_set_tuning_value(key, val);
-    if (r) rc = r;
+  int cus = 0;
+  while (std::fgets(line, sizeof line, f)) {
+    char* hash = std::strchr(line, '#');
+    if (hash) *hash = 0;
+    Entry e{};
+    char extra[8];
+    const int got = std::sscanf(line, "%63s %d %7s", e.key, &e.value, extra);
+    if (got <= 0) continue;  // blank or comment
+    if (got != 2) {
+      rc = BITONIC_EINVAL;
+      continue;
+    }
+    if (!std::strcmp(e.key, "cus")) cus = e.value;
+    else entries.push_back(e);
   }
   std::fclose(f);
+  if (cus > 0) {
+    int dev = 0, have = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&have, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+        have > 0 && have != cus)
+      return BITONIC_EUNSUPPORTED;
+    (void)hipGetLastError();
+  }
+  for (const Entry& e : entries) {
+    const int r = bitonic_set_tuning_value(e.key, e.value);
+    if (r) rc = r;
+  }
   return rc;
 }
 

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <climits>
+
 #include <type_traits>
 
 #include "codec.hpp"
@@ -66,16 +68,59 @@ struct Prog {
   static constexpr int NT = 1 << (L_ - R_LOG_);
   static constexpr int T = 1 << L_;
   static constexpr uint32_t LDSW = lds_words(L_, R_LOG_);  // padded LDS words of a tile
-  static constexpr bool VEC = KIND_ < 2;  // 16-byte vector global I/O allowed
+  static constexpr bool VEC = kind_is_vector(KIND_);  // 16-byte vector global I/O allowed
   // Recompute each layout's thread base at its regroup (fewer registers,
   // more ALU); used by the segment kernels, which run several programs in
   // one kernel.  (The single-array tile kernels keep the bases: 59 VGPRs
   // for the 2^14-key sort, 114 for the 2^15-key merge loop, both within the
   // 128 their workgroup sizes allow.)
-  static constexpr bool LEAN = KIND_ >= 2;
+  static constexpr bool LEAN = KIND_ == 2 || KIND_ == 3;
   static constexpr Program value = make_program(L_, R_LOG_, KIND_);
   static_assert(value.ngroups <= kMaxGroups, "program too long");
 };
+
+// v's value in lane (this lane XOR M) of the wave: DPP moves inside rows of
+// 16 lanes for M < 16, the swizzle that reverses groups of 32 lanes for
+// M = 31, a lane permute for M = 63.
+template <uint32_t M>
+__device__ __forceinline__ int32_t lane_xor(int32_t v) {
+  if constexpr (M == 1) return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false);   // quad_perm 1032
+  else if constexpr (M == 2) return __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false);  // 2301
+  else if constexpr (M == 3) return __builtin_amdgcn_mov_dpp(v, 0x1B, 0xF, 0xF, false);  // 3210
+  else if constexpr (M == 7) return __builtin_amdgcn_mov_dpp(v, 0x141, 0xF, 0xF, false);  // row_half_mirror
+  else if constexpr (M == 15) return __builtin_amdgcn_mov_dpp(v, 0x140, 0xF, 0xF, false);  // row_mirror
+  else if constexpr (M == 8) return __builtin_amdgcn_mov_dpp(v, 0x128, 0xF, 0xF, false);   // row_ror:8
+  else if constexpr (M == 4) return lane_xor<3>(lane_xor<7>(v));
+  else if constexpr (M == 31) return __builtin_amdgcn_ds_swizzle(v, 0x7C1F);  // xor 31 in 32 lanes
+  else if constexpr (M == 63) {
+    const uint32_t lane = __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+    return __builtin_amdgcn_ds_bpermute((int)((lane ^ 63u) << 2), v);
+  } else static_assert(M == 1, "lane exchange pattern not provided");
+  return v;
+}
+
+// The key a lane keeps from the pair (a, b): the maximum where c = INT32_MAX
+// (the upper end of the pair), the minimum where c = INT32_MIN; one v_med3.
+__device__ __forceinline__ int32_t keep_of_pair(int32_t a, int32_t b, int32_t c) {
+  return max(min(a, b), min(max(a, b), c));
+}
+
+// A lane step of one register with itself (partner: the same slot of lane
+// XOR M).  For M = 16 and 32 the gfx950 permlane swaps of the register with
+// itself leave the pair's two keys in every lane (the swap's two results), in
+// either order, which is all keep_of_pair needs.
+template <uint32_t M>
+__device__ __forceinline__ int32_t lane_pair_step(int32_t x, int32_t c) {
+  if constexpr (M == 16) {
+    const auto s = __builtin_amdgcn_permlane16_swap((uint32_t)x, (uint32_t)x, false, false);
+    return keep_of_pair((int32_t)s[0], (int32_t)s[1], c);
+  } else if constexpr (M == 32) {
+    const auto s = __builtin_amdgcn_permlane32_swap((uint32_t)x, (uint32_t)x, false, false);
+    return keep_of_pair((int32_t)s[0], (int32_t)s[1], c);
+  } else {
+    return keep_of_pair(x, lane_xor<M>(x), c);
+  }
+}
 
 // All compare-exchange steps of group G on the registers.
 template <class PR, int G, class E>
@@ -83,17 +128,39 @@ __device__ __forceinline__ void group_steps(E (&x)[PR::R]) {
   constexpr Group gr = PR::value.g[G];
   static_for<0, gr.nsteps>([&](auto S) {
     constexpr uint32_t D = gr.d[S];
-    static_for<0, PR::R>([&](auto J) {
-      constexpr uint32_t j = J;
-      constexpr uint32_t jj = j ^ D;
-      if constexpr (j < jj) {
-        if constexpr (slot_is_lower(gr, j, D)) {
-          cmpx(x[j], x[jj]);
-        } else {
-          cmpx(x[jj], x[j]);
+    if constexpr (step_lane(D) == 0) {
+      static_for<0, PR::R>([&](auto J) {
+        constexpr uint32_t j = J;
+        constexpr uint32_t jj = j ^ D;
+        if constexpr (j < jj) {
+          if constexpr (slot_is_lower(gr, j, D)) {
+            cmpx(x[j], x[jj]);
+          } else {
+            cmpx(x[jj], x[j]);
+          }
         }
-      }
-    });
+      });
+    } else {
+      // lane step: every slot meets a slot of lane (lane XOR M); the lane
+      // whose bit highbit(M) is set holds the upper end of all its pairs
+      static_assert(sizeof(E) == 4, "lane steps move 4-byte keys");
+      constexpr uint32_t M = step_lane(D);
+      constexpr uint32_t DR = step_reg(D);
+      const uint32_t lane = __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+      const int32_t c = ((lane >> highbit(M)) & 1u) ? INT32_MAX : INT32_MIN;
+      static_for<0, PR::R>([&](auto J) {
+        constexpr uint32_t j = J;
+        constexpr uint32_t jj = j ^ DR;
+        if constexpr (DR == 0) {
+          x[j] = lane_pair_step<M>(x[j], c);
+        } else if constexpr (j < jj) {
+          const int32_t pa = lane_xor<M>(x[jj]);
+          const int32_t pb = lane_xor<M>(x[j]);
+          x[j] = keep_of_pair(x[j], pa, c);
+          x[jj] = keep_of_pair(x[jj], pb, c);
+        }
+      });
+    }
   });
 }
 

@@ -18,7 +18,8 @@ constexpr int kLdsNetworkMaxLog2 = 13;
 
 bool tile_log2_supported(int L);
 
-// Tile sort (kind 0: phases 1..L) or tile merge (kind 1: strides
+// Tile sort (kind 0: phases 1..L; kind 4: the same with its steps on lane
+// bits as cross-lane steps) or tile merge (kind 1: strides
 // 2^(L-1)..1) over every 2^L tile of keys[0, n).  The merge runs at most
 // max_blocks workgroups (0 = one per tile), each looping over its tiles.
 // cx (CX_*): whether loads encode and stores decode; a tile sort takes

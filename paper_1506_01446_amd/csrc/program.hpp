@@ -22,6 +22,14 @@
 // depends on j and the layout, so it is decided at compile time and the step
 // compiles to straight v_min_i32 / v_max_i32 pairs.
 //
+// A "lane step" (a nonzero lane part, D >> 8) pairs slot j of lane l with
+// slot j XOR (D & 0xFF) of lane l XOR (D >> 8) of the same wave: a step on
+// index bits that the layout maps to lane bits, done with cross-lane moves
+// (DPP) instead of a regroup through LDS.  Lane steps occur only in the
+// blocked layout of the tile sort, where lane bit k is index bit r + k, and
+// the highest index bit a lane step flips is always a lane bit, so the lower
+// end of each pair is the lane whose bit highbit(D >> 8) is clear.
+//
 // LDS holds a tile at padded positions P(i) = i + floor(i / 32) (one unused
 // word after every 32), which spreads strided accesses over the banks.  P is
 // additive over bit-disjoint parts, so the LDS address of a slot is a
@@ -38,7 +46,7 @@
 namespace bitonic {
 
 constexpr int kMaxRegBits = 6;
-constexpr int kMaxSteps = 28;
+constexpr int kMaxSteps = 80;  // a tile of 2^15 keys with lane steps holds 66 in one layout
 constexpr int kMaxGroups = 40;
 
 struct Group {
@@ -55,6 +63,13 @@ struct Program {
   int ngroups = 0;
   Group g[kMaxGroups] = {};
 };
+
+// The register and lane parts of a step, and a lane step built from them.
+constexpr uint32_t step_reg(uint32_t D) { return D & 0xFFu; }
+constexpr uint32_t step_lane(uint32_t D) { return D >> 8; }
+constexpr uint32_t lane_step(uint32_t lane_mask, uint32_t reg_mask) {
+  return (lane_mask << 8) | reg_mask;
+}
 
 constexpr int highbit(uint32_t x) {
   int h = -1;
@@ -200,7 +215,31 @@ constexpr void add_merge_bits(Program& P, int top, bool mirror) {
 // vector I/O the keys are loaded straight into the blocked layout (R / 4
 // 16-byte loads per thread); with scalar I/O they are loaded in the scalar
 // I/O layout and regrouped.
-constexpr Program make_tile_sort(int L, int r, bool vector_io) {
+//
+// lane_top > r (needs a full wave of lanes, L - r >= 6, and L <= 2r + 6):
+// steps on index bits that the blocked layout maps to lane bits (bits r ..
+// r+5) run there as lane steps where that is cheap.  Phases r+1 .. lane_top
+// stay in the blocked layout with no regroup: the mirror step pairs lane l
+// with lane l XOR (2^(p-r) - 1) and slot j with slot j XOR (2^r - 1), a
+// half-cleaner on bit b pairs lane l with lane l XOR 2^(b-r), and the steps
+// on bits below r are register steps.  Phases lane_top+1 .. r+6 regroup
+// through LDS as without lane steps.  Longer phases take their top r bits
+// (with the mirror step) into the registers of one virtual layout and come
+// back to the blocked layout for the rest, its lane bits as lane steps: two
+// regroups, both crossing waves, instead of three.  Each lane step costs
+// twice the VALU of a register step (a cross-lane move and a v_med3 per
+// key), so the choice of lane_top trades VALU for LDS round trips (measured
+// on MI355X: lane_top = 9 for 2^14-key tiles).
+constexpr void add_lane_merge(int r, Group& blocked, int p, bool in_blocked_mirror) {
+  if (in_blocked_mirror) {
+    blocked.d[blocked.nsteps++] = lane_step((1u << (p - r)) - 1u, (1u << r) - 1u);
+  }
+  const int top = in_blocked_mirror ? p - 2 : p - r - 1;
+  for (int b = top; b >= r; --b) blocked.d[blocked.nsteps++] = lane_step(1u << (b - r), 0u);
+  for (int b = r - 1; b >= 0; --b) blocked.d[blocked.nsteps++] = 1u << b;
+}
+
+constexpr Program make_tile_sort(int L, int r, bool vector_io, int lane_top = 0) {
   Program P{};
   P.L = L;
   P.r = r;
@@ -211,8 +250,27 @@ constexpr Program make_tile_sort(int L, int r, bool vector_io) {
     g0.d[g0.nsteps++] = (1u << p) - 1u;          // mirror step of phase p
     for (int b = p - 2; b >= 0; --b) g0.d[g0.nsteps++] = 1u << b;
   }
-  P.g[P.ngroups++] = g0;
-  for (int p = r + 1; p <= L; ++p) add_merge_bits(P, p - 1, true);
+  if (lane_top > r && L - r >= 6 && L <= 2 * r + 6) {
+    const int flat = lane_top < L ? (lane_top < r + 6 ? lane_top : r + 6) : L;
+    for (int p = r + 1; p <= flat; ++p) add_lane_merge(r, g0, p, true);
+    P.g[P.ngroups++] = g0;
+    const int mid = L < r + 6 ? L : r + 6;
+    for (int p = flat + 1; p <= mid; ++p) add_merge_bits(P, p - 1, true);
+    for (int p = r + 7; p <= L; ++p) {
+      Group G{};
+      G.r = r;
+      for (int m = 0; m < r; ++m) G.v[m] = 1u << (p - 1 - m);
+      G.vmirror = p;
+      for (int m = 0; m < r; ++m) G.d[G.nsteps++] = 1u << m;  // bits p-1 .. p-r
+      P.g[P.ngroups++] = G;
+      Group B = blocked_group(r);
+      add_lane_merge(r, B, p, false);
+      P.g[P.ngroups++] = B;
+    }
+  } else {
+    P.g[P.ngroups++] = g0;
+    for (int p = r + 1; p <= L; ++p) add_merge_bits(P, p - 1, true);
+  }
   if (L > r) P.g[P.ngroups++] = vector_io ? io_group(L, r) : io_scalar_group(L, r);
   return P;
 }
@@ -256,9 +314,13 @@ constexpr Program make_tile_merge(int L, int r, bool vector_io) {
 }
 
 // Program kinds: 0 sort, 1 merge (16-byte vector I/O); 2 sort, 3 merge
-// (scalar I/O).
+// (scalar I/O); 4 sort with 16-byte vector I/O and lane steps (lane_top
+// kLaneTop; see make_tile_sort).
+constexpr int kLaneTop = 9;
+constexpr bool kind_is_vector(int kind) { return kind == 0 || kind == 1 || kind == 4; }
 constexpr Program make_program(int L, int r, int kind) {
-  return (kind & 1) ? make_tile_merge(L, r, kind < 2) : make_tile_sort(L, r, kind < 2);
+  return (kind & 1) ? make_tile_merge(L, r, kind_is_vector(kind))
+                    : make_tile_sort(L, r, kind_is_vector(kind), kind == 4 ? kLaneTop : 0);
 }
 
 constexpr bool layout_is_vector4(const Group& G) {

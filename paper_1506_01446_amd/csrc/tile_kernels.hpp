@@ -9,6 +9,10 @@
 //                                 optimization, section 4.1, with the
 //                                 register blocking of section 4.2 inside
 //                                 the tile)
+//  tile_kernel<L, r, 4, CX>       the same with every step on an index bit
+//                                 that a wave holds across its lanes done by
+//                                 cross-lane compare-exchanges (DPP, permlane
+//                                 swaps) instead of LDS regroups
 //  tile_kernel<L, r, 1, CX>       the last L steps (strides 2^(L-1)..1) of a
 //                                 phase longer than the tile, on every tile
 //  tile_loop_kernel<L, r, 1, CX>  the same merge, each workgroup looping over
@@ -105,6 +109,13 @@ inline void launch_tile_L(int kind, int32_t* keys, uint32_t n, Codec cd, int cx,
       tile_kernel<L, kTileRegLog, 0, CX_ENC><<<ntiles, NT, 0, st>>>(keys, n, cd);
     else
       tile_kernel<L, kTileRegLog, 0, CX_BOTH><<<ntiles, NT, 0, st>>>(keys, n, cd);
+  } else if (kind == 4) {  // the sort with lane steps (program kind 4)
+    if (cx == CX_NONE)
+      tile_kernel<L, kTileRegLog, 4, CX_NONE><<<ntiles, NT, 0, st>>>(keys, n, cd);
+    else if (cx == CX_ENC)
+      tile_kernel<L, kTileRegLog, 4, CX_ENC><<<ntiles, NT, 0, st>>>(keys, n, cd);
+    else
+      tile_kernel<L, kTileRegLog, 4, CX_BOTH><<<ntiles, NT, 0, st>>>(keys, n, cd);
   } else if (cx == CX_NONE) {
     launch_merge_LC<L, CX_NONE>(keys, n, cd, max_blocks, st);
   } else {

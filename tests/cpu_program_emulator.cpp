@@ -47,14 +47,17 @@ static Program make(int L, int r, int kind) {
 static bool layouts_valid(const Program& P, int L) {
   for (int g = 0; g < P.ngroups; ++g) {
     const Group& G = P.g[g];
+    if (G.nsteps > kMaxSteps) return false;
     uint32_t seen = 0;
     for (int m = 0; m < G.r; ++m) {
       const uint32_t v = G.v[m];
       if (v == 0 || (v & (v - 1)) || v >= (1u << L) || (seen & v)) return false;
       seen |= v;
     }
-    for (int s = 0; s < G.nsteps; ++s)
-      if (G.d[s] == 0 || G.d[s] >= (1u << G.r)) return false;
+    for (int s = 0; s < G.nsteps; ++s) {
+      const uint32_t D = G.d[s];
+      if (D == 0 || step_reg(D) >= (1u << G.r) || step_lane(D) >= 64u) return false;
+    }
   }
   return true;
 }
@@ -112,16 +115,40 @@ int emulate_tile(int L, int r, int kind, int32_t* tile, uint32_t valid) {
     }
     for (int s = 0; s < G.nsteps; ++s) {
       const uint32_t D = G.d[s];
-      for (uint32_t t = 0; t < NT; ++t)
-        for (uint32_t j = 0; j < R; ++j) {
-          const uint32_t jj = j ^ D;
-          if (j >= jj) continue;
-          int32_t& lo = slot_is_lower(G, j, D) ? x[t * R + j] : x[t * R + jj];
-          int32_t& hi = slot_is_lower(G, j, D) ? x[t * R + jj] : x[t * R + j];
-          const int32_t a = std::min(lo, hi), b = std::max(lo, hi);
-          lo = a;
-          hi = b;
+      if (step_lane(D) == 0) {
+        for (uint32_t t = 0; t < NT; ++t)
+          for (uint32_t j = 0; j < R; ++j) {
+            const uint32_t jj = j ^ D;
+            if (j >= jj) continue;
+            int32_t& lo = slot_is_lower(G, j, D) ? x[t * R + j] : x[t * R + jj];
+            int32_t& hi = slot_is_lower(G, j, D) ? x[t * R + jj] : x[t * R + j];
+            const int32_t a = std::min(lo, hi), b = std::max(lo, hi);
+            lo = a;
+            hi = b;
+          }
+      } else {
+        // lane step: slot j of thread t meets slot j ^ DR of thread t ^ M (the
+        // same 64-lane wave); the thread with lane bit highbit(M) set keeps
+        // the maximum.  Both ends must be the same pair of real indices seen
+        // from either side, one step of the network apart (i ^ partner has
+        // its highest bit where the lane bit says).
+        const uint32_t M = step_lane(D), DR = step_reg(D);
+        const int hb = highbit(M);
+        std::vector<int32_t> y(x);
+        for (uint32_t t = 0; t < NT; ++t) {
+          const uint32_t tp = t ^ M;
+          if (tp >= NT || tp / 64 != t / 64) return -1;
+          for (uint32_t j = 0; j < R; ++j) {
+            const uint32_t jj = j ^ DR;
+            const uint32_t i = real_index(G, L, t, j), ip = real_index(G, L, tp, jj);
+            const bool upper = ((t >> hb) & 1u) != 0;
+            if ((i > ip) != upper) return -1;
+            const int32_t a = x[t * R + j], b = x[tp * R + jj];
+            y[t * R + j] = upper ? std::max(a, b) : std::min(a, b);
+          }
         }
+        x.swap(y);
+      }
       ++steps;
     }
   }

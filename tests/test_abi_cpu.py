@@ -314,3 +314,36 @@ def test_noalloc_argument_errors(lib):
 def test_segmented_default_bound_arguments(lib):
     assert lib.bitonic_segmented_default_bound(None, 4) == -1
     assert lib.bitonic_segmented_default_bound(64, 2) == -1
+
+
+def test_bucket_tuning(lib, tmp_path):
+    """Per-size-bucket plan entries ("name@k"): they set the plan of that
+    size only, take precedence over the global values, and load from a
+    tuning file with comments."""
+    k = 22
+    try:
+        B.bitonic_set_tuning_value(f"tile_log2@{k}", 13)
+        B.bitonic_set_tuning_value(f"fuse@{k}", 5)
+        assert B.bitonic_get_tuning_value(f"tile_log2@{k}") == 13
+        assert B.bitonic_plan_tile_log2(2**k) == 13
+        assert B.bitonic_plan_tile_log2(2**k - 5) == 13
+        assert B.bitonic_plan_tile_log2(2**(k + 1)) == 14          # other buckets untouched
+        assert B.bitonic_plan_passes(2**k) == _closed_form_optimized(k, 13, 5)
+        assert B.bitonic_plan_passes(2**k, ("optimized", 14, 8)) == _closed_form_optimized(k, 14, 8)
+        for bad in ("tile_log2@32", "fuse@-1", "nonsense@3", "tile_log2@x"):
+            with pytest.raises(B.BitonicError):
+                B.bitonic_set_tuning_value(bad, 13)
+        with pytest.raises(B.BitonicError):
+            B.bitonic_set_tuning_value(f"fuse@{k}", 9)
+        p = tmp_path / "t.txt"
+        p.write_text(f"# tuned table\nmerge_blocks_per_cu@{k} 4   # four per CU\n\nfuse@{k} 6\n")
+        B.bitonic_load_tuning(str(p))
+        assert B.bitonic_get_tuning_value(f"merge_blocks_per_cu@{k}") == 4
+        assert B.bitonic_get_tuning_value(f"fuse@{k}") == 6
+        p.write_text("fuse@3 6 7\n")
+        with pytest.raises(B.BitonicError):
+            B.bitonic_load_tuning(str(p))
+    finally:
+        for name in ("tile_log2", "fuse", "merge_blocks_per_cu"):
+            B.bitonic_set_tuning_value(f"{name}@{k}", 0)
+    assert B.bitonic_plan_tile_log2(2**k) == 14

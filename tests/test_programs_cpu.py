@@ -59,6 +59,30 @@ def test_tile_sort_program(emu, L):
         assert (out == np.sort(keys)).all()
 
 
+@pytest.mark.parametrize("L", [11, 12, 13, 14, 15])
+def test_tile_sort_lane_step_program(emu, L):
+    """The sort program whose steps on the blocked layout's lane bits run as
+    lane steps (cross-lane compare-exchanges, kind 4): every lane step pairs
+    the right indices, the tile comes out sorted, full and partial; phases up
+    to 9 need no regroup, 10 and 11 regroup through LDS as before, longer
+    ones take two regroups."""
+    T = 1 << L
+    for valid in (T, T - 1, T // 2 + 7, 3):
+        keys = W.uniform_i32(L * 7 + valid, T)
+        out, steps = _run(emu, L, 5, 4, keys, valid)
+        assert steps == L * (L + 1) // 2
+        assert (out[:valid] == np.sort(keys[:valid])).all()
+        assert (out[valid:] == keys[valid:]).all()
+    for kind in ("reverse", "distinct16"):
+        keys = W.make_keys(kind, 5, T)
+        out, _ = _run(emu, L, 5, 4, keys, T)
+        assert (out == np.sort(keys)).all()
+    # the blocked layout through phase 9, two layouts for phase 10 and three
+    # for phase 11 (as kind 0), two per longer phase, the 16-byte store layout
+    assert emu.program_groups(L, 5, 4) == 1 + 2 + (3 if L >= 11 else 0) + \
+        2 * max(0, L - 11) + 1
+
+
 @pytest.mark.parametrize("L", [11, 13])
 def test_tile_sort_partial(emu, L):
     T = 1 << L
@@ -143,7 +167,7 @@ def test_wide_programs(emu, L):
 # Every tile program a kernel instantiates: (L, r, kind) -- the single-array
 # 4-byte tiles (vector I/O, and the 2^13 scalar-I/O tile), the 8-byte tiles,
 # the segmented small-segment programs and big-segment tiles.
-INSTANTIATED = sorted({(L, 5, k) for L in range(11, 16) for k in (0, 1)} |
+INSTANTIATED = sorted({(L, 5, k) for L in range(11, 16) for k in (0, 1, 4)} |
                       {(13, 5, 2), (13, 5, 3)} |
                       {(L, 4, k) for L in (11, 12, 13) for k in (2, 3)} |
                       {(L, 5, 2) for L in range(5, 14)} | {(13, 4, 2), (13, 4, 3)})
