@@ -74,7 +74,7 @@ struct Prog {
   // one kernel.  (The single-array tile kernels keep the bases: 59 VGPRs
   // for the 2^14-key sort, 114 for the 2^15-key merge loop, both within the
   // 128 their workgroup sizes allow.)
-  static constexpr bool LEAN = KIND_ == 2 || KIND_ == 3;
+  static constexpr bool LEAN = kind_is_lean(KIND_);
   static constexpr Program value = make_program(L_, R_LOG_, KIND_);
   static_assert(value.ngroups <= kMaxGroups, "program too long");
 };

@@ -93,13 +93,13 @@ void launch_tile_scalar(int kind, int32_t* keys, uint32_t n, Codec cd, int cx, h
   const uint32_t ntiles = (uint32_t)(((uint64_t)n + (1u << L) - 1) >> L);
   constexpr int NT = 1 << (L - kTileRegLog);
   if (codec_is_identity(cd)) cx = CX_NONE;
-  if (kind == 0) {
+  if (kind == 0) {  // the scalar-I/O sort with lane steps (program kind 6)
     if (cx == CX_NONE)
-      tile_kernel<L, kTileRegLog, 2, CX_NONE><<<ntiles, NT, 0, st>>>(keys, n, cd);
+      tile_kernel<L, kTileRegLog, 6, CX_NONE><<<ntiles, NT, 0, st>>>(keys, n, cd);
     else if (cx == CX_ENC)
-      tile_kernel<L, kTileRegLog, 2, CX_ENC><<<ntiles, NT, 0, st>>>(keys, n, cd);
+      tile_kernel<L, kTileRegLog, 6, CX_ENC><<<ntiles, NT, 0, st>>>(keys, n, cd);
     else
-      tile_kernel<L, kTileRegLog, 2, CX_BOTH><<<ntiles, NT, 0, st>>>(keys, n, cd);
+      tile_kernel<L, kTileRegLog, 6, CX_BOTH><<<ntiles, NT, 0, st>>>(keys, n, cd);
   } else if (cx == CX_NONE) {
     tile_kernel<L, kTileRegLog, 3, CX_NONE><<<ntiles, NT, 0, st>>>(keys, n, cd);
   } else {

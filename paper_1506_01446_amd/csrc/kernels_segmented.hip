@@ -106,21 +106,22 @@ __global__ __launch_bounds__(1024) void seg_prep_kernel(const int64_t* __restric
   part_k[tid] = sk;
   part_t[tid] = st;
   __syncthreads();
-  if (tid == 0) {
-    uint64_t ak = 0, at = 0;
-    for (int i = 0; i < 1024; ++i) {
-      const uint64_t k = part_k[i], t = part_t[i];
-      part_k[i] = ak;
-      part_t[i] = at;
-      ak += k;
-      at += t;
-    }
-    big_keys[nbig] = ak;
-    big_tiles[nbig] = at;
+  // inclusive scan of the 1024 chunk sums (ten rounds of adding the sum d
+  // places back, d = 1, 2, 4, ...), then each chunk's exclusive start
+  for (uint32_t d = 1; d < 1024; d <<= 1) {
+    const uint64_t ak = tid >= d ? part_k[tid - d] : 0;
+    const uint64_t at = tid >= d ? part_t[tid - d] : 0;
+    __syncthreads();
+    part_k[tid] += ak;
+    part_t[tid] += at;
+    __syncthreads();
   }
-  __syncthreads();
-  sk = part_k[tid];
-  st = part_t[tid];
+  if (tid == 1023) {
+    big_keys[nbig] = part_k[tid];
+    big_tiles[nbig] = part_t[tid];
+  }
+  sk = part_k[tid] - sk;
+  st = part_t[tid] - st;
   for (uint32_t i = b0; i < b1; ++i) {
     const uint32_t s = big_ids[i];
     const uint64_t len = (uint64_t)(offsets[s + 1] - offsets[s]);

@@ -314,13 +314,16 @@ constexpr Program make_tile_merge(int L, int r, bool vector_io) {
 }
 
 // Program kinds: 0 sort, 1 merge (16-byte vector I/O); 2 sort, 3 merge
-// (scalar I/O); 4 sort with 16-byte vector I/O and lane steps (lane_top
-// kLaneTop; see make_tile_sort).
+// (scalar I/O); 4 and 6: the sorts 0 and 2 with lane steps (lane_top
+// kLaneTop; see make_tile_sort), for 4-byte keys only (a lane step moves one
+// 4-byte word per key).
 constexpr int kLaneTop = 9;
 constexpr bool kind_is_vector(int kind) { return kind == 0 || kind == 1 || kind == 4; }
+constexpr bool kind_is_lean(int kind) { return kind == 2 || kind == 3 || kind == 6; }
 constexpr Program make_program(int L, int r, int kind) {
   return (kind & 1) ? make_tile_merge(L, r, kind_is_vector(kind))
-                    : make_tile_sort(L, r, kind_is_vector(kind), kind == 4 ? kLaneTop : 0);
+                    : make_tile_sort(L, r, kind_is_vector(kind),
+                                     kind == 4 || kind == 6 ? kLaneTop : 0);
 }
 
 constexpr bool layout_is_vector4(const Group& G) {

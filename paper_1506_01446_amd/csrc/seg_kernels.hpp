@@ -78,6 +78,13 @@ __device__ __forceinline__ void seg_tile_program(ST tile, uint32_t valid, CD cd,
   }
 }
 
+// The scalar-I/O tile-sort program of a storage: with lane steps (kind 6)
+// for 4-byte keys, without (kind 2) for 8-byte elements.
+template <class ST>
+constexpr int seg_sort_kind() {
+  return sizeof(typename ST::E) == 4 ? 6 : 2;
+}
+
 // ---------------------------------------------------------------------------
 // small segments
 
@@ -90,7 +97,7 @@ __device__ __attribute__((noinline)) void seg_small_item(ST keys,
                                                const int64_t* __restrict__ offsets,
                                                const uint32_t* __restrict__ ids, uint32_t first,
                                                uint32_t count, CD cd, typename ST::E* lds) {
-  using PR = Prog<L, kTileRegLogSeg, 2>;
+  using PR = Prog<L, kTileRegLogSeg, seg_sort_kind<ST>()>;
   constexpr uint32_t NT = PR::NT;
   static_assert((kSegThreads / NT) * PR::LDSW <= kSmallLdsWords, "padded tiles exceed LDS");
   const uint32_t grp = threadIdx.x / NT;
@@ -304,7 +311,7 @@ void seg_run(ST keys, CD cd, const SegLaunch& l, const int64_t* offsets, const S
       seg_small_kernel<<<l.grid, kSegThreads, 0, st>>>(keys, offsets, sc.meta, sc.small_ids, cd);
       break;
     case SegLaunch::kTileSort:
-      seg_tile_kernel<2><<<l.grid, seg_tile_threads<ST>(), 0, st>>>(
+      seg_tile_kernel<seg_sort_kind<ST>()><<<l.grid, seg_tile_threads<ST>(), 0, st>>>(
           keys, offsets, sc.meta, sc.big_ids, sc.big_tiles, l.cls, cd);
       break;
     case SegLaunch::kTileMerge:

@@ -122,8 +122,8 @@ int main() {
   }
 
   // the CPU emulator on every program the kernels instantiate
-  for (int kind : {0, 1, 2, 3, 4})
-    for (int L = (kind == 2 ? 5 : 11); L <= (kind >= 2 && kind <= 3 ? 13 : 15); ++L) {
+  for (int kind : {0, 1, 2, 3, 4, 6})
+    for (int L = (kind == 2 || kind == 6 ? 5 : 11); L <= (kind == 2 || kind == 3 || kind == 6 ? 13 : 15); ++L) {
       std::vector<int32_t> tile(size_t(1) << L);
       for (size_t i = 0; i < tile.size(); ++i) tile[i] = (int32_t)((i * 2654435761u) >> 7);
       CHECK(emulate_tile(L, 5, kind, tile.data(), (uint32_t)tile.size() - 3) >= 0);

@@ -59,6 +59,26 @@ def test_tile_sort_program(emu, L):
         assert (out == np.sort(keys)).all()
 
 
+@pytest.mark.parametrize("L", list(range(5, 14)))
+def test_scalar_io_lane_step_program(emu, L):
+    """The scalar-I/O sort of 4-byte keys with lane steps (kind 6: segments
+    and arrays off a 16-byte boundary): sorted, full and partial tiles; below
+    a full wave of lanes (L < 11) it is the plain program."""
+    T = 1 << L
+    for valid in sorted({T, T - 1, T // 2 + 3, 1}):
+        keys = W.uniform_i32(L * 13 + valid, T)
+        out, steps = _run(emu, L, 5, 6, keys, valid)
+        assert steps == L * (L + 1) // 2
+        assert (out[:valid] == np.sort(keys[:valid])).all()
+        assert (out[valid:] == keys[valid:]).all()
+    if L < 11:
+        assert emu.program_groups(L, 5, 6) == emu.program_groups(L, 5, 2)
+    else:
+        assert emu.program_groups(L, 5, 6) < emu.program_groups(L, 5, 2)
+    if L > 5:
+        assert emu.worst_bank_conflict(L, 5, 6, 32) == 1
+
+
 @pytest.mark.parametrize("L", [11, 12, 13, 14, 15])
 def test_tile_sort_lane_step_program(emu, L):
     """The sort program whose steps on the blocked layout's lane bits run as
@@ -168,9 +188,10 @@ def test_wide_programs(emu, L):
 # 4-byte tiles (vector I/O, and the 2^13 scalar-I/O tile), the 8-byte tiles,
 # the segmented small-segment programs and big-segment tiles.
 INSTANTIATED = sorted({(L, 5, k) for L in range(11, 16) for k in (0, 1, 4)} |
-                      {(13, 5, 2), (13, 5, 3)} |
+                      {(13, 5, 6), (13, 5, 3)} |
                       {(L, 4, k) for L in (11, 12, 13) for k in (2, 3)} |
-                      {(L, 5, 2) for L in range(5, 14)} | {(13, 4, 2), (13, 4, 3)})
+                      {(L, 5, k) for L in range(5, 14) for k in (2, 6)} |
+                      {(13, 4, 2), (13, 4, 3)})
 
 
 @pytest.mark.parametrize("L,r,kind", INSTANTIATED)
