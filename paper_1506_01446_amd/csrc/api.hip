@@ -334,6 +334,12 @@ static int bind_device(Resolved* r) {
   return BITONIC_OK;
 }
 
+// The big segments' tile (log2 elements) of a sort's data: 4-byte keys take
+// kSegTileLog32, 8-byte elements (8-byte keys, pairs) kSegTileLog64.
+static int seg_tile_log_of(const SegData& d) {
+  return (d.keys64 || d.values) ? kSegTileLog64 : kSegTileLog32;
+}
+
 // The launch sequence of one segmented sort (see kernels_segmented.hip) on
 // the given scratch buffer (seg_scratch_bytes(nseg) bytes); returns the
 // number of launches (enqueued unless count_only; shapes to obs, with `unit`
@@ -343,6 +349,7 @@ static int64_t enqueue_segmented(const SegData& d, const int64_t* offsets, int64
                                  int64_t max_seg_len, void* scratch, int cus, hipStream_t st,
                                  bool count_only = false, Observer* obs = nullptr,
                                  int unit = 4) {
+  const int T = seg_tile_log_of(d);
   int64_t launches = 0;
   auto emit = [&](bitonic_launch_shape sh, auto&& launch) {
     if (!count_only) launch();
@@ -351,18 +358,19 @@ static int64_t enqueue_segmented(const SegData& d, const int64_t* offsets, int64
   };
   const SegScratch sc = count_only ? SegScratch{} : seg_scratch_carve(scratch, nseg);
   emit({BITONIC_LAUNCH_SEG_PREP, 0, 0, 0, unit, 64},
-       [&] { launch_seg_prep(offsets, nseg, sc, st); });
+       [&] { launch_seg_prep(offsets, nseg, sc, T, st); });
   const int64_t slots = (int64_t)cus * g_seg_bpc.load();
   const int small_grid = (int)(slots < nseg ? slots : nseg);
   emit({BITONIC_LAUNCH_SEG_SMALL, 0, kSegSmallMaxLog2, 0, unit, 64},
        [&] { launch_seg_small(d, offsets, sc, small_grid, st); });
   const int M = ceil_log2(max_seg_len);
   if (M <= kSegSmallMaxLog2) return launches;
-  const int T = kSegSmallMaxLog2;  // big segments run 2^13-element tiles
-  const int grid = cus * 4;
+  // two workgroups per CU of the 2^14-key tiles (67.6 KB of LDS each), four
+  // of the 2^13-element ones
+  const int grid = cus * (T == kSegTileLog32 ? 2 : 4);
   const int pass_grid = cus * g_seg_pass_bpc.load();
   emit({BITONIC_LAUNCH_TILE_SORT, 0, T, 0, unit, 64},
-       [&] { launch_seg_tiles(false, d, offsets, sc, T + 1, grid, st); });
+       [&] { launch_seg_tiles(false, d, offsets, sc, kSegSmallMaxLog2 + 1, grid, st); });
   const int fuse = g_seg_fuse.load();
   for (int p = T + 1; p <= M; ++p) {
     const int nb = p - T;
@@ -676,7 +684,11 @@ int64_t bitonic_plan_shapes(int64_t n, int layout, const bitonic_plan* plan,
     case BITONIC_LAYOUT_SEG_PAIRS:
     case BITONIC_LAYOUT_SEG_KEYS64: {
       if (n == 0) return 0;
-      SegData d{};
+      SegData d{};  // only which storage it is matters when counting
+      int32_t dummy32 = 0;
+      int64_t dummy64 = 0;
+      if (layout == BITONIC_LAYOUT_SEG_PAIRS) d.values = &dummy32;
+      if (layout == BITONIC_LAYOUT_SEG_KEYS64) d.keys64 = &dummy64;
       return enqueue_segmented(d, nullptr, 1, n, nullptr, 256, nullptr, true, &obs,
                                layout == BITONIC_LAYOUT_SEG_KEYS64 ? 8 : 4);
     }

@@ -12,10 +12,12 @@
 //                        group of threads with the register tile programs
 //                        (scalar I/O, group-private LDS region); items are
 //                        taken from an atomic counter, largest class first
-//   seg_tile_kernel      tile sort of every 2^13-key tile of the big segments
-//                        (class > 13), grid-stride over a device-side tile list
-//   seg_pass_kernel and  per phase p > 13: the fused long-stride steps and the
-//   seg_tile_kernel      tile merges of the big segments of class >= p
+//   seg_tile_kernel      tile sort of every tile of the big segments (class
+//                        > 13; 2^14-key tiles for 4-byte keys, 2^13-element
+//                        for 8-byte elements), over a device-side tile list
+//   seg_pass_kernel and  per phase p above the tile: the fused long-stride
+//   seg_tile_kernel      steps and the tile merges of the big segments of
+//                        class >= p
 // The host only needs an upper bound on the largest class to know how many
 // phases to enqueue.
 #include "seg_kernels.hpp"
@@ -30,7 +32,8 @@ __global__ __launch_bounds__(1024) void seg_prep_kernel(const int64_t* __restric
                                                         uint32_t* __restrict__ small_ids,
                                                         uint32_t* __restrict__ big_ids,
                                                         uint64_t* __restrict__ big_keys,
-                                                        uint64_t* __restrict__ big_tiles) {
+                                                        uint64_t* __restrict__ big_tiles,
+                                                        int tile_log) {
   __shared__ uint32_t cnt[32];
   __shared__ uint32_t cur[32];
   __shared__ uint64_t part_k[1024];
@@ -66,13 +69,13 @@ __global__ __launch_bounds__(1024) void seg_prep_kernel(const int64_t* __restric
     // big buckets, largest class first
     uint32_t bpos = 0;
     int maxc = 0;
-    for (int c = 31; c > kSegTileLog; --c) {
+    for (int c = 31; c > kSegSmallMaxLog2; --c) {
       cur[c] = bpos;
       bpos += cnt[c];
       meta->big_ge[c] = bpos;  // segments of class >= c
       if (cnt[c] && !maxc) maxc = c;
     }
-    for (int c = 0; c <= kSegTileLog; ++c) meta->big_ge[c] = bpos;
+    for (int c = 0; c <= kSegSmallMaxLog2; ++c) meta->big_ge[c] = bpos;
     meta->big_ge[32] = 0;
     meta->nbig = bpos;
     meta->max_class = maxc;
@@ -85,7 +88,7 @@ __global__ __launch_bounds__(1024) void seg_prep_kernel(const int64_t* __restric
     int c = ceil_log2_u64(len);
     if (c < 5) c = 5;
     const uint32_t slot = atomicAdd(&cur[c], 1u);
-    if (c <= kSegTileLog)
+    if (c <= kSegSmallMaxLog2)
       small_ids[slot] = (uint32_t)s;
     else
       big_ids[slot] = (uint32_t)s;
@@ -101,7 +104,7 @@ __global__ __launch_bounds__(1024) void seg_prep_kernel(const int64_t* __restric
     const uint32_t s = big_ids[i];
     const uint64_t len = (uint64_t)(offsets[s + 1] - offsets[s]);
     sk += 1ull << ceil_log2_u64(len);
-    st += (len + (1u << kSegTileLog) - 1) >> kSegTileLog;
+    st += (len + (1ull << tile_log) - 1) >> tile_log;
   }
   part_k[tid] = sk;
   part_t[tid] = st;
@@ -128,7 +131,7 @@ __global__ __launch_bounds__(1024) void seg_prep_kernel(const int64_t* __restric
     big_keys[i] = sk;
     big_tiles[i] = st;
     sk += 1ull << ceil_log2_u64(len);
-    st += (len + (1u << kSegTileLog) - 1) >> kSegTileLog;
+    st += (len + (1ull << tile_log) - 1) >> tile_log;
   }
 }
 
@@ -145,9 +148,10 @@ static void seg_dispatch(const SegData& d, const SegLaunch& l, const int64_t* of
     seg_run_keys32(d, l, offsets, sc, st);
 }
 
-void launch_seg_prep(const int64_t* offsets, int64_t nseg, const SegScratch& sc, hipStream_t st) {
+void launch_seg_prep(const int64_t* offsets, int64_t nseg, const SegScratch& sc, int tile_log,
+                     hipStream_t st) {
   seg_prep_kernel<<<1, 1024, 0, st>>>(offsets, nseg, sc.meta, sc.small_ids, sc.big_ids,
-                                      sc.big_keys, sc.big_tiles);
+                                      sc.big_keys, sc.big_tiles, tile_log);
 }
 
 void launch_seg_small(const SegData& d, const int64_t* offsets, const SegScratch& sc, int grid,

@@ -14,7 +14,6 @@
 
 namespace bitonic {
 
-constexpr int kSegTileLog = kSegSmallMaxLog2;  // big segments: 2^13-element tiles
 constexpr int kSegThreads = 256;
 
 __device__ __forceinline__ int ceil_log2_u64(uint64_t n) {
@@ -183,26 +182,30 @@ __device__ __forceinline__ uint32_t advance_index(const uint64_t* __restrict__ p
   return i;
 }
 
-// Register slots (log2) per thread of the big-segment tile programs: 32 for
-// 4-byte keys; 16 for 8-byte elements, whose 2^13-element tile fills twice
-// the LDS, so that a CU still runs 16 waves of them.
+// Tile (log2 elements) and register slots (log2) per thread of the
+// big-segment tile programs: 2^14 4-byte keys at 32 per thread; 2^13 8-byte
+// elements at 16 per thread, so that a CU still runs 16 waves of them.
+template <class ST>
+constexpr int seg_tile_log() {
+  return sizeof(typename ST::E) == 8 ? kSegTileLog64 : kSegTileLog32;
+}
 template <class ST>
 constexpr int seg_tile_reg_log() {
   return sizeof(typename ST::E) == 8 ? 4 : kTileRegLogSeg;
 }
 template <class ST>
 constexpr int seg_tile_threads() {
-  return 1 << (kSegTileLog - seg_tile_reg_log<ST>());
+  return 1 << (seg_tile_log<ST>() - seg_tile_reg_log<ST>());
 }
 
-// Every 2^13-key tile of the big segments of class >= cls_min: sort
-// (KIND 2) or merge (KIND 3).
+// Every tile of the big segments of class >= cls_min: sort (KIND 2 or 6) or
+// merge (KIND 3).
 template <int KIND, class ST, class CD>
 __global__ __launch_bounds__(seg_tile_threads<ST>()) void seg_tile_kernel(
     ST keys, const int64_t* __restrict__ offsets,
     const SegMeta* __restrict__ meta, const uint32_t* __restrict__ big_ids,
     const uint64_t* __restrict__ big_tiles, int cls_min, CD cd) {
-  using PR = Prog<kSegTileLog, seg_tile_reg_log<ST>(), KIND>;
+  using PR = Prog<seg_tile_log<ST>(), seg_tile_reg_log<ST>(), KIND>;
   static_assert(PR::NT == seg_tile_threads<ST>(), "one tile per workgroup");
   // 8-byte elements regroup through 4-byte words (half the LDS: four
   // workgroups per CU instead of two)
@@ -213,20 +216,72 @@ __global__ __launch_bounds__(seg_tile_threads<ST>()) void seg_tile_kernel(
   uint64_t u, uend;
   unit_range(big_tiles[cnt], &u, &uend);
   uint32_t i = u < uend ? upper_index(big_tiles, cnt, u) : 0u;
-  for (; u < uend; ++u) {
-    // recompute the layouts' thread bases per tile instead of holding them
-    uint32_t tid = threadIdx.x;
-    asm volatile("" : "+v"(tid));
-    i = advance_index(big_tiles, cnt, i, u);
-    const uint64_t tile = u - big_tiles[i];
+  // tile uu's first element (segment-relative start off + t0) and its real
+  // element count; i walks forward through the big-segment list
+  auto locate = [&](uint64_t uu, uint64_t* start, uint32_t* valid) {
+    i = advance_index(big_tiles, cnt, i, uu);
+    const uint64_t tile = uu - big_tiles[i];
     const uint32_t s = big_ids[i];
     const int64_t off = offsets[s];
     const uint64_t len = (uint64_t)(offsets[s + 1] - off);
-    const uint64_t t0 = tile << kSegTileLog;
+    const uint64_t t0 = tile << seg_tile_log<ST>();
     const uint64_t left = len - t0;
-    const uint32_t valid = left < (uint64_t)PR::T ? (uint32_t)left : (uint32_t)PR::T;
-    seg_tile_program<PR, SPLIT>(keys.at(off + t0), valid, cd, lds, tid);
-    __syncthreads();  // LDS reuse by the next tile
+    *start = (uint64_t)off + t0;
+    *valid = left < (uint64_t)PR::T ? (uint32_t)left : (uint32_t)PR::T;
+  };
+  if constexpr (std::is_same_v<ST, Keys32>) {
+    // 4-byte keys: the next tile's keys are loaded (through a buffer
+    // resource of its real keys, so slots past them read 0 and touch no
+    // memory) while this tile is sorted and stored; each tile's keys are
+    // encoded, and its padding set, only when its program starts.
+    constexpr Group g0 = PR::value.g[0];
+    constexpr int LAST = PR::value.ngroups - 1;
+    auto load_raw = [&](int32_t (&x)[PR::R], uint64_t start, uint32_t valid, uint32_t tid) {
+      const __amdgpu_buffer_rsrc_t rs = tile_rsrc(keys.k + start, valid * 4u);
+      const uint32_t base = deposit<free_mask(g0, PR::L)>(tid);
+      static_for<0, PR::R>([&](auto J) {
+        const uint32_t idx = slot_index<PR, 0, J>(base);
+        x[J] = (int32_t)__builtin_amdgcn_raw_buffer_load_b32(rs, idx * 4u, 0, 0);
+      });
+    };
+    if (u >= uend) return;
+    uint64_t start = 0;
+    uint32_t valid = 0;
+    locate(u, &start, &valid);
+    int32_t x[PR::R];
+    load_raw(x, start, valid, threadIdx.x);
+    for (; u < uend; ++u) {
+      uint32_t tid = threadIdx.x;
+      asm volatile("" : "+v"(tid));
+      uint64_t nstart = start;
+      uint32_t nvalid = 0;  // no next tile: an empty resource
+      if (u + 1 < uend) locate(u + 1, &nstart, &nvalid);
+      int32_t y[PR::R];
+      load_raw(y, nstart, nvalid, tid);
+      {
+        const uint32_t base = deposit<free_mask(g0, PR::L)>(tid);
+        static_for<0, PR::R>([&](auto J) {
+          const uint32_t idx = slot_index<PR, 0, J>(base);
+          x[J] = idx < valid ? cd.enc(x[J]) : kPad;
+        });
+      }
+      run_from<PR, 0>(x, lds, tid);  // its first regroup waits for the LDS
+      store_tile<PR, LAST>(x, keys.k + start, valid, cd, tid);
+      static_for<0, PR::R>([&](auto J) { x[J] = y[J]; });
+      start = nstart;
+      valid = nvalid;
+    }
+  } else {
+    for (; u < uend; ++u) {
+      // recompute the layouts' thread bases per tile instead of holding them
+      uint32_t tid = threadIdx.x;
+      asm volatile("" : "+v"(tid));
+      uint64_t start = 0;
+      uint32_t valid = 0;
+      locate(u, &start, &valid);
+      seg_tile_program<PR, SPLIT>(keys.at(start), valid, cd, lds, tid);
+      __syncthreads();  // LDS reuse by the next tile
+    }
   }
 }
 
@@ -254,8 +309,8 @@ __device__ __forceinline__ uint32_t seg_pass_index(uint32_t blk, uint32_t c0, in
 // segments of class >= cls.  A workgroup unit is 256 C consecutive columns x
 // 2^F rows of one 2^(q+F)-element block of one segment (C = seg_pass_cols(F));
 // thread t holds columns c0 + t + 256 j (j < C), so every load and store of
-// a wave is 64 consecutive elements.  Since q >= 13, a block holds whole
-// units.
+// a wave is 64 consecutive elements.  Since q is at least the tile's log2
+// (13 or 14), a block holds whole units.
 template <int F, bool MIRROR, class ST, class CD>
 __global__ __launch_bounds__(kSegThreads) void seg_pass_kernel(
     ST keys, const int64_t* __restrict__ offsets,

@@ -10,6 +10,11 @@ namespace bitonic {
 
 constexpr int kTileRegLogSeg = 5;  // 32 keys per thread
 constexpr int kSegSmallMaxLog2 = 13;  // segments of up to 2^13 keys are "small"
+// Tiles of the big segments: 2^14 4-byte keys (the single-array sort's tile,
+// 67.6 KB of LDS, two workgroups per CU), 2^13 8-byte elements (regrouped
+// through half the LDS, 34 KB, four per CU).
+constexpr int kSegTileLog32 = 14;
+constexpr int kSegTileLog64 = 13;
 constexpr int kSmallClasses = 9;   // classes 13, 12, ..., 6 and "<= 5"
 constexpr int kSegFuseMax = 5;  // most steps per big-segment pass
 
@@ -31,7 +36,7 @@ struct SegScratch {
   uint32_t* small_ids;   // nseg entries, bucketed by class, class 13 first
   uint32_t* big_ids;     // nseg entries, largest class first
   uint64_t* big_keys;    // nseg + 1: exclusive prefix of padded sizes
-  uint64_t* big_tiles;   // nseg + 1: exclusive prefix of 2^13-key tiles
+  uint64_t* big_tiles;   // nseg + 1: exclusive prefix of big-segment tiles
 };
 
 constexpr size_t seg_scratch_bytes(int64_t nseg) {
@@ -97,7 +102,9 @@ void seg_run_pairs(const SegData& d, const SegLaunch& l, const int64_t* offsets,
 void seg_run_keys64(const SegData& d, const SegLaunch& l, const int64_t* offsets,
                     const SegScratch& sc, hipStream_t st);
 
-void launch_seg_prep(const int64_t* offsets, int64_t nseg, const SegScratch& sc, hipStream_t st);
+// tile_log: log2 of the big segments' tile (kSegTileLog32 or kSegTileLog64).
+void launch_seg_prep(const int64_t* offsets, int64_t nseg, const SegScratch& sc, int tile_log,
+                     hipStream_t st);
 void launch_seg_small(const SegData& d, const int64_t* offsets, const SegScratch& sc, int grid,
                       hipStream_t st);
 // Tile sort (merge == false) or tile merge of the big segments of class >= cls_min.

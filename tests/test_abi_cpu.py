@@ -282,6 +282,7 @@ def test_plan_shapes_segmented(lib, layout, unit):
     """The segmented planner, for a longest segment of 1..2^31 elements:
     prep, the small-segment kernel, and for segments past 2^13 elements the
     tile sort and per phase its passes (at most "seg_fuse" steps each) and merge."""
+    T = 14 if layout == "seg_keys32" else 13   # big-segment tile: 2^14 keys, 2^13 8-byte elements
     for k in range(0, 32):
         n = 2**k
         sh = B.bitonic_plan_shapes(n, layout)
@@ -290,13 +291,14 @@ def test_plan_shapes_segmented(lib, layout, unit):
         if k <= 13:
             assert len(sh) == 2
             continue
-        assert sh[2]["kind"] == "tile_sort" and sh[2]["q"] == 13
+        assert sh[2]["kind"] == "tile_sort" and sh[2]["q"] == T
         merges = [s for s in sh if s["kind"] == "tile_merge"]
         passes = [s for s in sh if s["kind"] == "global_pass"]
-        assert len(merges) == k - 13
+        assert len(merges) == max(0, k - T)
         assert all(s["fuse"] <= B.bitonic_get_tuning_value("seg_fuse") for s in passes)
-        # every phase p > 13 performs steps on bits p-1 .. 13 exactly once
-        assert sum(s["fuse"] for s in passes) == sum(p - 13 for p in range(14, k + 1))
+        assert all(s["q"] >= T for s in passes)
+        # every phase p > T performs steps on bits p-1 .. T exactly once
+        assert sum(s["fuse"] for s in passes) == sum(p - T for p in range(T + 1, k + 1))
 
 
 def test_noalloc_argument_errors(lib):
