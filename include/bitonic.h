@@ -148,7 +148,8 @@ int bitonic_sort_pairs(void* keys, int32_t* values, int64_t n, int key_type, int
  * longest segment actually present find no segment of their class on the
  * device and return at once, at the cost of their launches (a few
  * microseconds each); bitonic_sort_segmented_bounded_i32 with a tight bound
- * enqueues only the phases needed.  Bad offsets are undefined behaviour.
+ * enqueues only the phases needed.  Bad offsets are undefined behaviour
+ * unless offsets validation is on (bitonic_validation_error).
  * Calls on a stream that is being captured into a graph are refused
  * (BITONIC_EINVAL): the graph would share the stream's scratch buffer with
  * later eager calls; capture bitonic_graph_capture_segmented_i32 or
@@ -158,6 +159,22 @@ int bitonic_sort_pairs(void* keys, int32_t* values, int64_t n, int key_type, int
  */
 int bitonic_sort_segmented_i32(int32_t* keys, const int64_t* offsets,
                                int64_t nseg, int ascending, void* stream);
+
+/*
+ * Offsets validation (for debugging; off by default).  With the tuning value
+ * "validate" set to 1, or else the environment variable BITONIC_VALIDATE=1,
+ * every segmented sort first checks its offsets table on the device: offsets
+ * nondecreasing, offsets[0] >= 0, every segment below 2^31 keys and at most
+ * the bound (max_seg_len, or the default bound).  A table that fails is not
+ * sorted (the keys are left as they were) and its error is recorded on the
+ * device.  bitonic_validation_error waits for the device to be idle, then
+ * writes the first error recorded since its last call (0 none, 1 decreasing
+ * offsets, 2 a segment of 2^31 keys or more, 3 a segment longer than the
+ * bound, 4 offsets[0] < 0) to *code and clears it.  Without validation, bad
+ * offsets are undefined behaviour.  Returns BITONIC_OK, BITONIC_EINVAL (code
+ * NULL) or BITONIC_EDEVICE.
+ */
+int bitonic_validation_error(int32_t* code);
 
 /*
  * The bound on the segment length that the segmented sorts take when the
@@ -418,7 +435,8 @@ int bitonic_sort_plan_launches_i32(int32_t* keys, int64_t n, int ascending,
  * "merge_blocks_per_cu" (as in bitonic_plan), "seg_blocks_per_cu" (1..16, workgroups per compute unit of
  * the persistent small-segment kernel), "seg_pass_blocks_per_cu" (1..32,
  * workgroups per compute unit of the big-segment passes, default 8),
- * "seg_fuse" (1..5, steps per big-segment pass, default 5), "tile_lane_steps"
+ * "seg_fuse" (1..5, steps per big-segment pass, default 5), "validate" (0 or 1:
+ * offsets validation, see bitonic_validation_error), "tile_lane_steps"
  * (1, the default: the tile sort runs its phases up to 9 as cross-lane
  * compare-exchanges inside each wave; 0: every phase through LDS regroups),
  * "wide_tile_log2" (11..13) or

@@ -60,6 +60,7 @@ def load() -> ctypes.CDLL:
         "bitonic_sort_segmented_noalloc_i32": ([vp, vp, ctypes.c_int64, ctypes.c_int64,
                                                ctypes.c_int, vp], ctypes.c_int),
         "bitonic_segmented_default_bound": ([vp, ctypes.c_int], ctypes.c_int64),
+        "bitonic_validation_error": ([ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
         "bitonic_network_phases_i32": ([vp, ctypes.c_int64, ctypes.c_int, ctypes.c_int,
                                         ctypes.POINTER(bitonic_plan), vp], ctypes.c_int),
         "bitonic_plan_passes": ([ctypes.c_int64, ctypes.POINTER(bitonic_plan)],
@@ -368,6 +369,14 @@ def bitonic_segmented_default_bound(keys) -> int:
     """The segment-length bound the segmented sorts take for ``keys`` when
     no bound is given (end of the keys' device allocation, at most 2^31)."""
     return int(load().bitonic_segmented_default_bound(keys.data_ptr(), keys.element_size()))
+
+
+def bitonic_validation_error() -> int:
+    """The first segment-table error recorded by a validated segmented sort
+    since the last call (0: none); waits for the device, clears the record."""
+    c = ctypes.c_int32()
+    _check("bitonic_validation_error", load().bitonic_validation_error(ctypes.byref(c)))
+    return int(c.value)
 
 
 def bitonic_plan_tile_log2(n: int, plan=None) -> int:

@@ -39,6 +39,21 @@ static std::atomic<int> g_seg_bpc{4};    // small-segment workgroups per compute
 static std::atomic<int> g_seg_pass_bpc{8};  // big-segment pass workgroups per compute unit
 static std::atomic<int> g_seg_fuse{kSegFuseMax};  // steps per big-segment pass
 static std::atomic<int> g_tile_lane{1};  // tile sort with cross-lane steps (program kind 4)
+static std::atomic<int> g_validate{-1};  // check segment tables on the device; -1: not yet read
+
+// Offsets validation of the segmented sorts: the tuning value "validate", or
+// else the environment variable BITONIC_VALIDATE=1.
+static bool validate_enabled() {
+  int v = g_validate.load();
+  if (v < 0) {
+    const char* e = std::getenv("BITONIC_VALIDATE");
+    v = (e && e[0] == '1' && e[1] == 0) ? 1 : 0;
+    int expect = -1;
+    g_validate.compare_exchange_strong(expect, v);
+    v = g_validate.load();
+  }
+  return v == 1;
+}
 
 struct Resolved {
   int kind;
@@ -357,8 +372,12 @@ static int64_t enqueue_segmented(const SegData& d, const int64_t* offsets, int64
     ++launches;
   };
   const SegScratch sc = count_only ? SegScratch{} : seg_scratch_carve(scratch, nseg);
+  // with validation on, a check of the table comes first (one more launch,
+  // not counted among the sort's launches)
+  const bool validated = !count_only && validate_enabled();
+  if (validated) launch_seg_validate(offsets, nseg, max_seg_len, sc, st);
   emit({BITONIC_LAUNCH_SEG_PREP, 0, 0, 0, unit, 64},
-       [&] { launch_seg_prep(offsets, nseg, sc, T, st); });
+       [&] { launch_seg_prep(offsets, nseg, sc, T, validated, st); });
   const int64_t slots = (int64_t)cus * g_seg_bpc.load();
   const int small_grid = (int)(slots < nseg ? slots : nseg);
   emit({BITONIC_LAUNCH_SEG_SMALL, 0, kSegSmallMaxLog2, 0, unit, 64},
@@ -820,6 +839,11 @@ int bitonic_sort_segmented_pairs(void* keys, int32_t* values, const int64_t* off
   return sort_segmented(keys, values, offsets, nseg, max_seg_len, key_type, ascending, stream);
 }
 
+int bitonic_validation_error(int32_t* code) {
+  if (!code) return BITONIC_EINVAL;
+  return seg_validation_error(code) == 0 ? BITONIC_OK : BITONIC_EDEVICE;
+}
+
 int64_t bitonic_segmented_default_bound(const void* keys, int key_bytes) {
   if (keys == nullptr || (key_bytes != 4 && key_bytes != 8)) return -1;
   return allocation_bound(keys, key_bytes);
@@ -928,6 +952,11 @@ int bitonic_set_tuning_value(const char* key, int value) {
     g_seg_fuse.store(value);
     return BITONIC_OK;
   }
+  if (!std::strcmp(key, "validate")) {
+    if (value < 0 || value > 1) return BITONIC_EINVAL;
+    g_validate.store(value);
+    return BITONIC_OK;
+  }
   if (!std::strcmp(key, "tile_lane_steps")) {
     if (value < 0 || value > 1) return BITONIC_EINVAL;
     g_tile_lane.store(value);
@@ -968,6 +997,7 @@ int bitonic_get_tuning_value(const char* key, int* value) {
   else if (!std::strcmp(key, "seg_pass_blocks_per_cu")) *value = g_seg_pass_bpc.load();
   else if (!std::strcmp(key, "seg_fuse")) *value = g_seg_fuse.load();
   else if (!std::strcmp(key, "tile_lane_steps")) *value = g_tile_lane.load();
+  else if (!std::strcmp(key, "validate")) *value = validate_enabled() ? 1 : 0;
   else if (!std::strcmp(key, "wide_tile_log2")) *value = g_wide_tile_log2.load();
   else if (!std::strcmp(key, "wide_fuse")) *value = g_wide_fuse.load();
   else return BITONIC_EINVAL;

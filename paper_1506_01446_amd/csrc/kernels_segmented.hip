@@ -25,6 +25,50 @@
 namespace bitonic {
 
 // ---------------------------------------------------------------------------
+// validation (only when enabled: bitonic_set_tuning_value("validate", 1) or
+// BITONIC_VALIDATE=1)
+
+// First table error any validated call found on this device (0: none).
+__device__ int32_t g_seg_validation_error;
+
+__global__ __launch_bounds__(1024) void seg_validate_kernel(const int64_t* __restrict__ offsets,
+                                                            int64_t nseg, int64_t bound,
+                                                            SegMeta* __restrict__ meta) {
+  __shared__ int32_t err;
+  if (threadIdx.x == 0) err = offsets[0] < 0 ? kSegTableNegative : kSegTableOk;
+  __syncthreads();
+  for (int64_t s = threadIdx.x; s < nseg; s += 1024) {
+    const int64_t len = offsets[s + 1] - offsets[s];
+    int32_t e = kSegTableOk;
+    if (len < 0) e = kSegTableDecreasing;
+    else if (len >= (int64_t(1) << 31)) e = kSegTableTooLong;
+    else if (len > bound) e = kSegTableOverBound;
+    if (e != kSegTableOk) atomicCAS(&err, kSegTableOk, e);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    meta->invalid = err;
+    if (err != kSegTableOk) atomicCAS(&g_seg_validation_error, kSegTableOk, err);
+  }
+}
+
+void launch_seg_validate(const int64_t* offsets, int64_t nseg, int64_t bound, const SegScratch& sc,
+                         hipStream_t st) {
+  seg_validate_kernel<<<1, 1024, 0, st>>>(offsets, nseg, bound, sc.meta);
+}
+
+int seg_validation_error(int32_t* code) {
+  int32_t v = 0;
+  const int32_t zero = 0;
+  if (hipDeviceSynchronize() != hipSuccess ||
+      hipMemcpyFromSymbol(&v, HIP_SYMBOL(g_seg_validation_error), sizeof v) != hipSuccess ||
+      hipMemcpyToSymbol(HIP_SYMBOL(g_seg_validation_error), &zero, sizeof zero) != hipSuccess)
+    return -1;
+  *code = v;
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
 // prep
 
 __global__ __launch_bounds__(1024) void seg_prep_kernel(const int64_t* __restrict__ offsets,
@@ -33,13 +77,33 @@ __global__ __launch_bounds__(1024) void seg_prep_kernel(const int64_t* __restric
                                                         uint32_t* __restrict__ big_ids,
                                                         uint64_t* __restrict__ big_keys,
                                                         uint64_t* __restrict__ big_tiles,
-                                                        int tile_log) {
+                                                        int tile_log, int validated) {
   __shared__ uint32_t cnt[32];
   __shared__ uint32_t cur[32];
   __shared__ uint64_t part_k[1024];
   __shared__ uint64_t part_t[1024];
   __shared__ uint32_t nbig_s;
   const uint32_t tid = threadIdx.x;
+  if (validated && meta->invalid) {
+    // a refused table classifies as empty: no kernel after this one touches
+    // the keys or reads the offsets again
+    if (tid == 0) {
+      meta->small_counter = 0;
+      meta->small_items = 0;
+      meta->nbig = 0;
+      meta->max_class = 0;
+      for (int i = 0; i < kSmallClasses; ++i) {
+        meta->small_start[i] = 0;
+        meta->small_count[i] = 0;
+        meta->item_prefix[i] = 0;
+      }
+      meta->item_prefix[kSmallClasses] = 0;
+      for (int c = 0; c < 33; ++c) meta->big_ge[c] = 0;
+      big_keys[0] = 0;
+      big_tiles[0] = 0;
+    }
+    return;
+  }
   if (tid < 32) cnt[tid] = 0;
   __syncthreads();
   for (int64_t s = tid; s < nseg; s += 1024) {
@@ -149,9 +213,9 @@ static void seg_dispatch(const SegData& d, const SegLaunch& l, const int64_t* of
 }
 
 void launch_seg_prep(const int64_t* offsets, int64_t nseg, const SegScratch& sc, int tile_log,
-                     hipStream_t st) {
+                     bool validated, hipStream_t st) {
   seg_prep_kernel<<<1, 1024, 0, st>>>(offsets, nseg, sc.meta, sc.small_ids, sc.big_ids,
-                                      sc.big_keys, sc.big_tiles, tile_log);
+                                      sc.big_keys, sc.big_tiles, tile_log, validated ? 1 : 0);
 }
 
 void launch_seg_small(const SegData& d, const int64_t* offsets, const SegScratch& sc, int grid,

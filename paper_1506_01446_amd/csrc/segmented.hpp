@@ -28,6 +28,17 @@ struct SegMeta {
   uint32_t small_count[kSmallClasses];
   uint32_t item_prefix[kSmallClasses + 1];
   uint32_t big_ge[33];     // number of big segments of class >= c
+  int32_t invalid;         // set by the validation kernel: the table is refused
+};
+static_assert(sizeof(SegMeta) <= 1024, "the segment meta block takes the scratch's first KiB");
+
+// Errors the validation kernel finds in a segment table (first one wins).
+enum SegTableError : int32_t {
+  kSegTableOk = 0,
+  kSegTableDecreasing = 1,  // offsets[s + 1] < offsets[s]
+  kSegTableTooLong = 2,     // a segment of 2^31 keys or more
+  kSegTableOverBound = 3,   // a segment longer than the caller's bound
+  kSegTableNegative = 4     // offsets[0] < 0
 };
 
 // Pointers into the scratch buffer of one segmented call (device memory).
@@ -103,8 +114,22 @@ void seg_run_keys64(const SegData& d, const SegLaunch& l, const int64_t* offsets
                     const SegScratch& sc, hipStream_t st);
 
 // tile_log: log2 of the big segments' tile (kSegTileLog32 or kSegTileLog64).
+// validated: a validation kernel ran first (launch_seg_validate); an invalid
+// table then classifies as empty, so no later kernel touches the keys.
 void launch_seg_prep(const int64_t* offsets, int64_t nseg, const SegScratch& sc, int tile_log,
-                     hipStream_t st);
+                     bool validated, hipStream_t st);
+
+// Checks offsets[0 .. nseg] (nondecreasing, offsets[0] >= 0, every segment
+// below 2^31 keys and at most `bound` keys) on the device; records the first
+// error of the call in sc.meta->invalid and in the device's error word
+// (seg_validation_error) if that is still clear.
+void launch_seg_validate(const int64_t* offsets, int64_t nseg, int64_t bound, const SegScratch& sc,
+                         hipStream_t st);
+
+// Reads (and then clears) the current device's error word: the first error
+// (SegTableError) any validated call recorded since the last read.  Blocks
+// until the device is idle.  0 on success, -1 on a HIP error.
+int seg_validation_error(int32_t* code);
 void launch_seg_small(const SegData& d, const int64_t* offsets, const SegScratch& sc, int grid,
                       hipStream_t st);
 // Tile sort (merge == false) or tile merge of the big segments of class >= cls_min.

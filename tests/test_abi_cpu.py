@@ -349,3 +349,18 @@ def test_bucket_tuning(lib, tmp_path):
         for name in ("tile_log2", "fuse", "merge_blocks_per_cu"):
             B.bitonic_set_tuning_value(f"{name}@{k}", 0)
     assert B.bitonic_plan_tile_log2(2**k) == 14
+
+
+def test_validation_switch(lib):
+    """Offsets validation is a switch ("validate", 0 or 1; off unless
+    BITONIC_VALIDATE=1 is set); its error query needs an output pointer."""
+    import os
+    saved = B.bitonic_get_tuning_value("validate")
+    assert saved == (1 if os.environ.get("BITONIC_VALIDATE") == "1" else 0)
+    for bad in (-1, 2):
+        with pytest.raises(B.BitonicError):
+            B.bitonic_set_tuning_value("validate", bad)
+    B.bitonic_set_tuning_value("validate", 1)
+    assert B.bitonic_get_tuning_value("validate") == 1
+    B.bitonic_set_tuning_value("validate", saved)
+    assert lib.bitonic_validation_error(None) == -1

@@ -344,6 +344,36 @@ def test_segmented_fuse_depths(seg_fuse):
         B.bitonic_set_tuning_value("seg_fuse", saved)
 
 
+def test_segmented_offsets_validation():
+    """With validation on, a bad CSR table is refused on the device: the keys
+    stay as they were and the error is recorded (1 decreasing offsets, 3 a
+    segment over the bound, 4 a negative first offset); a good table sorts
+    and records nothing.  The tables are checked before anything reads them
+    as segments, so no kernel indexes out of range."""
+    keys = W.uniform_i32(51, 4096)
+    good = np.array([0, 100, 100, 3000, 4096], dtype=np.int64)
+    cases = [(np.array([0, 100, 50, 4096], dtype=np.int64), None, 1),
+             (good, 1000, 3),
+             (np.array([-5, 100, 4000], dtype=np.int64), None, 4)]
+    saved = B.bitonic_get_tuning_value("validate")
+    try:
+        B.bitonic_set_tuning_value("validate", 1)
+        assert B.bitonic_validation_error() == 0
+        for off, bound, code in cases:
+            t = torch.from_numpy(keys.copy()).cuda()
+            o = torch.from_numpy(off).cuda()
+            print(f"[case] validation offsets={off.tolist()} bound={bound}", flush=True)
+            B.bitonic_sort_segmented_i32(t, o, True, max_seg_len=bound)
+            assert B.bitonic_validation_error() == code, (off, bound)
+            assert np.array_equal(t.cpu().numpy(), keys)
+            assert B.bitonic_validation_error() == 0     # read once, then clear
+        got = gpu_sort_segmented(keys, good, True)
+        assert B.bitonic_validation_error() == 0
+        assert np.array_equal(got, O.sort_segmented_i32(keys, good, True))
+    finally:
+        B.bitonic_set_tuning_value("validate", saved)
+
+
 def test_segmented_default_bound():
     """Without a bound the segmented sort bounds segments by the end of the
     keys' allocation (no device read, no wait): at least the keys it was
