@@ -2,7 +2,7 @@
 
 python -m paper_1506_01446_amd.autotune [--buckets 16,18,20,22,24,26,28]
         [--reps 5] [--out paper_1506_01446_amd/tuning/mi355x.txt]
-        [--log profiles/autotune_mi355x.txt]
+        [--log <full log>] [--summary profiles/autotune_mi355x.txt]
 
 Searches, on the GPU, the plan parameters that do not change the result
 (the paper leaves the shared-memory tile and the register fusion depth open,
@@ -21,9 +21,12 @@ sections 4.1 and 4.2):
     wide_tile_log2, wide_fuse
 Every candidate is timed with HIP events over fresh copies of the same seeded
 input (median of `reps` runs) and its output checked sorted.  The winners are
-written as "<name> <value>" lines (bucket entries as "name@k") under a
-"cus <count>" line, which bitonic_load_tuning reads; every timing goes to the
-log, one JSON object per line.
+written as "<name> <value>" lines (bucket entries as "name@k", only where
+the tuned plan beats the built-in one by 1 % or more) under a "cus <count>"
+line, which bitonic_load_tuning reads; every timing goes to the log, one JSON
+object per line, and a short summary (per bucket the five fastest plans and
+the winner against the built-in plan; the segmented and 8-byte timings in
+full) to --summary.
 """
 from __future__ import annotations
 
@@ -186,8 +189,29 @@ def write_tuning(path: str, best: dict, command: str = "") -> None:
                 f.write(f"{name} {best[name]}\n")
         for k, e in sorted(best.get("buckets", {}).items()):
             f.write(f"# n = 2^{k}: {e['ms']} ms tuned, {e['default_ms']} ms with the built-in plan\n")
-            for name in ("tile_log2", "fuse", "merge_blocks_per_cu"):
-                f.write(f"{name}@{k} {e[name]}\n")
+            if e["ms"] < 0.99 * e["default_ms"]:   # a bucket entry only where it pays
+                for name in ("tile_log2", "fuse", "merge_blocks_per_cu"):
+                    f.write(f"{name}@{k} {e[name]}\n")
+
+
+def write_summary(path: str, rows: list, command: str) -> None:
+    """The condensed timing table: per size bucket the five fastest plans and
+    the winner, then every segmented and 8-byte timing."""
+    out = ["# autotuner timings (ms, median of --reps runs), one JSON object per line",
+           f"# command: {command}",
+           "# per size bucket: the five fastest plans of those timed, then the winner",
+           "# against the built-in plan; the segmented and 8-byte knobs in full"]
+    for k in sorted({r["bucket"] for r in rows if "bucket" in r}):
+        cand = sorted((r for r in rows if r.get("bucket") == k and "ms" in r),
+                      key=lambda r: r["ms"])
+        out.append(f"## n = 2^{k}: {len(cand)} plans timed, slowest {cand[-1]['ms']} ms"
+                   if cand else f"## n = 2^{k}")
+        out += [json.dumps(r) for r in cand[:5]]
+        out += [json.dumps(r) for r in rows if r.get("bucket") == k and "best" in r]
+    out.append("## segmented and 8-byte knobs")
+    out += [json.dumps(r) for r in rows if "bucket" not in r]
+    with open(path, "w") as f:
+        f.write("\n".join(out) + "\n")
 
 
 def main(argv=None) -> int:
@@ -197,23 +221,28 @@ def main(argv=None) -> int:
     ap.add_argument("--quick", action="store_true")
     ap.add_argument("--out", default=DEFAULT_OUT)
     ap.add_argument("--log", default="")
+    ap.add_argument("--summary", default="")
     a = ap.parse_args(argv)
     buckets = tuple(int(x) for x in a.buckets.split(",") if x)
+    command = "python -m paper_1506_01446_amd.autotune " + " ".join(
+        argv if argv is not None else sys.argv[1:])
     logf = open(a.log, "w") if a.log else None
+    rows = []
 
     def log(s):
         print(s, file=sys.stderr, flush=True)
+        rows.append(json.loads(s))
         if logf:
             logf.write(s + "\n")
             logf.flush()
 
     if logf:
         logf.write("# autotuner timings (ms, median of --reps runs), one JSON object per line\n")
-        logf.write("# command: python -m paper_1506_01446_amd.autotune " + " ".join(
-            argv if argv is not None else sys.argv[1:]) + "\n")
+        logf.write(f"# command: {command}\n")
     best = tune(buckets, a.reps, a.quick, log=log)
-    write_tuning(a.out, best, "python -m paper_1506_01446_amd.autotune " + " ".join(
-        argv if argv is not None else sys.argv[1:]))
+    write_tuning(a.out, best, command)
+    if a.summary:
+        write_summary(a.summary, rows, command)
     B.bitonic_load_tuning(a.out)
     print(json.dumps(best))
     if logf:

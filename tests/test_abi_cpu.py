@@ -364,3 +364,20 @@ def test_validation_switch(lib):
     assert B.bitonic_get_tuning_value("validate") == 1
     B.bitonic_set_tuning_value("validate", saved)
     assert lib.bitonic_validation_error(None) == -1
+
+
+def test_autotune_summary(tmp_path):
+    """The autotuner's summary keeps the five fastest plans per bucket, the
+    winner, and every segmented and 8-byte timing."""
+    import json
+    from paper_1506_01446_amd import autotune
+    rows = [{"bucket": 20, "tile_log2": t, "fuse": 8, "merge_blocks_per_cu": -1, "ms": 1.0 + t}
+            for t in range(12, 19)]
+    rows.append({"bucket": 20, "best": {"tile_log2": 12, "ms": 13.0, "default_ms": 14.0}})
+    rows.append({"seg_blocks_per_cu": 4, "ms": 0.5})
+    p = tmp_path / "summary.txt"
+    autotune.write_summary(str(p), rows, "cmd")
+    body = [json.loads(ln) for ln in p.read_text().splitlines() if ln.startswith("{")]
+    assert [r["tile_log2"] for r in body if "tile_log2" in r][:5] == [12, 13, 14, 15, 16]
+    assert any("best" in r for r in body) and body[-1] == {"seg_blocks_per_cu": 4, "ms": 0.5}
+    assert "slowest 19.0 ms" in p.read_text()
