@@ -161,7 +161,8 @@ def kernel_table(torch, B, src, plan, repeats=10):
 KERNEL_SOURCES = ("program.hpp", "device.hpp", "codec.hpp", "launch.hpp", "tile_kernels.hpp",
                   "column_pass.hpp", "kernels_plain.hip", "kernels_tile14.hip",
                   "kernels_tile15.hip", "kernels_pass.hip", "kernels_column.hip",
-                  "kernels_column8.hip", "kernels_column8m.hip")
+                  "kernels_column8.hip", "kernels_column8m.hip", "kernels_column_lanes7.hip",
+                  "kernels_column_lanes8.hip")
 
 
 def kernel_source_hash() -> str:
@@ -189,6 +190,9 @@ def kernel_class(name: str):
     if name.startswith("column_pass_kernel<") and "Keys32" in name:
         f_, _, bounded = name[len("column_pass_kernel<"):name.index(">")].split(", ")[:3]
         return f"global_pass_f{f_}" if bounded == "false" else None
+    if name.startswith("column_lanes_pass_kernel<"):
+        fr, g = name[len("column_lanes_pass_kernel<"):name.index(">")].split(", ")[:2]
+        return f"global_pass_f{int(fr) + int(g)}"
     return None
 
 

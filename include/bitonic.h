@@ -263,7 +263,9 @@ int bitonic_sort_segmented_pairs(void* keys, int32_t* values, const int64_t* off
  *                           per step (section 4.1)
  *   BITONIC_PLAN_OPTIMIZED  register-resident tile sort and merges, and up to
  *                           `fuse` consecutive long-stride steps per HBM pass
- *                           (sections 4.1 and 4.2)
+ *                           (sections 4.1 and 4.2); passes of nine and ten
+ *                           steps split each column of keys over two or four
+ *                           lanes of a wave (tuning value "lane_pass")
  */
 enum bitonic_plan_kind {
   BITONIC_PLAN_AUTO = 0,
@@ -278,9 +280,11 @@ typedef struct bitonic_plan {
                               the optimized plan, 1..13 for semi (0 = library
                               choice: by n for the optimized plan, see
                               bitonic_plan_tile_log2; 12 for semi) */
-  int fuse;                /* max long-stride steps per HBM pass, 1..8
-                              (0 = library choice, 8); at most 7 are used
-                              when n is not a power of two */
+  int fuse;                /* max long-stride steps per HBM pass, 1..10
+                              (0 = library choice, 10); at most 7 are used
+                              when n is not a power of two, at most 8 for
+                              an array off a 16-byte boundary, in phases
+                              above 30, or with lane passes off */
   int merge_blocks_per_cu; /* tile-merge workgroups per compute unit, 1..16,
                               each looping over its tiles with the next
                               tile's loads in flight; -1 = one tile per
@@ -439,6 +443,10 @@ int bitonic_sort_plan_launches_i32(int32_t* keys, int64_t n, int ascending,
  * offsets validation, see bitonic_validation_error), "tile_lane_steps"
  * (1, the default: the tile sort runs its phases up to 9 as cross-lane
  * compare-exchanges inside each wave; 0: every phase through LDS regroups),
+ * "lane_pass" (7, the default: passes of eight and nine steps hold 2^7 keys
+ * of a column per lane over two and four lanes, ten steps 2^8 over four;
+ * 8: only nine and ten steps as lane passes, 2^8 keys per lane; 0: no lane
+ * passes, so at most eight steps per pass),
  * "wide_tile_log2" (11..13) or
  * "wide_fuse" (1..6) (the 8-byte sorts' plan); bitonic_get_tuning_value
  * reads one.

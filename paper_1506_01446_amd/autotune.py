@@ -9,9 +9,12 @@ Searches, on the GPU, the plan parameters that do not change the result
 sections 4.1 and 4.2):
   per size bucket k (n = 2^k keys, single-array 4-byte sort)
     tile_log2            keys per on-chip tile (2^12 .. 2^15)
-    fuse                 long-stride steps fused per HBM pass (4 .. 8)
+    fuse                 long-stride steps fused per HBM pass (6 .. 10)
     merge_blocks_per_cu  tile-merge workgroups per compute unit (-1: one
                          tile each)
+  lane_pass              how passes of eight to ten steps split columns
+                         over lanes (7 or 8), by the summed time of the
+                         tuned plans of the buckets from 2^22 up
   segmented sort (the 8192-segment batched workload, and a table of 64
   segments of the serving workload's lengths, 2^8 .. 2^22 keys)
     seg_blocks_per_cu       small-segment kernel workgroups per compute unit
@@ -108,7 +111,7 @@ def tune(buckets=(16, 18, 20, 22, 24, 26, 28), reps: int = 5, quick: bool = Fals
     best = {"cus": torch.cuda.get_device_properties(0).multi_processor_count,
             "device": torch.cuda.get_device_name(0), "buckets": {}}
     tiles = (13, 14) if quick else (12, 13, 14, 15)
-    fuses = (7, 8) if quick else (4, 5, 6, 7, 8)
+    fuses = (8, 10) if quick else (6, 7, 8, 9, 10)
     merges = (2,) if quick else (-1, 1, 2, 4)
     for k in buckets:
         n = 1 << k
@@ -130,6 +133,24 @@ def tune(buckets=(16, 18, 20, 22, 24, 26, 28), reps: int = 5, quick: bool = Fals
                               "ms": round(ms, 4), "default_ms": round(default_ms, 4)}
         log(json.dumps({"bucket": k, "best": best["buckets"][k]}))
         del src, buf
+    lanes = []
+    for mode in (7, 8):
+        B.bitonic_set_tuning_value("lane_pass", mode)
+        total = 0.0
+        for k, e in best["buckets"].items():
+            if k < 22:
+                continue
+            src = torch.empty(1 << k, dtype=torch.int32, device="cuda")
+            B.bitonic_keygen_i32(src, W.SEED_BASE + k)
+            buf = torch.empty_like(src)
+            total += _time_plain(torch, src, buf, ("optimized", e["tile_log2"], e["fuse"],
+                                                   e["merge_blocks_per_cu"]), reps)
+            del src, buf
+        lanes.append((total, mode))
+        log(json.dumps({"lane_pass": mode, "ms_buckets_22_up": round(total, 4)}))
+    lanes.sort()
+    B.bitonic_set_tuning_value("lane_pass", lanes[0][1])
+    best["lane_pass"] = lanes[0][1]
     tables = _segment_tables(torch)
     seg = []
     for bpc in ((4,) if quick else (2, 3, 4, 6, 8)):
@@ -183,7 +204,7 @@ def write_tuning(path: str, best: dict, command: str = "") -> None:
             f.write(f"# command: {command}\n")
         if "cus" in best:
             f.write(f"cus {best['cus']}\n")
-        for name in ("tile_log2", "fuse", "merge_blocks_per_cu", "seg_blocks_per_cu",
+        for name in ("tile_log2", "fuse", "merge_blocks_per_cu", "lane_pass", "seg_blocks_per_cu",
                      "seg_pass_blocks_per_cu", "seg_fuse", "wide_tile_log2", "wide_fuse"):
             if name in best:
                 f.write(f"{name} {best[name]}\n")

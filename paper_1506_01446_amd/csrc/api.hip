@@ -31,7 +31,7 @@
 namespace bitonic {
 
 static std::atomic<int> g_tile_log2{0};  // 0: by n (default_tile_log2)
-static std::atomic<int> g_fuse{8};
+static std::atomic<int> g_fuse{10};
 static std::atomic<int> g_merge_bpc{2};  // 0: one tile per workgroup
 static std::atomic<int> g_wide_tile_log2{13};  // 8-byte sorts
 static std::atomic<int> g_wide_fuse{6};
@@ -39,6 +39,11 @@ static std::atomic<int> g_seg_bpc{4};    // small-segment workgroups per compute
 static std::atomic<int> g_seg_pass_bpc{8};  // big-segment pass workgroups per compute unit
 static std::atomic<int> g_seg_fuse{kSegFuseMax};  // steps per big-segment pass
 static std::atomic<int> g_tile_lane{1};  // tile sort with cross-lane steps (program kind 4)
+// Lane passes (columns split over lanes; launch_column_lanes_pass): 0 off, so
+// at most kFuseMaxColumn steps per pass; 8: nine and ten steps as 2^8 keys
+// per lane over two and four lanes; 7: eight and nine steps as 2^7 keys per
+// lane over two and four lanes (ten as with 8).
+static std::atomic<int> g_lane_pass{7};
 static std::atomic<int> g_validate{-1};  // check segment tables on the device; -1: not yet read
 
 // Offsets validation of the segmented sorts: the tuning value "validate", or
@@ -61,6 +66,7 @@ struct Resolved {
   int fuse;
   int sort_kind = 0;      // tile-sort program: 0, or 4 with cross-lane steps
   int merge_bpc;          // tile-merge workgroups per compute unit
+  int lane_pass = 0;      // g_lane_pass at resolve time
   uint32_t merge_blocks;  // merge_bpc x compute units (set when enqueueing)
   bool scalar_io = false;  // optimized plan for an array off a 16-byte boundary
 };
@@ -128,6 +134,7 @@ static int resolve(const bitonic_plan* plan, int64_t n, Resolved* r) {
   if (r->kind == BITONIC_PLAN_OPTIMIZED && r->tile == 0) r->tile = default_tile_log2(n);
   if (r->kind == BITONIC_PLAN_OPTIMIZED && !tile_log2_supported(r->tile)) return BITONIC_EINVAL;
   if (r->fuse < 1 || r->fuse > kFuseMax) return BITONIC_EINVAL;
+  r->lane_pass = g_lane_pass.load();
   return BITONIC_OK;
 }
 
@@ -145,6 +152,14 @@ struct Observer {
 
 // Enqueue (or, with count_only, just count) the launches for phases 1..K of
 // the network over keys[0, n).
+// Keys per lane (log2) of an f-step lane pass under lane-pass mode `mode`
+// (g_lane_pass), or 0 for a register pass.
+static int lane_pass_regs(int mode, int f) {
+  if (mode == 8) return f >= 9 ? 8 : 0;
+  if (mode == 7) return f == 8 || f == 9 ? 7 : (f == 10 ? 8 : 0);
+  return 0;
+}
+
 static int64_t enqueue_plain(int32_t* keys, uint32_t n, int K, Codec flip, const Resolved& r,
                              hipStream_t st, bool count_only, Observer* obs = nullptr) {
   const int k = ceil_log2(n);
@@ -223,6 +238,10 @@ static int64_t enqueue_plain(int32_t* keys, uint32_t n, int K, Codec flip, const
   // a pass that straddles n takes the bounds-checked eight-step kernel, which
   // runs out of registers, so such sorts use at most seven.
   const int fuse = (r.fuse > kFuseMaxRagged && (n & (n - 1)) != 0) ? kFuseMaxRagged : r.fuse;
+  // Passes of more than kFuseMaxColumn steps split each column over lanes;
+  // they need whole blocks and lane byte offsets below 2^32 (lane_pass_fits):
+  // aligned power-of-two arrays, phases up to 30.
+  const bool lanes_ok = r.lane_pass != 0 && !r.scalar_io && (n & (n - 1)) == 0;
   emit(tile_shape(BITONIC_LAUNCH_TILE_SORT, L), [&] {
     if (r.scalar_io)
       launch_tile_scalar(0, keys, n, flip, CX_ENC, st);
@@ -230,8 +249,10 @@ static int64_t enqueue_plain(int32_t* keys, uint32_t n, int K, Codec flip, const
       launch_tile(L, r.sort_kind, keys, n, flip, CX_ENC, 0, st);
   });
   for (int p = L + 1; p <= K; ++p) {
+    const bool lanes = lanes_ok && p <= 30;
+    const int fz = lanes || fuse < kFuseMaxColumn ? fuse : kFuseMaxColumn;
     const int nb = p - L;                          // long-stride steps
-    const int npass = (nb + fuse - 1) / fuse;      // fused HBM passes
+    const int npass = (nb + fz - 1) / fz;          // fused HBM passes
     int top = p - 1;
     // Each pass takes as many steps as it may, the last one what is left:
     // the phase's first pass, the one with the mirror step, is then always
@@ -240,7 +261,8 @@ static int64_t enqueue_plain(int32_t* keys, uint32_t n, int K, Codec flip, const
     for (int i = 0; i < npass; ++i) {
       const int left = top - L + 1;                // bits still to do
       const int passes_left = npass - i;
-      const int f = fuse < left - (passes_left - 1) ? fuse : left - (passes_left - 1);
+      const int f = fz < left - (passes_left - 1) ? fz : left - (passes_left - 1);
+      const int fr = lanes ? lane_pass_regs(r.lane_pass, f) : 0;
       const int q = top - f + 1;
       // the four-column passes (f <= 5, aligned) form 32-bit byte offsets
       // below 2^(q+2); the one-column passes follow column_pass_offset_bits
@@ -250,6 +272,8 @@ static int64_t enqueue_plain(int32_t* keys, uint32_t n, int K, Codec flip, const
       emit(sh, [&] {
         if (r.scalar_io)
           launch_column_pass_i32(f, i == 0, keys, n, q, st);
+        else if (fr)
+          (void)launch_column_lanes_pass(f, fr, i == 0, keys, n, q, st);
         else
           launch_global_pass(f, i == 0, keys, n, q, st);
       });
@@ -962,6 +986,11 @@ int bitonic_set_tuning_value(const char* key, int value) {
     g_tile_lane.store(value);
     return BITONIC_OK;
   }
+  if (!std::strcmp(key, "lane_pass")) {
+    if (value != 0 && value != 7 && value != 8) return BITONIC_EINVAL;
+    g_lane_pass.store(value);
+    return BITONIC_OK;
+  }
   if (!std::strcmp(key, "wide_tile_log2")) {
     if (value < kWideTileMinLog2 || value > kWideTileMaxLog2) return BITONIC_EINVAL;
     g_wide_tile_log2.store(value);
@@ -997,6 +1026,7 @@ int bitonic_get_tuning_value(const char* key, int* value) {
   else if (!std::strcmp(key, "seg_pass_blocks_per_cu")) *value = g_seg_pass_bpc.load();
   else if (!std::strcmp(key, "seg_fuse")) *value = g_seg_fuse.load();
   else if (!std::strcmp(key, "tile_lane_steps")) *value = g_tile_lane.load();
+  else if (!std::strcmp(key, "lane_pass")) *value = g_lane_pass.load();
   else if (!std::strcmp(key, "validate")) *value = validate_enabled() ? 1 : 0;
   else if (!std::strcmp(key, "wide_tile_log2")) *value = g_wide_tile_log2.load();
   else if (!std::strcmp(key, "wide_fuse")) *value = g_wide_fuse.load();

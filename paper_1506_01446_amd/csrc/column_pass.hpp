@@ -180,3 +180,89 @@ static void launch_column_pass_F(bool mirror, ST st, uint32_t n, int q, hipStrea
 }
 
 }  // namespace bitonic
+
+namespace bitonic {
+
+// F = FR + G steps on index bits q+F-1 .. q of 4-byte keys with every column
+// of a 2^(q+F) block split over 2^G neighbouring lanes of 2^FR keys each, so
+// that the steps on the top G row bits are cross-lane compare-exchanges
+// (DPP) and the other FR run in registers: passes of more steps than one
+// thread's registers hold (up to 10 with 2^8 keys per lane), one HBM round
+// trip instead of two.  Thread g = blockIdx.x * 256 + threadIdx.x is lane
+// s = g mod 2^G of column c = (g / 2^G) mod 2^q of block g / 2^(q+G), and
+// holds rows s 2^FR .. s 2^FR + 2^FR - 1 of column c in ascending order.
+// With MIRROR the upper half of a column's lanes hold the mirrored rows:
+// lane s >= 2^(G-1) holds rows R_s .. R_s + 2^FR - 1 of column 2^q-1-c,
+// R_s = 2^F - (s - 2^(G-1) + 1) 2^FR, again ascending, so the mirror step
+// pairs register j of lane s with register 2^FR-1-j of lane s XOR 2^(G-1),
+// and in every later step the lower register of a pair holds the lower
+// index.  Whole blocks only (n a multiple of 2^(q+F)), lane byte offsets
+// below 2^(q+F+2) <= 2^32.  A wave's access to one register row is two (G
+// = 1) or four (G = 2) runs of consecutive keys.
+template <int FR, int G, bool MIRROR>
+__global__ __launch_bounds__(256) void column_lanes_pass_kernel(int32_t* __restrict__ keys, int q) {
+  constexpr int F = FR + G;
+  constexpr int M = 1 << FR;
+  constexpr uint32_t SUBS = 1u << G;
+  constexpr uint32_t HALF = SUBS >> 1;
+  static_assert(G >= 1 && G <= 2, "one or two lane bits per column");
+  int32_t x[M];
+  const uint32_t gw = blockIdx.x * 256u;                        // uniform
+  const uint32_t bs = (gw >> (q + G)) << (q + F);               // uniform block start
+  const uint32_t t = (gw + threadIdx.x) & ((1u << (q + G)) - 1u);
+  const uint32_t s = t & (SUBS - 1u);
+  const uint32_t col = t >> G;
+  const bool upper = MIRROR && s >= HALF;
+  const uint32_t colx = upper ? ((1u << q) - 1u) - col : col;
+  const uint32_t row0 = upper ? (1u << F) - (s - HALF + 1u) * (uint32_t)M : s * (uint32_t)M;
+  const uint32_t off = ((row0 << q) + colx) * 4u;               // lane byte offset
+  static_for<0, M>([&](auto J) {
+    const uint32_t r0 = bs + ((uint32_t)J << q);                // uniform row start
+    x[J] = Keys32{keys}.at(r0).getb(off);
+  });
+  __builtin_amdgcn_sched_barrier(0);
+  if constexpr (MIRROR) {
+    // the lower half of the column's lanes keeps the minimum of each pair
+    const int32_t c = upper ? INT32_MAX : INT32_MIN;
+    static_for<0, M / 2>([&](auto J) {
+      constexpr int j = J;
+      constexpr int jj = M - 1 - j;
+      const int32_t pa = lane_xor<HALF>(x[jj]);
+      const int32_t pb = lane_xor<HALF>(x[j]);
+      x[j] = keep_of_pair(x[j], pa, c);
+      x[jj] = keep_of_pair(x[jj], pb, c);
+    });
+  }
+  // half-cleaners on the remaining lane bits, highest first: the lane with
+  // the lower rows keeps the minimum (in the mirrored half, the lane whose
+  // bit is set)
+  constexpr int NL = MIRROR ? G - 1 : G;
+  static_for<0, NL>([&](auto I) {
+    constexpr int b = NL - 1 - I;
+    const bool bit = ((s >> b) & 1u) != 0;
+    const int32_t c = (upper ? !bit : bit) ? INT32_MAX : INT32_MIN;
+    static_for<0, M>([&](auto J) { x[J] = lane_pair_step<(1u << b)>(x[J], c); });
+  });
+  pass_steps<FR, false, 1>(x);
+  __builtin_amdgcn_sched_barrier(0);
+  // row starts for the stores from an opaque copy of the block start (see
+  // column_pass_kernel)
+  uint32_t bs_st = bs;
+  asm volatile("" : "+s"(bs_st));
+  static_for<0, M>([&](auto J) {
+    const uint32_t r0 = bs_st + ((uint32_t)J << q);
+    Keys32{keys}.at(r0).putb(off, x[J]);
+    __builtin_amdgcn_sched_barrier(0);
+  });
+}
+
+template <int FR, int G>
+static void launch_column_lanes_FG(bool mirror, int32_t* keys, uint32_t n, int q, hipStream_t st) {
+  const uint32_t blocks = n >> (FR + 8);  // n / 2^FR threads, 256 per workgroup
+  if (mirror)
+    column_lanes_pass_kernel<FR, G, true><<<blocks, 256, 0, st>>>(keys, q);
+  else
+    column_lanes_pass_kernel<FR, G, false><<<blocks, 256, 0, st>>>(keys, q);
+}
+
+}  // namespace bitonic

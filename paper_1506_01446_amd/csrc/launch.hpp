@@ -12,7 +12,8 @@ constexpr int kTileRegLogPlain = 5;  // 32 keys per thread in the tile kernels
 constexpr int kFuseMaxFourColumn = 5;  // wider aligned passes take the one-column kernel
 constexpr int kTileMinLog2 = 11;
 constexpr int kTileMaxLog2 = 15;
-constexpr int kFuseMax = 8;
+constexpr int kFuseMaxColumn = 8;  // steps one thread's registers hold (one column)
+constexpr int kFuseMax = 10;       // with a column split over lanes (lane passes)
 constexpr int kFuseMaxRagged = 7;  // n not a power of two (see enqueue_plain)
 constexpr int kLdsNetworkMaxLog2 = 13;
 
@@ -35,13 +36,23 @@ void launch_tile_scalar(int kind, int32_t* keys, uint32_t n, Codec cd, int cx, h
 
 // f fused steps on bits q+f-1 .. q (the first one the mirror step if
 // `mirror`) on keys already in the sorting domain.  Requires q >= 8,
-// q + f <= 31, 1 <= f <= kFuseMax (f <= 5: four columns per thread; 6..8:
-// one column).
+// q + f <= 31, 1 <= f <= kFuseMaxColumn (f <= 5: four columns per thread;
+// 6..8: one column).
 void launch_global_pass(int f, bool mirror, int32_t* keys, uint32_t n, int q, hipStream_t st);
 
-// The one-column passes: behind launch_global_pass for f = 6 .. kFuseMax,
-// and for every f (1 .. kFuseMax) in the plan for unaligned arrays.
+// The one-column passes: behind launch_global_pass for f = 6 .. kFuseMaxColumn,
+// and for every f (1 .. kFuseMaxColumn) in the plan for unaligned arrays.
 void launch_column_pass_i32(int f, bool mirror, int32_t* keys, uint32_t n, int q, hipStream_t st);
+
+// Lane passes (column_lanes_pass_kernel): f = fr + g steps, each column split
+// over 2^g lanes of 2^fr keys; (fr, g) in {7, 8} x {1, 2}.  Needs n a
+// multiple of 2^(q+f) and q + f <= 30 (lane_pass_fits); false (nothing
+// launched) for any other shape.
+constexpr bool lane_pass_fits(uint32_t n, int q, int f) {
+  return q + f <= 30 && q >= 8 && n != 0 && (n & ((uint32_t(1) << (q + f)) - 1u)) == 0;
+}
+bool launch_column_lanes_pass(int f, int fr, bool mirror, int32_t* keys, uint32_t n, int q,
+                              hipStream_t st);
 
 // LDS network on 2^L tiles (L <= kLdsNetworkMaxLog2).
 void launch_lds_network(int L, int p_first, int p_last, bool tail, int32_t* keys, uint32_t n,

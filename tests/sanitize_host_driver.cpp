@@ -47,7 +47,7 @@ int main() {
   for (int64_t n : sizes) {
     for (int kind = 0; kind <= 3; ++kind)
       for (int t : {0, 11, 13, 15})
-        for (int f : {0, 1, 5, 8}) {
+        for (int f : {0, 1, 5, 8, 9, 10}) {
           bitonic_plan plan{kind, kind == 2 && t > 13 ? 12 : t, f, 0};
           const int64_t m = bitonic_plan_passes(n, &plan);
           if (m < 0) continue;
@@ -66,10 +66,20 @@ int main() {
     for (int lay = BITONIC_LAYOUT_SEG_KEYS32; lay <= BITONIC_LAYOUT_SEG_KEYS64; ++lay)
       CHECK(bitonic_plan_shapes(n, lay, nullptr, shapes.data(), 4096) >= 0);
   }
+  // lane-pass modes
+  for (int mode : {0, 7, 8}) {
+    CHECK(bitonic_set_tuning_value("lane_pass", mode) == BITONIC_OK);
+    bitonic_plan plan{BITONIC_PLAN_OPTIMIZED, 11, 10, 0};
+    for (int64_t n : sizes)
+      CHECK(bitonic_plan_shapes(n, BITONIC_LAYOUT_KEYS32, &plan, shapes.data(), 4096) ==
+            bitonic_plan_passes(n, &plan));
+  }
+  CHECK(bitonic_set_tuning_value("lane_pass", 5) == BITONIC_EINVAL);
+  CHECK(bitonic_set_tuning_value("lane_pass", 7) == BITONIC_OK);
   CHECK(bitonic_plan_shapes(-1, 0, nullptr, nullptr, 0) == -1);
   CHECK(bitonic_plan_shapes(5, 99, nullptr, nullptr, 0) == -1);
   // shapes into a too-small array: the count still comes back, nothing overflows
-  CHECK(bitonic_plan_shapes(1 << 24, BITONIC_LAYOUT_KEYS32, nullptr, shapes.data(), 3) == 23);
+  CHECK(bitonic_plan_shapes(1 << 24, BITONIC_LAYOUT_KEYS32, nullptr, shapes.data(), 3) == 21);
 
   // argument checks that return before any device work
   CHECK(bitonic_sort_i32(nullptr, -1, 1, nullptr) == BITONIC_EINVAL);

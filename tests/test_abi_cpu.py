@@ -38,7 +38,7 @@ def test_argument_errors_are_synchronous(lib):
     assert lib.bitonic_sort_plan_i32(None, 0, 1, ctypes.byref(bad), None) == -1
     bad = B.bitonic_plan(3, 17, 0, 0)
     assert lib.bitonic_sort_plan_i32(None, 0, 1, ctypes.byref(bad), None) == -1
-    bad = B.bitonic_plan(3, 13, 9, 0)
+    bad = B.bitonic_plan(3, 13, 11, 0)
     assert lib.bitonic_sort_plan_i32(None, 0, 1, ctypes.byref(bad), None) == -1
     bad = B.bitonic_plan(3, 13, 4, 17)
     assert lib.bitonic_sort_plan_i32(None, 0, 1, ctypes.byref(bad), None) == -1
@@ -51,7 +51,7 @@ def test_argument_errors_are_synchronous(lib):
     assert lib.bitonic_sort_segmented_bounded_i32(None, None, 3, -1, 1, None) == -1
     assert lib.bitonic_keygen_i32(None, -1, 0, 0, None) == -1
     assert lib.bitonic_set_tuning(99, 0, 0) == -1
-    assert lib.bitonic_set_tuning(0, 9, 0) == -1
+    assert lib.bitonic_set_tuning(0, 11, 0) == -1
     assert lib.bitonic_set_tuning(0, 0, 99) == -1
     assert lib.bitonic_set_tuning(0, 0, -2) == -1
     assert lib.bitonic_load_tuning(b"/nonexistent/tuning.txt") == -1
@@ -93,15 +93,19 @@ def test_wide_argument_errors_are_synchronous(lib):
 
 
 def _closed_form_optimized(k, t, f):
+    """Launches of the optimized plan on n = 2^k: the tile sort, then per
+    phase p > t its ceil((p - t) / f) passes and one merge; passes of more
+    than eight steps (columns split over lanes) only up to phase 30."""
     if k <= 1:
         return k
     if k <= t:
         return 1
-    return 1 + sum(-(-(p - t) // f) + 1 for p in range(t + 1, k + 1))
+    return 1 + sum(-(-(p - t) // (f if f <= 8 or p <= 30 else 8)) + 1
+                   for p in range(t + 1, k + 1))
 
 
 @pytest.mark.parametrize("t", [11, 12, 13, 14, 15])
-@pytest.mark.parametrize("f", [1, 2, 3, 4, 5, 6, 7, 8])
+@pytest.mark.parametrize("f", [1, 2, 3, 4, 5, 6, 7, 8, 9, 10])
 def test_optimized_pass_count(lib, t, f):
     for k in range(1, 32):
         n = 2**k
@@ -143,7 +147,8 @@ def test_semi_plan_counts(lib):
 def test_headline_pass_count(lib):
     # n = 2^24 with 2^13-key tiles and up to 4 fused steps per HBM pass
     assert B.bitonic_plan_passes(2**24, ("optimized", 13, 4)) == 33
-    assert B.bitonic_plan_passes(2**24) == 23  # default: 2^14 tiles, 8 fused steps
+    # default: 2^14 tiles, up to 10 fused steps (one pass per phase)
+    assert B.bitonic_plan_passes(2**24) == 21
     assert B.bitonic_plan_passes(0) == 0 and B.bitonic_plan_passes(1) == 0
     assert B.bitonic_plan_passes(-1) == -1
 
@@ -238,6 +243,10 @@ def _check_shapes(shapes, n, elem_bytes):
         assert (1 << s["q"]) * s["elem_bytes"] <= 2 ** s["offset_bits"], (n, s)
         if s["kind"] in ("global_pass", "step"):
             assert 1 <= s["fuse"] and s["q"] + s["fuse"] <= k <= 31, (n, s)
+        if s["kind"] == "global_pass" and s["fuse"] > 8:
+            # a lane pass: whole blocks, its lane byte offsets span the block
+            assert elem_bytes == 4 and n == 1 << k, (n, s)
+            assert (1 << (s["q"] + s["fuse"])) * 4 <= 2 ** s["offset_bits"], (n, s)
 
 
 @pytest.mark.parametrize("layout", ["keys32", "keys32_unaligned"])
@@ -246,7 +255,7 @@ def test_plan_shapes_4byte(lib, layout):
     every optimized plan and the Basic and Semi plans, keeps its byte
     offsets within their width; the shapes are the plan's launches."""
     plans = [None, "basic", ("semi", 8), ("semi", 13)] + \
-        [("optimized", t, f) for t in (11, 12, 13, 14, 15) for f in range(1, 9)]
+        [("optimized", t, f) for t in (11, 12, 13, 14, 15) for f in range(1, 11)]
     for plan in plans:
         for n in SHAPE_SIZES:
             sh = B.bitonic_plan_shapes(n, layout, plan)
@@ -336,7 +345,7 @@ def test_bucket_tuning(lib, tmp_path):
             with pytest.raises(B.BitonicError):
                 B.bitonic_set_tuning_value(bad, 13)
         with pytest.raises(B.BitonicError):
-            B.bitonic_set_tuning_value(f"fuse@{k}", 9)
+            B.bitonic_set_tuning_value(f"fuse@{k}", 11)
         p = tmp_path / "t.txt"
         p.write_text(f"# tuned table\nmerge_blocks_per_cu@{k} 4   # four per CU\n\nfuse@{k} 6\n")
         B.bitonic_load_tuning(str(p))
@@ -381,3 +390,33 @@ def test_autotune_summary(tmp_path):
     assert [r["tile_log2"] for r in body if "tile_log2" in r][:5] == [12, 13, 14, 15, 16]
     assert any("best" in r for r in body) and body[-1] == {"seg_blocks_per_cu": 4, "ms": 0.5}
     assert "slowest 19.0 ms" in p.read_text()
+
+
+def test_lane_pass_modes(lib):
+    """Passes of nine and ten steps exist only with lane passes on, for
+    power-of-two arrays on a 16-byte boundary; off, or for other arrays,
+    a pass takes at most eight steps (seven for other sizes)."""
+    saved = B.bitonic_get_tuning_value("lane_pass")
+    try:
+        for bad in (1, 6, 9, -1):
+            with pytest.raises(B.BitonicError):
+                B.bitonic_set_tuning_value("lane_pass", bad)
+        for mode in (7, 8):
+            B.bitonic_set_tuning_value("lane_pass", mode)
+            assert B.bitonic_get_tuning_value("lane_pass") == mode
+            for f in (9, 10):
+                assert B.bitonic_plan_passes(2**24, ("optimized", 14, f)) == \
+                    _closed_form_optimized(24, 14, f)
+                fuses = [s["fuse"] for s in B.bitonic_plan_shapes(2**24, "keys32", ("optimized", 14, f))
+                         if s["kind"] == "global_pass"]
+                assert max(fuses) == f
+                assert max(s["fuse"] for s in B.bitonic_plan_shapes(
+                    2**24, "keys32_unaligned", ("optimized", 14, f))
+                    if s["kind"] == "global_pass") == 8
+                assert B.bitonic_plan_passes(2**24 - 1, ("optimized", 14, f)) == \
+                    _closed_form_optimized(24, 14, 7)
+        B.bitonic_set_tuning_value("lane_pass", 0)
+        assert B.bitonic_plan_passes(2**24, ("optimized", 14, 10)) == \
+            _closed_form_optimized(24, 14, 8)
+    finally:
+        B.bitonic_set_tuning_value("lane_pass", saved)

@@ -136,6 +136,53 @@ def test_per_phase_states(plan):
         assert np.array_equal(t.cpu().numpy(), states[p]), (plan, p)
 
 
+@pytest.mark.parametrize("mode", [8, 7])
+def test_lane_passes(mode):
+    """Passes of eight to ten steps with each column split over two or four
+    lanes (lane passes; with mode 7 eight- and nine-step passes take 2^7
+    keys per lane): every tile size, both directions, at power-of-two sizes
+    whose last phases have nine and ten long-stride steps, so that mirror
+    and plain lane passes of every width run."""
+    saved = B.bitonic_get_tuning_value("lane_pass")
+    want = {}
+    try:
+        B.bitonic_set_tuning_value("lane_pass", mode)
+        for t in (11, 12, 13, 14, 15):
+            for k in sorted({min(t + 9, 24), min(t + 10, 24)}):
+                if k not in want:
+                    keys = W.uniform_i32(W.SEED_BASE + 300 + k, 1 << k)
+                    want[k] = (keys, O.sort_i32(keys, True))
+                keys, w = want[k]
+                for f in (8, 9, 10):
+                    plan = ("optimized", t, f)
+                    assert max(s["fuse"] for s in B.bitonic_plan_shapes(1 << k, "keys32", plan)
+                               if s["kind"] == "global_pass") == min(f, k - t)
+                    for asc in (True, False):
+                        print(f"[case] lane_pass={mode} plan={plan} n=2^{k} asc={asc}", flush=True)
+                        got = gpu_sort(keys, asc, plan)
+                        assert np.array_equal(got, w if asc else w[::-1]), (mode, plan, k, asc)
+    finally:
+        B.bitonic_set_tuning_value("lane_pass", saved)
+
+
+@pytest.mark.parametrize("plan", [("optimized", 11, 10), ("optimized", 11, 9)],
+                         ids=lambda p: "-".join(map(str, p)))
+def test_per_phase_states_lane_passes(plan):
+    """Per-phase states through the lane passes: n = 2^21 with 2^11 tiles,
+    whose phases 20 and 21 take nine- and ten-step passes."""
+    n = 1 << 21
+    keys = W.uniform_i32(79, n)
+    states = {}
+    O.bitonic_i32(keys, True, O.FLIP_VIRTUAL,
+                  hook=lambda p, s, x: states.__setitem__(p, x) if s == p else None)
+    for p in range(12, 22):
+        print(f"[case] per-phase lane passes plan={plan} p={p}", flush=True)
+        t = torch.from_numpy(keys.copy()).cuda()
+        B.bitonic_network_phases_i32(t, p, True, plan)
+        torch.cuda.synchronize()
+        assert np.array_equal(t.cpu().numpy(), states[p]), (plan, p)
+
+
 @pytest.mark.parametrize("shift", [1, 2, 3])
 def test_per_phase_states_unaligned(shift):
     """The same on views 1-3 keys past a 16-byte boundary, which take the
@@ -231,10 +278,12 @@ def test_config_2_full_size():
 
 
 @pytest.mark.parametrize("plan", [("optimized", 14, 8, 2), ("optimized", 14, 7, 2),
-                                  ("optimized", 13, 6)],
+                                  ("optimized", 13, 6), ("optimized", 14, 10, 2),
+                                  ("optimized", 15, 9, 1)],
                          ids=lambda p: "-".join(map(str, p)))
 def test_wide_fusion_full_size(plan):
-    """Six to eight fused steps (one-column passes) at strides up to 2^23."""
+    """Six to ten fused steps (one-column and lane passes; the ragged size
+    takes at most seven) at strides up to 2^23."""
     for n, seed in ((1 << 24, W.SEED_BASE + 2), (10_000_007, W.SEED_BASE + 3)):
         keys = W.uniform_i32(seed, n)
         want = O.sort_i32(keys, True)
