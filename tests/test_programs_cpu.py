@@ -188,7 +188,7 @@ def test_wide_programs(emu, L):
 # 4-byte tiles (vector I/O, and the 2^13 scalar-I/O tile), the 8-byte tiles,
 # the segmented small-segment programs and big-segment tiles.
 INSTANTIATED = sorted({(L, 5, k) for L in range(11, 16) for k in (0, 1, 4)} |
-                      {(13, 5, 6), (13, 5, 3)} |
+                      {(13, 5, 6), (13, 5, 3), (14, 5, 6), (14, 5, 3)} |
                       {(L, 4, k) for L in (11, 12, 13) for k in (2, 3)} |
                       {(L, 5, k) for L in range(5, 14) for k in (2, 6)} |
                       {(13, 4, 2), (13, 4, 3)})
