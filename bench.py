@@ -124,7 +124,10 @@ def kernel_table(torch, B, src, plan, repeats=10):
     launch is run `repeats` times back to back on its own, bracketed by two
     HIP events on the launch stream (the network is data-oblivious, so
     repeating a launch on its own output costs the same)."""
-    desc = B.bitonic_plan_describe(src.numel(), plan)
+    # the launches' kinds; a tile merge that starts with the mirror step is
+    # a whole phase on tiles twice the sort's tile (tile_phase)
+    desc = [("tile_phase" if sh["kind"] == "tile_merge" and sh["mirror"] else sh["kind"],
+             sh["fuse"]) for sh in B.bitonic_plan_shapes(src.numel(), "keys32", plan)]
     ev = B.HipEvents(2)
     rt = ev.rt
     rt.hipEventRecord.argtypes = [B.ctypes.c_void_p, B.ctypes.c_void_p]
@@ -179,11 +182,12 @@ def kernel_source_hash() -> str:
 
 def kernel_class(name: str):
     """Kernel class of a (demangled, shortened) kernel name: tile_sort,
-    tile_merge, global_pass_f<F> for the unbounded pass kernels, else None."""
+    tile_merge, tile_phase, global_pass_f<F> for the unbounded pass kernels,
+    else None."""
     for pre in ("tile_kernel<", "tile_loop_kernel<"):
         if name.startswith(pre):
             args = name[len(pre):name.index(">")].split(", ")
-            return "tile_merge" if args[2] == "1" else "tile_sort"
+            return {"1": "tile_merge", "5": "tile_phase"}.get(args[2], "tile_sort")
     if name.startswith("global_pass_kernel<"):
         f_, _, bounded = name[len("global_pass_kernel<"):name.index(">")].split(", ")
         return f"global_pass_f{f_}" if bounded == "false" else None

@@ -374,6 +374,8 @@ int64_t bitonic_plan_describe(int64_t n, const bitonic_plan* plan, int32_t* kind
  *                sorts); log2 of the tile for tile, LDS and small-segment
  *                launches
  *   mirror       1 if the launch's first step is the mirror step of a phase
+ *                (a tile merge with mirror 1 performs all of phase q on its
+ *                2^q-key tiles: phase t+1 of a sort with 2^t-key tiles)
  *   elem_bytes   bytes per element in each array: 4 (4-byte keys; pairs,
  *                whose keys and values are two 4-byte arrays) or 8 (8-byte keys)
  *   offset_bits  width of the byte offsets the kernel adds to a row or tile
@@ -443,6 +445,9 @@ int bitonic_sort_plan_launches_i32(int32_t* keys, int64_t n, int ascending,
  * offsets validation, see bitonic_validation_error), "tile_lane_steps"
  * (1, the default: the tile sort runs its phases up to 9 as cross-lane
  * compare-exchanges inside each wave; 0: every phase through LDS regroups),
+ * "phase_merge" (1, the default: phase t+1 of a sort with 2^t-key tiles,
+ * t <= 14, 16-byte aligned keys, runs as one launch on 2^(t+1)-key tiles;
+ * 0: a one-step pass and a tile merge),
  * "lane_pass" (7, the default: passes of eight and nine steps hold 2^7 keys
  * of a column per lane over two and four lanes, ten steps 2^8 over four;
  * 8: only nine and ten steps as lane passes, 2^8 keys per lane; 0: no lane

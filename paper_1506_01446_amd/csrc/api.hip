@@ -44,6 +44,9 @@ static std::atomic<int> g_tile_lane{1};  // tile sort with cross-lane steps (pro
 // per lane over two and four lanes; 7: eight and nine steps as 2^7 keys per
 // lane over two and four lanes (ten as with 8).
 static std::atomic<int> g_lane_pass{7};
+// Phase t+1 of a sort with 2^t-key tiles (t <= 14) as one tile-phase launch
+// on 2^(t+1)-key tiles instead of a one-step pass and a merge.
+static std::atomic<int> g_phase_merge{1};
 static std::atomic<int> g_validate{-1};  // check segment tables on the device; -1: not yet read
 
 // Offsets validation of the segmented sorts: the tuning value "validate", or
@@ -67,6 +70,7 @@ struct Resolved {
   int sort_kind = 0;      // tile-sort program: 0, or 4 with cross-lane steps
   int merge_bpc;          // tile-merge workgroups per compute unit
   int lane_pass = 0;      // g_lane_pass at resolve time
+  bool phase_merge = false;  // g_phase_merge at resolve time
   uint32_t merge_blocks;  // merge_bpc x compute units (set when enqueueing)
   bool scalar_io = false;  // optimized plan for an array off a 16-byte boundary
 };
@@ -135,6 +139,7 @@ static int resolve(const bitonic_plan* plan, int64_t n, Resolved* r) {
   if (r->kind == BITONIC_PLAN_OPTIMIZED && !tile_log2_supported(r->tile)) return BITONIC_EINVAL;
   if (r->fuse < 1 || r->fuse > kFuseMax) return BITONIC_EINVAL;
   r->lane_pass = g_lane_pass.load();
+  r->phase_merge = g_phase_merge.load() != 0;
   return BITONIC_OK;
 }
 
@@ -249,6 +254,13 @@ static int64_t enqueue_plain(int32_t* keys, uint32_t n, int K, Codec flip, const
       launch_tile(L, r.sort_kind, keys, n, flip, CX_ENC, 0, st);
   });
   for (int p = L + 1; p <= K; ++p) {
+    if (p == L + 1 && r.phase_merge && !r.scalar_io && p <= kTileMaxLog2) {
+      // the whole phase on 2^p-key tiles (mirror step included)
+      const int cx = p == K ? CX_DEC : CX_NONE;
+      emit(bitonic_launch_shape{BITONIC_LAUNCH_TILE_MERGE, 0, p, 1, 4, 64},
+           [&] { launch_tile(p, 5, keys, n, flip, cx, r.merge_blocks, st); });
+      continue;
+    }
     const bool lanes = lanes_ok && p <= 30;
     const int fz = lanes || fuse < kFuseMaxColumn ? fuse : kFuseMaxColumn;
     const int nb = p - L;                          // long-stride steps
@@ -986,6 +998,11 @@ int bitonic_set_tuning_value(const char* key, int value) {
     g_tile_lane.store(value);
     return BITONIC_OK;
   }
+  if (!std::strcmp(key, "phase_merge")) {
+    if (value < 0 || value > 1) return BITONIC_EINVAL;
+    g_phase_merge.store(value);
+    return BITONIC_OK;
+  }
   if (!std::strcmp(key, "lane_pass")) {
     if (value != 0 && value != 7 && value != 8) return BITONIC_EINVAL;
     g_lane_pass.store(value);
@@ -1027,6 +1044,7 @@ int bitonic_get_tuning_value(const char* key, int* value) {
   else if (!std::strcmp(key, "seg_fuse")) *value = g_seg_fuse.load();
   else if (!std::strcmp(key, "tile_lane_steps")) *value = g_tile_lane.load();
   else if (!std::strcmp(key, "lane_pass")) *value = g_lane_pass.load();
+  else if (!std::strcmp(key, "phase_merge")) *value = g_phase_merge.load();
   else if (!std::strcmp(key, "validate")) *value = validate_enabled() ? 1 : 0;
   else if (!std::strcmp(key, "wide_tile_log2")) *value = g_wide_tile_log2.load();
   else if (!std::strcmp(key, "wide_fuse")) *value = g_wide_fuse.load();

@@ -20,11 +20,12 @@ constexpr int kLdsNetworkMaxLog2 = 13;
 bool tile_log2_supported(int L);
 
 // Tile sort (kind 0: phases 1..L; kind 4: the same with its steps on lane
-// bits as cross-lane steps) or tile merge (kind 1: strides
-// 2^(L-1)..1) over every 2^L tile of keys[0, n).  The merge runs at most
-// max_blocks workgroups (0 = one per tile), each looping over its tiles.
-// cx (CX_*): whether loads encode and stores decode; a tile sort takes
-// CX_ENC or CX_BOTH, a merge CX_NONE or CX_DEC.
+// bits as cross-lane steps), tile merge (kind 1: strides 2^(L-1)..1) or
+// tile phase (kind 5, L >= 12: phase L, for tiles whose halves are each
+// ascending) over every 2^L tile of keys[0, n).  Merges and phases run at
+// most max_blocks workgroups (0 = one per tile), each looping over its
+// tiles.  cx (CX_*): whether loads encode and stores decode; a tile sort
+// takes CX_ENC or CX_BOTH, a merge or phase CX_NONE or CX_DEC.
 void launch_tile(int L, int kind, int32_t* keys, uint32_t n, Codec cd, int cx,
                  uint32_t max_blocks, hipStream_t st);
 

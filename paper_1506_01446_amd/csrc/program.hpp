@@ -313,17 +313,37 @@ constexpr Program make_tile_merge(int L, int r, bool vector_io) {
   return P;
 }
 
+// All of phase L on each tile whose two halves are each ascending: the
+// mirror step on bit L-1, then half-cleaners on bits L-2 .. 0, so the tile
+// comes out ascending.  For a sort with 2^(L-1)-key tiles this is phase L in
+// one launch instead of a one-step pass and a tile merge.  Loaded and stored
+// in the 16-byte I/O layout; the steps run in the layouts of the tile sort's
+// longer phases (a virtual layout for the mirror step), one regroup more than
+// a merge.
+constexpr Program make_tile_phase(int L, int r) {
+  Program P{};
+  P.L = L;
+  P.r = r;
+  P.g[P.ngroups++] = io_group(L, r);
+  add_merge_bits(P, L - 1, true);
+  P.g[P.ngroups++] = io_group(L, r);
+  return P;
+}
+
 // Program kinds: 0 sort, 1 merge (16-byte vector I/O); 2 sort, 3 merge
 // (scalar I/O); 4 and 6: the sorts 0 and 2 with lane steps (lane_top
 // kLaneTop; see make_tile_sort), for 4-byte keys only (a lane step moves one
-// 4-byte word per key).
+// 4-byte word per key); 5: one whole phase (make_tile_phase, vector I/O).
 constexpr int kLaneTop = 9;
-constexpr bool kind_is_vector(int kind) { return kind == 0 || kind == 1 || kind == 4; }
+constexpr bool kind_is_vector(int kind) {
+  return kind == 0 || kind == 1 || kind == 4 || kind == 5;
+}
 constexpr bool kind_is_lean(int kind) { return kind == 2 || kind == 3 || kind == 6; }
 constexpr Program make_program(int L, int r, int kind) {
-  return (kind & 1) ? make_tile_merge(L, r, kind_is_vector(kind))
-                    : make_tile_sort(L, r, kind_is_vector(kind),
-                                     kind == 4 || kind == 6 ? kLaneTop : 0);
+  return kind == 5    ? make_tile_phase(L, r)
+         : (kind & 1) ? make_tile_merge(L, r, kind_is_vector(kind))
+                      : make_tile_sort(L, r, kind_is_vector(kind),
+                                       kind == 4 || kind == 6 ? kLaneTop : 0);
 }
 
 constexpr bool layout_is_vector4(const Group& G) {

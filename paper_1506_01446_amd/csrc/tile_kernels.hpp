@@ -15,8 +15,11 @@
 //                                 swaps) instead of LDS regroups
 //  tile_kernel<L, r, 1, CX>       the last L steps (strides 2^(L-1)..1) of a
 //                                 phase longer than the tile, on every tile
-//  tile_loop_kernel<L, r, 1, CX>  the same merge, each workgroup looping over
-//                                 several tiles
+//  tile_kernel<L, r, 5, CX>       phase L (mirror step, then strides
+//                                 2^(L-2)..1) on every tile: phase t+1 of a
+//                                 sort with 2^t-key tiles in one launch
+//  tile_loop_kernel<L, r, K, CX>  the same (K = 1, 5), each workgroup
+//                                 looping over several tiles
 #pragma once
 
 #include "device.hpp"
@@ -82,15 +85,15 @@ __global__ __launch_bounds__(1 << (L - RL)) void tile_loop_kernel(int32_t* __res
 
 constexpr int kTileRegLog = kTileRegLogPlain;
 
-template <int L, int CX>
+template <int L, int KIND, int CX>
 inline void launch_merge_LC(int32_t* keys, uint32_t n, Codec cd, uint32_t max_blocks,
                             hipStream_t st) {
   const uint32_t ntiles = (uint32_t)(((uint64_t)n + (1u << L) - 1) >> L);
   constexpr int NT = 1 << (L - kTileRegLog);
   if (max_blocks == 0 || max_blocks >= ntiles)
-    tile_kernel<L, kTileRegLog, 1, CX><<<ntiles, NT, 0, st>>>(keys, n, cd);
+    tile_kernel<L, kTileRegLog, KIND, CX><<<ntiles, NT, 0, st>>>(keys, n, cd);
   else
-    tile_loop_kernel<L, kTileRegLog, 1, CX><<<max_blocks, NT, 0, st>>>(keys, n, cd);
+    tile_loop_kernel<L, kTileRegLog, KIND, CX><<<max_blocks, NT, 0, st>>>(keys, n, cd);
 }
 
 // Instantiated codec modes: a tile sort is a sort's first kernel (CX_ENC, or
@@ -116,10 +119,17 @@ inline void launch_tile_L(int kind, int32_t* keys, uint32_t n, Codec cd, int cx,
       tile_kernel<L, kTileRegLog, 4, CX_ENC><<<ntiles, NT, 0, st>>>(keys, n, cd);
     else
       tile_kernel<L, kTileRegLog, 4, CX_BOTH><<<ntiles, NT, 0, st>>>(keys, n, cd);
+  } else if (kind == 5) {  // one whole phase (program kind 5), 2^12..2^15 tiles
+    if constexpr (L >= 12) {
+      if (cx == CX_NONE)
+        launch_merge_LC<L, 5, CX_NONE>(keys, n, cd, max_blocks, st);
+      else
+        launch_merge_LC<L, 5, CX_DEC>(keys, n, cd, max_blocks, st);
+    }
   } else if (cx == CX_NONE) {
-    launch_merge_LC<L, CX_NONE>(keys, n, cd, max_blocks, st);
+    launch_merge_LC<L, 1, CX_NONE>(keys, n, cd, max_blocks, st);
   } else {
-    launch_merge_LC<L, CX_DEC>(keys, n, cd, max_blocks, st);
+    launch_merge_LC<L, 1, CX_DEC>(keys, n, cd, max_blocks, st);
   }
 }
 

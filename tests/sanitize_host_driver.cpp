@@ -75,11 +75,18 @@ int main() {
             bitonic_plan_passes(n, &plan));
   }
   CHECK(bitonic_set_tuning_value("lane_pass", 5) == BITONIC_EINVAL);
+  for (int on : {0, 1}) {
+    CHECK(bitonic_set_tuning_value("phase_merge", on) == BITONIC_OK);
+    bitonic_plan plan{BITONIC_PLAN_OPTIMIZED, 14, 8, 0};
+    for (int64_t n : sizes)
+      CHECK(bitonic_plan_shapes(n, BITONIC_LAYOUT_KEYS32, &plan, shapes.data(), 4096) ==
+            bitonic_plan_passes(n, &plan));
+  }
   CHECK(bitonic_set_tuning_value("lane_pass", 7) == BITONIC_OK);
   CHECK(bitonic_plan_shapes(-1, 0, nullptr, nullptr, 0) == -1);
   CHECK(bitonic_plan_shapes(5, 99, nullptr, nullptr, 0) == -1);
   // shapes into a too-small array: the count still comes back, nothing overflows
-  CHECK(bitonic_plan_shapes(1 << 24, BITONIC_LAYOUT_KEYS32, nullptr, shapes.data(), 3) == 21);
+  CHECK(bitonic_plan_shapes(1 << 24, BITONIC_LAYOUT_KEYS32, nullptr, shapes.data(), 3) == 20);
 
   // argument checks that return before any device work
   CHECK(bitonic_sort_i32(nullptr, -1, 1, nullptr) == BITONIC_EINVAL);

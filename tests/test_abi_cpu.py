@@ -92,16 +92,17 @@ def test_wide_argument_errors_are_synchronous(lib):
     assert lib.bitonic_set_tuning_value(b"wide_fuse", 0) == -1
 
 
-def _closed_form_optimized(k, t, f):
+def _closed_form_optimized(k, t, f, phase=True):
     """Launches of the optimized plan on n = 2^k: the tile sort, then per
     phase p > t its ceil((p - t) / f) passes and one merge; passes of more
-    than eight steps (columns split over lanes) only up to phase 30."""
+    than eight steps (columns split over lanes) only up to phase 30; with
+    `phase` (16-byte aligned keys, t <= 14) phase t + 1 is one launch."""
     if k <= 1:
         return k
     if k <= t:
         return 1
     return 1 + sum(-(-(p - t) // (f if f <= 8 or p <= 30 else 8)) + 1
-                   for p in range(t + 1, k + 1))
+                   for p in range(t + 1, k + 1)) - (1 if phase and t <= 14 else 0)
 
 
 @pytest.mark.parametrize("t", [11, 12, 13, 14, 15])
@@ -125,7 +126,7 @@ def test_wide_pass_count(lib, t, f):
     tile sort, then per phase beyond the tile its fused passes and a merge)."""
     for k in range(1, 32):
         got = B.bitonic_wide_plan_passes(2**k, ("optimized", t, f))
-        assert got == _closed_form_optimized(k, t, f), (k, t, f)
+        assert got == _closed_form_optimized(k, t, f, phase=False), (k, t, f)
         if k >= 2:
             assert B.bitonic_wide_plan_passes(2**k - 1, ("optimized", t, f)) == got
 
@@ -146,9 +147,10 @@ def test_semi_plan_counts(lib):
 
 def test_headline_pass_count(lib):
     # n = 2^24 with 2^13-key tiles and up to 4 fused steps per HBM pass
-    assert B.bitonic_plan_passes(2**24, ("optimized", 13, 4)) == 33
-    # default: 2^14 tiles, up to 10 fused steps (one pass per phase)
-    assert B.bitonic_plan_passes(2**24) == 21
+    assert B.bitonic_plan_passes(2**24, ("optimized", 13, 4)) == 32  # phase 14 in one launch
+    # default: 2^14 tiles, up to 10 fused steps (one pass per phase), phase
+    # 15 as one launch
+    assert B.bitonic_plan_passes(2**24) == 20
     assert B.bitonic_plan_passes(0) == 0 and B.bitonic_plan_passes(1) == 0
     assert B.bitonic_plan_passes(-1) == -1
 
@@ -420,3 +422,31 @@ def test_lane_pass_modes(lib):
             _closed_form_optimized(24, 14, 8)
     finally:
         B.bitonic_set_tuning_value("lane_pass", saved)
+
+
+def test_phase_merge_switch(lib):
+    """Phase t + 1 as one tile-phase launch (a tile merge whose first step
+    is the mirror step, on 2^(t+1)-key tiles) for aligned arrays with
+    t <= 14; off, a one-step pass and a merge."""
+    saved = B.bitonic_get_tuning_value("phase_merge")
+    try:
+        for bad in (-1, 2):
+            with pytest.raises(B.BitonicError):
+                B.bitonic_set_tuning_value("phase_merge", bad)
+        for on in (0, 1):
+            B.bitonic_set_tuning_value("phase_merge", on)
+            for t in (11, 12, 13, 14, 15):
+                for k in (t, t + 1, t + 2, 24):
+                    plan = ("optimized", t, 8)
+                    assert B.bitonic_plan_passes(2**k, plan) == \
+                        _closed_form_optimized(k, t, 8, bool(on)), (on, t, k)
+                    sh = B.bitonic_plan_shapes(2**k, "keys32", plan)
+                    ph = [s for s in sh if s["kind"] == "tile_merge" and s["mirror"]]
+                    assert len(ph) == (1 if on and t <= 14 and k > t else 0)
+                    if ph:
+                        assert ph[0]["q"] == t + 1 and sh[1] == ph[0]
+                    # an array off a 16-byte boundary keeps pass and merge
+                    assert not any(s["kind"] == "tile_merge" and s["mirror"] for s in
+                                   B.bitonic_plan_shapes(2**k, "keys32_unaligned", plan))
+    finally:
+        B.bitonic_set_tuning_value("phase_merge", saved)

@@ -183,6 +183,54 @@ def test_per_phase_states_lane_passes(plan):
         assert np.array_equal(t.cpu().numpy(), states[p]), (plan, p)
 
 
+@pytest.mark.parametrize("t", [11, 12, 13, 14])
+def test_phase_merge(t):
+    """Phase t + 1 as one launch on 2^(t+1)-key tiles (the tile phase), on
+    and off: as the last launch (n = 2^(t+1), keys decoded there, also
+    float32 keys), followed by further phases, with a ragged tail, with
+    looping workgroups, both directions; and the state after phase t + 1
+    equals the oracle network's."""
+    saved = B.bitonic_get_tuning_value("phase_merge")
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    try:
+        for on in (1, 0):
+            B.bitonic_set_tuning_value("phase_merge", on)
+            for n in (1 << (t + 1), (1 << (t + 1)) - 3, (1 << (t + 3)) + 4099,
+                      (3 * cus << (t + 1)) + 5):
+                for plan in (("optimized", t, 8, -1), ("optimized", t, 10, 1)):
+                    keys = W.uniform_i32(W.SEED_BASE + 57 * t + n, n)
+                    for asc in (True, False):
+                        print(f"[case] phase_merge={on} plan={plan} n={n} asc={asc}", flush=True)
+                        got = gpu_sort(keys, asc, plan)
+                        assert np.array_equal(got, O.sort_i32(keys, asc)), (on, plan, n, asc)
+            n = 1 << (t + 1)
+            bits = W.uniform_i32(W.SEED_BASE + 58, n).view(np.uint32).copy()
+            bits[: len(TOTAL_ORDER_BITS)] = TOTAL_ORDER_BITS
+            old = B.bitonic_get_tuning_value("tile_log2")
+            B.bitonic_set_tuning_value("tile_log2", t)
+            try:
+                for asc in (True, False):
+                    tk = torch.from_numpy(bits.view(np.int32).copy()).cuda()
+                    B.bitonic_sort_keys(tk, asc, "float32")
+                    torch.cuda.synchronize()
+                    want = O.sort_keys(bits.view(np.float32), O.KEY_F32, asc).view(np.int32)
+                    assert np.array_equal(tk.cpu().numpy(), want), (on, asc)
+            finally:
+                B.bitonic_set_tuning_value("tile_log2", old)
+            n = (1 << (t + 2)) + 321
+            keys = W.uniform_i32(80 + t, n)
+            states = {}
+            O.bitonic_i32(keys, True, O.FLIP_VIRTUAL,
+                          hook=lambda p, s, x: states.__setitem__(p, x) if s == p else None)
+            for p in (t + 1, t + 2):
+                tk = torch.from_numpy(keys.copy()).cuda()
+                B.bitonic_network_phases_i32(tk, p, True, ("optimized", t, 8))
+                torch.cuda.synchronize()
+                assert np.array_equal(tk.cpu().numpy(), states[p]), (on, t, p)
+    finally:
+        B.bitonic_set_tuning_value("phase_merge", saved)
+
+
 @pytest.mark.parametrize("shift", [1, 2, 3])
 def test_per_phase_states_unaligned(shift):
     """The same on views 1-3 keys past a 16-byte boundary, which take the
