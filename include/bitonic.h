@@ -447,7 +447,9 @@ int bitonic_sort_plan_launches_i32(int32_t* keys, int64_t n, int ascending,
  * compare-exchanges inside each wave; 0: every phase through LDS regroups),
  * "phase_merge" (1, the default: phase t+1 of a sort with 2^t-key tiles,
  * t <= 14, 16-byte aligned keys, runs as one launch on 2^(t+1)-key tiles;
- * 0: a one-step pass and a tile merge),
+ * 0: a one-step pass and a tile merge), "phase_blocks_per_cu" (-1..16:
+ * tile-phase workgroups per compute unit, each looping over its tiles,
+ * default 1; -1 one tile per workgroup; 0 as the tile merges),
  * "lane_pass" (7, the default: passes of eight and nine steps hold 2^7 keys
  * of a column per lane over two and four lanes, ten steps 2^8 over four;
  * 8: only nine and ten steps as lane passes, 2^8 keys per lane; 0: no lane

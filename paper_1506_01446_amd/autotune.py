@@ -15,6 +15,9 @@ sections 4.1 and 4.2):
   lane_pass              how passes of eight to ten steps split columns
                          over lanes (7 or 8), by the summed time of the
                          tuned plans of the buckets from 2^22 up
+  phase_blocks_per_cu    workgroups of the tile phase (phase t+1 in one
+                         launch) per compute unit, -1, 1, 2 or 4, by the
+                         summed time of the tuned plans from 2^20 up
   segmented sort (the 8192-segment batched workload, and a table of 64
   segments of the serving workload's lengths, 2^8 .. 2^22 keys)
     seg_blocks_per_cu       small-segment kernel workgroups per compute unit
@@ -133,12 +136,10 @@ def tune(buckets=(16, 18, 20, 22, 24, 26, 28), reps: int = 5, quick: bool = Fals
                               "ms": round(ms, 4), "default_ms": round(default_ms, 4)}
         log(json.dumps({"bucket": k, "best": best["buckets"][k]}))
         del src, buf
-    lanes = []
-    for mode in (7, 8):
-        B.bitonic_set_tuning_value("lane_pass", mode)
+    def bucket_total(lo):
         total = 0.0
         for k, e in best["buckets"].items():
-            if k < 22:
+            if k < lo:
                 continue
             src = torch.empty(1 << k, dtype=torch.int32, device="cuda")
             B.bitonic_keygen_i32(src, W.SEED_BASE + k)
@@ -146,6 +147,21 @@ def tune(buckets=(16, 18, 20, 22, 24, 26, 28), reps: int = 5, quick: bool = Fals
             total += _time_plain(torch, src, buf, ("optimized", e["tile_log2"], e["fuse"],
                                                    e["merge_blocks_per_cu"]), reps)
             del src, buf
+        return total
+
+    phases = []
+    for pb in ((1,) if quick else (-1, 1, 2, 4)):
+        B.bitonic_set_tuning_value("phase_blocks_per_cu", pb)
+        total = bucket_total(20)
+        phases.append((total, pb))
+        log(json.dumps({"phase_blocks_per_cu": pb, "ms_buckets_20_up": round(total, 4)}))
+    phases.sort()
+    B.bitonic_set_tuning_value("phase_blocks_per_cu", phases[0][1])
+    best["phase_blocks_per_cu"] = phases[0][1]
+    lanes = []
+    for mode in (7, 8):
+        B.bitonic_set_tuning_value("lane_pass", mode)
+        total = bucket_total(22)
         lanes.append((total, mode))
         log(json.dumps({"lane_pass": mode, "ms_buckets_22_up": round(total, 4)}))
     lanes.sort()
@@ -204,7 +220,8 @@ def write_tuning(path: str, best: dict, command: str = "") -> None:
             f.write(f"# command: {command}\n")
         if "cus" in best:
             f.write(f"cus {best['cus']}\n")
-        for name in ("tile_log2", "fuse", "merge_blocks_per_cu", "lane_pass", "seg_blocks_per_cu",
+        for name in ("tile_log2", "fuse", "merge_blocks_per_cu", "lane_pass", "phase_blocks_per_cu",
+                     "seg_blocks_per_cu",
                      "seg_pass_blocks_per_cu", "seg_fuse", "wide_tile_log2", "wide_fuse"):
             if name in best:
                 f.write(f"{name} {best[name]}\n")

@@ -47,6 +47,9 @@ static std::atomic<int> g_lane_pass{7};
 // Phase t+1 of a sort with 2^t-key tiles (t <= 14) as one tile-phase launch
 // on 2^(t+1)-key tiles instead of a one-step pass and a merge.
 static std::atomic<int> g_phase_merge{1};
+// Tile-phase workgroups per compute unit, each looping over its tiles
+// (-1: one tile per workgroup; 0: as the tile merges).
+static std::atomic<int> g_phase_bpc{1};
 static std::atomic<int> g_validate{-1};  // check segment tables on the device; -1: not yet read
 
 // Offsets validation of the segmented sorts: the tuning value "validate", or
@@ -72,6 +75,7 @@ struct Resolved {
   int lane_pass = 0;      // g_lane_pass at resolve time
   bool phase_merge = false;  // g_phase_merge at resolve time
   uint32_t merge_blocks;  // merge_bpc x compute units (set when enqueueing)
+  uint32_t phase_blocks = 0;  // the same for the tile phase
   bool scalar_io = false;  // optimized plan for an array off a 16-byte boundary
 };
 
@@ -258,7 +262,7 @@ static int64_t enqueue_plain(int32_t* keys, uint32_t n, int K, Codec flip, const
       // the whole phase on 2^p-key tiles (mirror step included)
       const int cx = p == K ? CX_DEC : CX_NONE;
       emit(bitonic_launch_shape{BITONIC_LAUNCH_TILE_MERGE, 0, p, 1, 4, 64},
-           [&] { launch_tile(p, 5, keys, n, flip, cx, r.merge_blocks, st); });
+           [&] { launch_tile(p, 5, keys, n, flip, cx, r.phase_blocks, st); });
       continue;
     }
     const bool lanes = lanes_ok && p <= 30;
@@ -382,6 +386,8 @@ static int bind_device(Resolved* r) {
   int rc = current_device(&dev);
   if (rc) return rc;
   r->merge_blocks = r->merge_bpc > 0 ? (uint32_t)(device_cus(dev) * r->merge_bpc) : 0u;
+  const int pb = g_phase_bpc.load();
+  r->phase_blocks = pb == 0 ? r->merge_blocks : (pb > 0 ? (uint32_t)(device_cus(dev) * pb) : 0u);
   return BITONIC_OK;
 }
 
@@ -998,6 +1004,11 @@ int bitonic_set_tuning_value(const char* key, int value) {
     g_tile_lane.store(value);
     return BITONIC_OK;
   }
+  if (!std::strcmp(key, "phase_blocks_per_cu")) {
+    if (value < -1 || value > 16) return BITONIC_EINVAL;
+    g_phase_bpc.store(value);
+    return BITONIC_OK;
+  }
   if (!std::strcmp(key, "phase_merge")) {
     if (value < 0 || value > 1) return BITONIC_EINVAL;
     g_phase_merge.store(value);
@@ -1045,6 +1056,7 @@ int bitonic_get_tuning_value(const char* key, int* value) {
   else if (!std::strcmp(key, "tile_lane_steps")) *value = g_tile_lane.load();
   else if (!std::strcmp(key, "lane_pass")) *value = g_lane_pass.load();
   else if (!std::strcmp(key, "phase_merge")) *value = g_phase_merge.load();
+  else if (!std::strcmp(key, "phase_blocks_per_cu")) *value = g_phase_bpc.load();
   else if (!std::strcmp(key, "validate")) *value = validate_enabled() ? 1 : 0;
   else if (!std::strcmp(key, "wide_tile_log2")) *value = g_wide_tile_log2.load();
   else if (!std::strcmp(key, "wide_fuse")) *value = g_wide_fuse.load();

@@ -433,6 +433,14 @@ def test_phase_merge_switch(lib):
         for bad in (-1, 2):
             with pytest.raises(B.BitonicError):
                 B.bitonic_set_tuning_value("phase_merge", bad)
+        pb = B.bitonic_get_tuning_value("phase_blocks_per_cu")
+        for bad in (-2, 17):
+            with pytest.raises(B.BitonicError):
+                B.bitonic_set_tuning_value("phase_blocks_per_cu", bad)
+        for ok in (-1, 0, 4):
+            B.bitonic_set_tuning_value("phase_blocks_per_cu", ok)
+            assert B.bitonic_get_tuning_value("phase_blocks_per_cu") == ok
+        B.bitonic_set_tuning_value("phase_blocks_per_cu", pb)
         for on in (0, 1):
             B.bitonic_set_tuning_value("phase_merge", on)
             for t in (11, 12, 13, 14, 15):
