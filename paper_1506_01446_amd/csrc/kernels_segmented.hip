@@ -235,6 +235,15 @@ void launch_seg_tiles(bool merge, const SegData& d, const int64_t* offsets, cons
   seg_dispatch(d, l, offsets, sc, st);
 }
 
+void launch_seg_phase(const SegData& d, const int64_t* offsets, const SegScratch& sc, int grid,
+                      hipStream_t st) {
+  SegLaunch l{};
+  l.what = SegLaunch::kPhase;
+  l.cls = kSegTileLog32 + 1;
+  l.grid = grid;
+  seg_dispatch(d, l, offsets, sc, st);
+}
+
 void launch_seg_pass(int f, bool mirror, const SegData& d, const int64_t* offsets,
                      const SegScratch& sc, int cls, int q, int grid, hipStream_t st) {
   SegLaunch l{};

@@ -320,27 +320,29 @@ constexpr Program make_tile_merge(int L, int r, bool vector_io) {
 // in the 16-byte I/O layout; the steps run in the layouts of the tile sort's
 // longer phases (a virtual layout for the mirror step), one regroup more than
 // a merge.
-constexpr Program make_tile_phase(int L, int r) {
+constexpr Program make_tile_phase(int L, int r, bool vector_io) {
   Program P{};
   P.L = L;
   P.r = r;
-  P.g[P.ngroups++] = io_group(L, r);
+  const Group io = vector_io ? io_group(L, r) : io_scalar_group(L, r);
+  P.g[P.ngroups++] = io;
   add_merge_bits(P, L - 1, true);
-  P.g[P.ngroups++] = io_group(L, r);
+  P.g[P.ngroups++] = io;
   return P;
 }
 
 // Program kinds: 0 sort, 1 merge (16-byte vector I/O); 2 sort, 3 merge
 // (scalar I/O); 4 and 6: the sorts 0 and 2 with lane steps (lane_top
 // kLaneTop; see make_tile_sort), for 4-byte keys only (a lane step moves one
-// 4-byte word per key); 5: one whole phase (make_tile_phase, vector I/O).
+// 4-byte word per key); 5 and 7: one whole phase (make_tile_phase) with
+// vector and scalar I/O.
 constexpr int kLaneTop = 9;
 constexpr bool kind_is_vector(int kind) {
   return kind == 0 || kind == 1 || kind == 4 || kind == 5;
 }
-constexpr bool kind_is_lean(int kind) { return kind == 2 || kind == 3 || kind == 6; }
+constexpr bool kind_is_lean(int kind) { return kind == 2 || kind == 3 || kind == 6 || kind == 7; }
 constexpr Program make_program(int L, int r, int kind) {
-  return kind == 5    ? make_tile_phase(L, r)
+  return kind == 5 || kind == 7 ? make_tile_phase(L, r, kind == 5)
          : (kind & 1) ? make_tile_merge(L, r, kind_is_vector(kind))
                       : make_tile_sort(L, r, kind_is_vector(kind),
                                        kind == 4 || kind == 6 ? kLaneTop : 0);

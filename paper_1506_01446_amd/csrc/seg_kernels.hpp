@@ -285,6 +285,44 @@ __global__ __launch_bounds__(seg_tile_threads<ST>()) void seg_tile_kernel(
   }
 }
 
+// Phase kSegTileLog32 + 1 of the big segments of that class and above
+// (4-byte keys): the mirror step and the half-cleaners on units of
+// 2^(kSegTileLog32 + 1) keys, whose two halves the tile sort left ascending
+// (program kind 7, scalar I/O).  Units run over the segments' padded sizes
+// (big_keys), so a unit wholly in a segment's virtual padding has no work;
+// one workgroup per CU (135 KiB of LDS), each taking a contiguous range of
+// units.
+constexpr int kSegPhaseLog = kSegTileLog32 + 1;
+constexpr int kSegPhaseThreads = 1 << (kSegPhaseLog - kTileRegLogSeg);
+
+template <class CD>
+__global__ __launch_bounds__(kSegPhaseThreads) void seg_phase_kernel(
+    Keys32 keys, const int64_t* __restrict__ offsets, const SegMeta* __restrict__ meta,
+    const uint32_t* __restrict__ big_ids, const uint64_t* __restrict__ big_keys, CD cd) {
+  using PR = Prog<kSegPhaseLog, kTileRegLogSeg, 7>;
+  static_assert(PR::NT == kSegPhaseThreads, "one unit per workgroup");
+  __shared__ int32_t lds[PR::LDSW];
+  const uint32_t cnt = meta->big_ge[kSegPhaseLog];
+  uint64_t u, uend;
+  unit_range(big_keys[cnt] >> kSegPhaseLog, &u, &uend);
+  uint32_t i = u < uend ? upper_index(big_keys, cnt, u << kSegPhaseLog) : 0u;
+  for (; u < uend; ++u) {
+    const uint64_t key0 = u << kSegPhaseLog;
+    i = advance_index(big_keys, cnt, i, key0);
+    const uint64_t lk = key0 - big_keys[i];  // unit's first key, segment-local
+    const uint32_t s = big_ids[i];
+    const int64_t off = offsets[s];
+    const uint64_t len = (uint64_t)(offsets[s + 1] - off);
+    if (lk >= len) continue;  // only virtual padding (the same for the whole workgroup)
+    const uint64_t left = len - lk;
+    const uint32_t valid = left < (uint64_t)PR::T ? (uint32_t)left : (uint32_t)PR::T;
+    uint32_t tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    tile_program<PR>(keys.k + off + lk, valid, cd, lds, tid);
+    __syncthreads();  // LDS reuse by the next unit
+  }
+}
+
 // Columns per thread of a big-segment pass of F steps: 4 up to F = 3, then
 // fewer as the rows double, so that a thread holds at most 32 elements
 // (2^F rows x the columns).
@@ -372,6 +410,11 @@ void seg_run(ST keys, CD cd, const SegLaunch& l, const int64_t* offsets, const S
     case SegLaunch::kTileMerge:
       seg_tile_kernel<3><<<l.grid, seg_tile_threads<ST>(), 0, st>>>(
           keys, offsets, sc.meta, sc.big_ids, sc.big_tiles, l.cls, cd);
+      break;
+    case SegLaunch::kPhase:
+      if constexpr (std::is_same_v<ST, Keys32>)
+        seg_phase_kernel<<<l.grid, kSegPhaseThreads, 0, st>>>(keys, offsets, sc.meta, sc.big_ids,
+                                                              sc.big_keys, cd);
       break;
     case SegLaunch::kPass: {
 #define BITONIC_SEG_PASS(F)                                                                     \

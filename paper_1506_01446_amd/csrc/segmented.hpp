@@ -96,7 +96,7 @@ struct SegData {
 // sort or merge of the segments of class >= cls, or a pass of f steps on
 // bits q+f-1 .. q of them.
 struct SegLaunch {
-  enum : int { kSmall = 0, kTileSort = 1, kTileMerge = 2, kPass = 3 };
+  enum : int { kSmall = 0, kTileSort = 1, kTileMerge = 2, kPass = 3, kPhase = 4 };
   int what;
   int f;
   bool mirror;
@@ -138,5 +138,11 @@ void launch_seg_tiles(bool merge, const SegData& d, const int64_t* offsets, cons
 // f fused steps on bits q+f-1 .. q of the big segments of class >= cls.
 void launch_seg_pass(int f, bool mirror, const SegData& d, const int64_t* offsets,
                      const SegScratch& sc, int cls, int q, int grid, hipStream_t st);
+// Phase kSegTileLog32 + 1 of the big segments of that class or above, 4-byte
+// keys only (seg_phase_supported): one launch instead of a one-step pass and
+// a tile merge.
+constexpr bool seg_phase_supported(const SegData& d) { return !d.keys64 && !d.values; }
+void launch_seg_phase(const SegData& d, const int64_t* offsets, const SegScratch& sc, int grid,
+                      hipStream_t st);
 
 }  // namespace bitonic

@@ -292,8 +292,11 @@ def test_plan_shapes_8byte(lib, layout, unit):
 def test_plan_shapes_segmented(lib, layout, unit):
     """The segmented planner, for a longest segment of 1..2^31 elements:
     prep, the small-segment kernel, and for segments past 2^13 elements the
-    tile sort and per phase its passes (at most "seg_fuse" steps each) and merge."""
+    tile sort and per phase its passes (at most "seg_fuse" steps each) and
+    merge; for 4-byte keys phase 15 in one launch (a tile merge with the
+    mirror step, on 2^15-key units), with "phase_merge" on."""
     T = 14 if layout == "seg_keys32" else 13   # big-segment tile: 2^14 keys, 2^13 8-byte elements
+    phase = layout == "seg_keys32" and B.bitonic_get_tuning_value("phase_merge") == 1
     for k in range(0, 32):
         n = 2**k
         sh = B.bitonic_plan_shapes(n, layout)
@@ -306,10 +309,14 @@ def test_plan_shapes_segmented(lib, layout, unit):
         merges = [s for s in sh if s["kind"] == "tile_merge"]
         passes = [s for s in sh if s["kind"] == "global_pass"]
         assert len(merges) == max(0, k - T)
+        if phase and k > T:
+            assert merges[0]["mirror"] == 1 and merges[0]["q"] == T + 1 and sh[3] == merges[0]
         assert all(s["fuse"] <= B.bitonic_get_tuning_value("seg_fuse") for s in passes)
         assert all(s["q"] >= T for s in passes)
-        # every phase p > T performs steps on bits p-1 .. T exactly once
-        assert sum(s["fuse"] for s in passes) == sum(p - T for p in range(T + 1, k + 1))
+        # every phase p > T performs steps on bits p-1 .. T exactly once (the
+        # tile phase those of phase T + 1)
+        done = 1 if phase and k > T else 0
+        assert sum(s["fuse"] for s in passes) + done == sum(p - T for p in range(T + 1, k + 1))
 
 
 def test_noalloc_argument_errors(lib):

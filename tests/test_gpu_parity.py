@@ -421,6 +421,41 @@ def test_segmented_big_classes_unaligned():
         assert np.array_equal(got, want), ("bounded", asc)
 
 
+def test_segmented_phase_switch():
+    """Phase 15 of the big segments as one launch on 2^15-key units (the
+    default) and as a one-step pass and a merge: segments of 2^14 + 1 ..
+    2^17 + 3 keys whose last unit is full, one key long, or past the
+    segment's end (only padding), at unaligned offsets, both directions,
+    uint32 and float32 keys too."""
+    lens = np.array([(1 << 14) + 1, (1 << 15) - 1, 1 << 15, (1 << 15) + 1, (1 << 16) + 1,
+                     (3 << 14) + 5, (1 << 17) + 3, 7, 0, (1 << 16) - 1], dtype=np.int64)
+    off = W.offsets_from_lengths(lens) + 5
+    keys = W.uniform_i32(43, int(off[-1]) + 3)
+    saved = B.bitonic_get_tuning_value("phase_merge")
+    try:
+        for on in (1, 0):
+            B.bitonic_set_tuning_value("phase_merge", on)
+            for asc in (True, False):
+                print(f"[case] segmented phase_merge={on} asc={asc}", flush=True)
+                want = keys.copy()
+                want[off[0]:off[-1]] = O.sort_segmented_i32(keys[off[0]:off[-1]], off - off[0], asc)
+                assert np.array_equal(gpu_sort_segmented(keys, off, asc), want), (on, asc)
+            bits = keys.view(np.uint32).copy()
+            bits[off[3]:off[3] + len(TOTAL_ORDER_BITS)] = TOTAL_ORDER_BITS
+            for kt, nk in (("uint32", O.KEY_U32), ("float32", O.KEY_F32)):
+                t = torch.from_numpy(bits.view(np.int32).copy()).cuda()
+                o = torch.from_numpy(off).cuda()
+                B.bitonic_sort_segmented_keys(t, o, True, kt)
+                torch.cuda.synchronize()
+                want = bits.copy()
+                view = want.view(np.float32) if kt == "float32" else want
+                seg = O.sort_segmented_keys(view[off[0]:off[-1]], off - off[0], nk, True)
+                want[off[0]:off[-1]] = seg.view(np.uint32)
+                assert np.array_equal(t.cpu().numpy().view(np.uint32), want), (on, kt)
+    finally:
+        B.bitonic_set_tuning_value("phase_merge", saved)
+
+
 @pytest.mark.parametrize("seg_fuse", [1, 2, 3, 4, 5])
 def test_segmented_fuse_depths(seg_fuse):
     """Big-segment passes of 1..5 fused steps (4, 4, 4, 2 and 1 columns per

@@ -128,17 +128,17 @@ def test_tile_merge_program(emu, L):
         assert (out == np.sort(keys)).all()
 
 
-@pytest.mark.parametrize("L", [12, 13, 14, 15])
-def test_tile_phase_program(emu, L):
-    """Kind 5, all of phase L on a tile whose halves are each ascending (as
-    the tile sort of 2^(L-1)-key tiles leaves them): the mirror step and L-1
-    half-cleaners, L steps, tile sorted; for partial tiles too (absent keys
-    are the virtual sentinels)."""
+@pytest.mark.parametrize("L,kind", [(12, 5), (13, 5), (14, 5), (15, 5), (15, 7)])
+def test_tile_phase_program(emu, L, kind):
+    """Kinds 5 and 7 (vector and scalar I/O), all of phase L on a tile whose
+    halves are each ascending (as the tile sort of 2^(L-1)-key tiles leaves
+    them): the mirror step and L-1 half-cleaners, L steps, tile sorted; for
+    partial tiles too (absent keys are the virtual sentinels)."""
     T = 1 << L
     for seed in range(3):
         keys = W.uniform_i32(seed + 40, T)
         two = np.concatenate([np.sort(keys[:T // 2]), np.sort(keys[T // 2:])])
-        out, steps = _run(emu, L, 5, 5, two, T)
+        out, steps = _run(emu, L, 5, kind, two, T)
         assert steps == L
         assert (out == np.sort(keys)).all()
     for valid in (T - 1, T // 2 + 5):
@@ -146,11 +146,11 @@ def test_tile_phase_program(emu, L):
         two = keys.copy()
         two[:T // 2] = np.sort(keys[:T // 2])
         two[T // 2:valid] = np.sort(keys[T // 2:valid])
-        out, _ = _run(emu, L, 5, 5, two, valid)
+        out, _ = _run(emu, L, 5, kind, two, valid)
         assert (out[:valid] == np.sort(keys[:valid])).all()
         assert (out[valid:] == two[valid:]).all()
     # load layout, the merge layouts of phase L, store layout
-    assert emu.program_groups(L, 5, 5) == 2 + -(-L // 5)
+    assert emu.program_groups(L, 5, kind) == 2 + -(-L // 5)
 
 
 @pytest.mark.parametrize("L", [11, 12, 13, 14, 15])
@@ -213,7 +213,7 @@ def test_wide_programs(emu, L):
 # 4-byte tiles (vector I/O, and the 2^13 scalar-I/O tile), the 8-byte tiles,
 # the segmented small-segment programs and big-segment tiles.
 INSTANTIATED = sorted({(L, 5, k) for L in range(11, 16) for k in (0, 1, 4)} |
-                      {(L, 5, 5) for L in range(12, 16)} |
+                      {(L, 5, 5) for L in range(12, 16)} | {(15, 5, 7)} |
                       {(13, 5, 6), (13, 5, 3), (14, 5, 6), (14, 5, 3)} |
                       {(L, 4, k) for L in (11, 12, 13) for k in (2, 3)} |
                       {(L, 5, k) for L in range(5, 14) for k in (2, 6)} |
