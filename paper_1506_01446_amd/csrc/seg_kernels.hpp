@@ -233,9 +233,16 @@ __global__ __launch_bounds__(seg_tile_threads<ST>()) void seg_tile_kernel(
     // 4-byte keys: the next tile's keys are loaded (through a buffer
     // resource of its real keys, so slots past them read 0 and touch no
     // memory) while this tile is sorted and stored; each tile's keys are
-    // encoded, and its padding set, only when its program starts.
+    // encoded, and its padding set, only when its program starts.  The
+    // sort runs a segment's last tile, when at most half of it holds keys,
+    // with the half-size program (16 keys per thread, the same threads):
+    // about 43 % of the work; that tile's keys are not prefetched.
     constexpr Group g0 = PR::value.g[0];
     constexpr int LAST = PR::value.ngroups - 1;
+    constexpr bool HALF = KIND == 6;
+    using PH = Prog<seg_tile_log<ST>() - 1, seg_tile_reg_log<ST>() - 1, KIND>;
+    static_assert(!HALF || (PH::NT == PR::NT && PH::LDSW <= PR::LDSW), "half tile in the same workgroup");
+    auto half = [](uint32_t v) { return HALF && v <= (uint32_t)PH::T; };
     auto load_raw = [&](int32_t (&x)[PR::R], uint64_t start, uint32_t valid, uint32_t tid) {
       const __amdgpu_buffer_rsrc_t rs = tile_rsrc(keys.k + start, valid * 4u);
       const uint32_t base = deposit<free_mask(g0, PR::L)>(tid);
@@ -249,7 +256,7 @@ __global__ __launch_bounds__(seg_tile_threads<ST>()) void seg_tile_kernel(
     uint32_t valid = 0;
     locate(u, &start, &valid);
     int32_t x[PR::R];
-    load_raw(x, start, valid, threadIdx.x);
+    load_raw(x, start, half(valid) ? 0u : valid, threadIdx.x);
     for (; u < uend; ++u) {
       uint32_t tid = threadIdx.x;
       asm volatile("" : "+v"(tid));
@@ -257,16 +264,20 @@ __global__ __launch_bounds__(seg_tile_threads<ST>()) void seg_tile_kernel(
       uint32_t nvalid = 0;  // no next tile: an empty resource
       if (u + 1 < uend) locate(u + 1, &nstart, &nvalid);
       int32_t y[PR::R];
-      load_raw(y, nstart, nvalid, tid);
-      {
-        const uint32_t base = deposit<free_mask(g0, PR::L)>(tid);
-        static_for<0, PR::R>([&](auto J) {
-          const uint32_t idx = slot_index<PR, 0, J>(base);
-          x[J] = idx < valid ? cd.enc(x[J]) : kPad;
-        });
+      load_raw(y, nstart, half(nvalid) ? 0u : nvalid, tid);
+      if (half(valid)) {
+        tile_program<PH>(keys.k + start, valid, cd, lds, tid);  // loads its own keys
+      } else {
+        {
+          const uint32_t base = deposit<free_mask(g0, PR::L)>(tid);
+          static_for<0, PR::R>([&](auto J) {
+            const uint32_t idx = slot_index<PR, 0, J>(base);
+            x[J] = idx < valid ? cd.enc(x[J]) : kPad;
+          });
+        }
+        run_from<PR, 0>(x, lds, tid);  // its first regroup waits for the LDS
+        store_tile<PR, LAST>(x, keys.k + start, valid, cd, tid);
       }
-      run_from<PR, 0>(x, lds, tid);  // its first regroup waits for the LDS
-      store_tile<PR, LAST>(x, keys.k + start, valid, cd, tid);
       static_for<0, PR::R>([&](auto J) { x[J] = y[J]; });
       start = nstart;
       valid = nvalid;

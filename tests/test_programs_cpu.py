@@ -103,6 +103,21 @@ def test_tile_sort_lane_step_program(emu, L):
         2 * max(0, L - 11) + 1
 
 
+def test_half_tile_sort_program(emu):
+    """The half-size scalar-I/O sort with lane steps (2^13 keys, 16 per
+    thread, kind 6) that the big-segment tile sort runs on a segment's last
+    tile when at most half of it holds keys: sorted, full and partial, at
+    most 2-way LDS bank conflicts."""
+    T = 1 << 13
+    for valid in (T, T - 3, T // 2 + 1, 100, 1):
+        keys = W.uniform_i32(valid + 13, T)
+        out, steps = _run(emu, 13, 4, 6, keys, valid)
+        assert steps == 13 * 14 // 2
+        assert (out[:valid] == np.sort(keys[:valid])).all()
+        assert (out[valid:] == keys[valid:]).all()
+    assert emu.worst_bank_conflict_lanes(13, 4, 6, 32, 32) <= 2
+
+
 @pytest.mark.parametrize("L", [11, 13])
 def test_tile_sort_partial(emu, L):
     T = 1 << L
@@ -213,7 +228,7 @@ def test_wide_programs(emu, L):
 # 4-byte tiles (vector I/O, and the 2^13 scalar-I/O tile), the 8-byte tiles,
 # the segmented small-segment programs and big-segment tiles.
 INSTANTIATED = sorted({(L, 5, k) for L in range(11, 16) for k in (0, 1, 4)} |
-                      {(L, 5, 5) for L in range(12, 16)} | {(15, 5, 7)} |
+                      {(L, 5, 5) for L in range(12, 16)} | {(15, 5, 7), (13, 4, 6)} |
                       {(13, 5, 6), (13, 5, 3), (14, 5, 6), (14, 5, 3)} |
                       {(L, 4, k) for L in (11, 12, 13) for k in (2, 3)} |
                       {(L, 5, k) for L in range(5, 14) for k in (2, 6)} |
