@@ -535,7 +535,15 @@ static int64_t enqueue_wide(int64_t* k64, int32_t* k32, int32_t* vals, uint32_t 
   }
   emit(tile_shape(BITONIC_LAUNCH_TILE_SORT, L),
        [&] { launch_wide_tile(L, 0, k64, k32, vals, n, cd, CX_ENC, st); });
+  const bool phase = g_phase_merge.load() != 0;
   for (int p = L + 1; p <= K; ++p) {
+    if (p == L + 1 && phase) {
+      // the whole phase on 2^p-element tiles (mirror step included)
+      const int cx = p == K ? CX_DEC : CX_NONE;
+      emit(bitonic_launch_shape{BITONIC_LAUNCH_TILE_MERGE, 0, p, 1, unit, 64},
+           [&] { launch_wide_phase(p, k64, k32, vals, n, cd, cx, st); });
+      continue;
+    }
     const int nb = p - L;
     const int npass = (nb + F - 1) / F;
     int top = p - 1;

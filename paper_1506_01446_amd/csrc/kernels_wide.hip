@@ -14,7 +14,9 @@
 // elements (8-byte accesses for int64 keys, a 4-byte access into each array
 // for pairs), which needs no alignment beyond the element's own.
 //
-//  wide_tile_kernel<L, KIND, CX, ST>  tile sort (KIND 2) or merge (KIND 3)
+//  wide_tile_kernel<L, KIND, CX, ST>  tile sort (KIND 2), merge (KIND 3) or
+//                                     phase L (KIND 7: phase t+1 on tiles
+//                                     twice the sort's tile)
 //  column_pass_kernel<F, MIRROR, B, ST>  F long-stride steps, one column of
 //                                        2^F elements per thread (column_pass.hpp)
 //
@@ -103,6 +105,27 @@ static void launch_wide_tile_st(int L, int kind, ST st, uint32_t n, Codec64 cd, 
   }
 }
 
+template <int L, class ST>
+static void launch_wide_phase_L(ST st, uint32_t n, Codec64 cd, int cx, hipStream_t s) {
+  const uint32_t ntiles = (uint32_t)(((uint64_t)n + (1u << L) - 1) >> L);
+  constexpr int NT = 1 << (L - kWideRegLog);
+  if (codec_is_identity(cd)) cx = CX_NONE;
+  if (cx == CX_NONE)
+    wide_tile_kernel<L, 7, CX_NONE, ST><<<ntiles, NT, 0, s>>>(st, n, cd);
+  else
+    wide_tile_kernel<L, 7, CX_DEC, ST><<<ntiles, NT, 0, s>>>(st, n, cd);
+}
+
+template <class ST>
+static void launch_wide_phase_st(int L, ST st, uint32_t n, Codec64 cd, int cx, hipStream_t s) {
+  switch (L) {
+    case 12: launch_wide_phase_L<12>(st, n, cd, cx, s); break;
+    case 13: launch_wide_phase_L<13>(st, n, cd, cx, s); break;
+    case 14: launch_wide_phase_L<14>(st, n, cd, cx, s); break;
+    default: break;
+  }
+}
+
 template <class ST>
 static void launch_wide_pass_st(int f, bool mirror, ST st, uint32_t n, int q, hipStream_t s) {
   switch (f) {
@@ -122,6 +145,14 @@ void launch_wide_tile(int L, int kind, int64_t* keys64, int32_t* keys32, int32_t
     launch_wide_tile_st(L, kind, Pairs{keys32, values}, n, cd, cx, s);
   else
     launch_wide_tile_st(L, kind, Keys64{keys64}, n, cd, cx, s);
+}
+
+void launch_wide_phase(int L, int64_t* keys64, int32_t* keys32, int32_t* values, uint32_t n,
+                       Codec64 cd, int cx, hipStream_t s) {
+  if (values)
+    launch_wide_phase_st(L, Pairs{keys32, values}, n, cd, cx, s);
+  else
+    launch_wide_phase_st(L, Keys64{keys64}, n, cd, cx, s);
 }
 
 void launch_wide_pass(int f, bool mirror, int64_t* keys64, int32_t* keys32, int32_t* values,

@@ -77,6 +77,13 @@ constexpr int kWideFuseMax = 6;
 void launch_wide_tile(int L, int kind, int64_t* keys64, int32_t* keys32, int32_t* values,
                       uint32_t n, Codec64 cd, int cx, hipStream_t st);
 
+// Phase L (program kind 7: the mirror step, then strides 2^(L-2)..1) over
+// the 2^L-element tiles of an 8-byte sort whose halves are each ascending,
+// L = kWideTileMinLog2 + 1 .. kWideTileMaxLog2 + 1: phase t+1 after the tile
+// sort of 2^t-element tiles in one launch.  cx CX_NONE or CX_DEC.
+void launch_wide_phase(int L, int64_t* keys64, int32_t* keys32, int32_t* values, uint32_t n,
+                       Codec64 cd, int cx, hipStream_t st);
+
 // f fused steps on bits q+f-1 .. q of an 8-byte sort, on mapped elements.
 // Requires q + f <= 31, 1 <= f <= kWideFuseMax.
 void launch_wide_pass(int f, bool mirror, int64_t* keys64, int32_t* keys32, int32_t* values,

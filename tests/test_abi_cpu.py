@@ -126,7 +126,8 @@ def test_wide_pass_count(lib, t, f):
     tile sort, then per phase beyond the tile its fused passes and a merge)."""
     for k in range(1, 32):
         got = B.bitonic_wide_plan_passes(2**k, ("optimized", t, f))
-        assert got == _closed_form_optimized(k, t, f, phase=False), (k, t, f)
+        phase = B.bitonic_get_tuning_value("phase_merge") == 1
+        assert got == _closed_form_optimized(k, t, f, phase=phase), (k, t, f)
         if k >= 2:
             assert B.bitonic_wide_plan_passes(2**k - 1, ("optimized", t, f)) == got
 

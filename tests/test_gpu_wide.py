@@ -57,6 +57,38 @@ def _sort_pairs(keys, values, asc, key_type="int32", plan=None):
     return k.cpu().numpy(), v.cpu().numpy()
 
 
+@pytest.mark.parametrize("t", [11, 12, 13])
+def test_wide_phase_merge(t):
+    """Phase t + 1 as one launch on 2^(t+1)-element tiles (on, the default)
+    and as a one-step pass and a merge (off): int64 keys and pairs, the
+    phase as the last launch (n = 2^(t+1), decoding), followed by more
+    phases, ragged, both directions, float64 keys decoded by it."""
+    saved = B.bitonic_get_tuning_value("phase_merge")
+    try:
+        for on in (1, 0):
+            B.bitonic_set_tuning_value("phase_merge", on)
+            for n in (1 << (t + 1), (1 << (t + 1)) - 5, (1 << (t + 3)) + 333):
+                plan = ("optimized", t, 6)
+                keys = _i64(W.SEED_BASE + 70 * t + n, n)
+                kp = W.uniform_i32(W.SEED_BASE + 71 * t + n, n) % 97
+                vals = W.uniform_i32(W.SEED_BASE + 72 * t + n, n)
+                for asc in (True, False):
+                    print(f"[case] wide phase_merge={on} t={t} n={n} asc={asc}", flush=True)
+                    want = O.sort_keys64(keys, O.KEY_I64, asc)
+                    assert np.array_equal(_sort64(keys, asc, "int64", plan), want), (on, n, asc)
+                    wk, wv = O.sort_pairs(kp, vals, O.KEY_I32, asc)
+                    gk, gv = _sort_pairs(kp, vals, asc, "int32", plan)
+                    assert np.array_equal(gk, wk) and np.array_equal(gv, wv), (on, n, asc)
+            n = 1 << (t + 1)
+            f = W.uniform_i64(W.SEED_BASE + 73, n).view(np.float64).copy()
+            f[:4] = [np.inf, -np.inf, -0.0, 0.0]
+            want = O.sort_keys64(f, O.KEY_F64, True)
+            got = _sort64(f, True, "float64", ("optimized", t, 6))
+            assert np.array_equal(got.view(np.uint64), np.asarray(want).view(np.uint64)), on
+    finally:
+        B.bitonic_set_tuning_value("phase_merge", saved)
+
+
 @pytest.mark.parametrize("plan", PLANS, ids=lambda p: "default" if p is None else
                          "-".join(map(str, p)))
 def test_int64_sizes_and_plans(plan):

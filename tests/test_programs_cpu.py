@@ -143,9 +143,11 @@ def test_tile_merge_program(emu, L):
         assert (out == np.sort(keys)).all()
 
 
-@pytest.mark.parametrize("L,kind", [(12, 5), (13, 5), (14, 5), (15, 5), (15, 7)])
-def test_tile_phase_program(emu, L, kind):
-    """Kinds 5 and 7 (vector and scalar I/O), all of phase L on a tile whose
+@pytest.mark.parametrize("L,r,kind", [(12, 5, 5), (13, 5, 5), (14, 5, 5), (15, 5, 5), (15, 5, 7),
+                                      (12, 4, 7), (13, 4, 7), (14, 4, 7)])
+def test_tile_phase_program(emu, L, r, kind):
+    """Kinds 5 and 7 (vector and scalar I/O; 4-byte keys at r = 5, 8-byte
+    elements at r = 4), all of phase L on a tile whose
     halves are each ascending (as the tile sort of 2^(L-1)-key tiles leaves
     them): the mirror step and L-1 half-cleaners, L steps, tile sorted; for
     partial tiles too (absent keys are the virtual sentinels)."""
@@ -153,7 +155,7 @@ def test_tile_phase_program(emu, L, kind):
     for seed in range(3):
         keys = W.uniform_i32(seed + 40, T)
         two = np.concatenate([np.sort(keys[:T // 2]), np.sort(keys[T // 2:])])
-        out, steps = _run(emu, L, 5, kind, two, T)
+        out, steps = _run(emu, L, r, kind, two, T)
         assert steps == L
         assert (out == np.sort(keys)).all()
     for valid in (T - 1, T // 2 + 5):
@@ -161,11 +163,11 @@ def test_tile_phase_program(emu, L, kind):
         two = keys.copy()
         two[:T // 2] = np.sort(keys[:T // 2])
         two[T // 2:valid] = np.sort(keys[T // 2:valid])
-        out, _ = _run(emu, L, 5, kind, two, valid)
+        out, _ = _run(emu, L, r, kind, two, valid)
         assert (out[:valid] == np.sort(keys[:valid])).all()
         assert (out[valid:] == two[valid:]).all()
     # load layout, the merge layouts of phase L, store layout
-    assert emu.program_groups(L, 5, kind) == 2 + -(-L // 5)
+    assert emu.program_groups(L, r, kind) == 2 + -(-L // r)
 
 
 @pytest.mark.parametrize("L", [11, 12, 13, 14, 15])
@@ -229,6 +231,7 @@ def test_wide_programs(emu, L):
 # the segmented small-segment programs and big-segment tiles.
 INSTANTIATED = sorted({(L, 5, k) for L in range(11, 16) for k in (0, 1, 4)} |
                       {(L, 5, 5) for L in range(12, 16)} | {(15, 5, 7), (13, 4, 6)} |
+                      {(L, 4, 7) for L in (12, 13, 14)} |
                       {(13, 5, 6), (13, 5, 3), (14, 5, 6), (14, 5, 3)} |
                       {(L, 4, k) for L in (11, 12, 13) for k in (2, 3)} |
                       {(L, 5, k) for L in range(5, 14) for k in (2, 6)} |
