@@ -433,12 +433,14 @@ static int64_t enqueue_segmented(const SegData& d, const int64_t* offsets, int64
   emit({BITONIC_LAUNCH_TILE_SORT, 0, T, 0, unit, 64},
        [&] { launch_seg_tiles(false, d, offsets, sc, kSegSmallMaxLog2 + 1, grid, st); });
   const int fuse = g_seg_fuse.load();
-  const bool phase = g_phase_merge.load() != 0 && seg_phase_supported(d) && T == kSegTileLog32;
+  const bool phase = g_phase_merge.load() != 0;
   for (int p = T + 1; p <= M; ++p) {
     if (p == T + 1 && phase) {
       // the whole phase on units of 2^p keys (mirror step included)
+      // one workgroup per CU for 4-byte keys (135 KiB of LDS), two for 8-byte
+      // elements (68 KiB)
       emit({BITONIC_LAUNCH_TILE_MERGE, 0, p, 1, unit, 64},
-           [&] { launch_seg_phase(d, offsets, sc, cus, st); });
+           [&] { launch_seg_phase(d, offsets, sc, T == kSegTileLog32 ? cus : 2 * cus, st); });
       continue;
     }
     const int nb = p - T;

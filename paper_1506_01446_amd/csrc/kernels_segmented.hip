@@ -239,7 +239,6 @@ void launch_seg_phase(const SegData& d, const int64_t* offsets, const SegScratch
                       hipStream_t st) {
   SegLaunch l{};
   l.what = SegLaunch::kPhase;
-  l.cls = kSegTileLog32 + 1;
   l.grid = grid;
   seg_dispatch(d, l, offsets, sc, st);
 }

@@ -296,36 +296,46 @@ __global__ __launch_bounds__(seg_tile_threads<ST>()) void seg_tile_kernel(
   }
 }
 
-// Phase kSegTileLog32 + 1 of the big segments of that class and above
-// (4-byte keys): the mirror step and the half-cleaners on units of
-// 2^(kSegTileLog32 + 1) keys, whose two halves the tile sort left ascending
+// Phase T + 1 of the big segments of that class and above (T the big
+// segments' tile, seg_tile_log): the mirror step and the half-cleaners on
+// units of 2^(T+1) elements, whose two halves the tile sort left ascending
 // (program kind 7, scalar I/O).  Units run over the segments' padded sizes
 // (big_keys), so a unit wholly in a segment's virtual padding has no work
-// and is skipped; one workgroup per CU (135 KiB of LDS), each taking a
-// contiguous range of units, with the next unit's keys loaded (through a
-// buffer resource of its real keys) while this one is processed.
-constexpr int kSegPhaseLog = kSegTileLog32 + 1;
-constexpr int kSegPhaseThreads = 1 << (kSegPhaseLog - kTileRegLogSeg);
+// and is skipped; each workgroup takes a contiguous range of units (one per
+// CU for 4-byte keys, 135 KiB of LDS; two for 8-byte elements, whose
+// regroups go through 4-byte words).  For 4-byte keys the next unit's keys
+// are loaded (through a buffer resource of its real keys) while this one is
+// processed.
+template <class ST>
+constexpr int seg_phase_log() {
+  return seg_tile_log<ST>() + 1;
+}
+template <class ST>
+constexpr int seg_phase_threads() {
+  return 1 << (seg_phase_log<ST>() - seg_tile_reg_log<ST>());
+}
 
-template <class CD>
-__global__ __launch_bounds__(kSegPhaseThreads) void seg_phase_kernel(
-    Keys32 keys, const int64_t* __restrict__ offsets, const SegMeta* __restrict__ meta,
+template <class ST, class CD>
+__global__ __launch_bounds__(seg_phase_threads<ST>()) void seg_phase_kernel(
+    ST keys, const int64_t* __restrict__ offsets, const SegMeta* __restrict__ meta,
     const uint32_t* __restrict__ big_ids, const uint64_t* __restrict__ big_keys, CD cd) {
-  using PR = Prog<kSegPhaseLog, kTileRegLogSeg, 7>;
-  static_assert(PR::NT == kSegPhaseThreads, "one unit per workgroup");
-  __shared__ int32_t lds[PR::LDSW];
+  constexpr int kSegPhaseLog = seg_phase_log<ST>();
+  using PR = Prog<kSegPhaseLog, seg_tile_reg_log<ST>(), 7>;
+  static_assert(PR::NT == seg_phase_threads<ST>(), "one unit per workgroup");
+  constexpr bool SPLIT = sizeof(typename ST::E) == 8;
+  __shared__ uint32_t lds32[PR::LDSW];
   constexpr Group g0 = PR::value.g[0];
   constexpr int LAST = PR::value.ngroups - 1;
   const uint32_t cnt = meta->big_ge[kSegPhaseLog];
   uint64_t u, uend;
   unit_range(big_keys[cnt] >> kSegPhaseLog, &u, &uend);
   uint32_t i = u < uend ? upper_index(big_keys, cnt, u << kSegPhaseLog) : 0u;
-  // unit uu's first key and real key count; false for a unit of padding only
-  // (the same answer for the whole workgroup)
+  // unit uu's first element and real element count; false for a unit of
+  // padding only (the same answer for the whole workgroup)
   auto locate = [&](uint64_t uu, uint64_t* start, uint32_t* valid) -> bool {
     const uint64_t key0 = uu << kSegPhaseLog;
     i = advance_index(big_keys, cnt, i, key0);
-    const uint64_t lk = key0 - big_keys[i];  // unit's first key, segment-local
+    const uint64_t lk = key0 - big_keys[i];  // unit's first element, segment-local
     const uint32_t s = big_ids[i];
     const int64_t off = offsets[s];
     const uint64_t len = (uint64_t)(offsets[s + 1] - off);
@@ -335,42 +345,54 @@ __global__ __launch_bounds__(kSegPhaseThreads) void seg_phase_kernel(
     *valid = left < (uint64_t)PR::T ? (uint32_t)left : (uint32_t)PR::T;
     return true;
   };
-  auto load_raw = [&](int32_t (&x)[PR::R], uint64_t start, uint32_t valid, uint32_t tid) {
-    const __amdgpu_buffer_rsrc_t rs = tile_rsrc(keys.k + start, valid * 4u);
-    const uint32_t base = deposit<free_mask(g0, PR::L)>(tid);
-    static_for<0, PR::R>([&](auto J) {
-      const uint32_t idx = slot_index<PR, 0, J>(base);
-      x[J] = (int32_t)__builtin_amdgcn_raw_buffer_load_b32(rs, idx * 4u, 0, 0);
-    });
-  };
   uint64_t start = 0;
   uint32_t valid = 0;
-  while (u < uend && !locate(u, &start, &valid)) ++u;
-  if (u >= uend) return;
-  int32_t x[PR::R];
-  load_raw(x, start, valid, threadIdx.x);
-  while (u < uend) {
-    uint32_t tid = threadIdx.x;
-    asm volatile("" : "+v"(tid));
-    uint64_t nu = u + 1;
-    uint64_t nstart = start;
-    uint32_t nvalid = 0;  // no next unit: an empty resource
-    while (nu < uend && !locate(nu, &nstart, &nvalid)) ++nu;
-    int32_t y[PR::R];
-    load_raw(y, nstart, nvalid, tid);
-    {
+  if constexpr (SPLIT) {
+    for (; u < uend; ++u) {
+      if (!locate(u, &start, &valid)) continue;
+      uint32_t tid = threadIdx.x;
+      asm volatile("" : "+v"(tid));
+      seg_tile_program<PR, true>(keys.at(start), valid, cd,
+                                 reinterpret_cast<typename ST::E*>(lds32), tid);
+      __syncthreads();  // LDS reuse by the next unit
+    }
+  } else {
+    int32_t* lds = reinterpret_cast<int32_t*>(lds32);
+    auto load_raw = [&](int32_t (&x)[PR::R], uint64_t st0, uint32_t v, uint32_t tid) {
+      const __amdgpu_buffer_rsrc_t rs = tile_rsrc(keys.k + st0, v * 4u);
       const uint32_t base = deposit<free_mask(g0, PR::L)>(tid);
       static_for<0, PR::R>([&](auto J) {
         const uint32_t idx = slot_index<PR, 0, J>(base);
-        x[J] = idx < valid ? cd.enc(x[J]) : kPad;
+        x[J] = (int32_t)__builtin_amdgcn_raw_buffer_load_b32(rs, idx * 4u, 0, 0);
       });
+    };
+    while (u < uend && !locate(u, &start, &valid)) ++u;
+    if (u >= uend) return;
+    int32_t x[PR::R];
+    load_raw(x, start, valid, threadIdx.x);
+    while (u < uend) {
+      uint32_t tid = threadIdx.x;
+      asm volatile("" : "+v"(tid));
+      uint64_t nu = u + 1;
+      uint64_t nstart = start;
+      uint32_t nvalid = 0;  // no next unit: an empty resource
+      while (nu < uend && !locate(nu, &nstart, &nvalid)) ++nu;
+      int32_t y[PR::R];
+      load_raw(y, nstart, nvalid, tid);
+      {
+        const uint32_t base = deposit<free_mask(g0, PR::L)>(tid);
+        static_for<0, PR::R>([&](auto J) {
+          const uint32_t idx = slot_index<PR, 0, J>(base);
+          x[J] = idx < valid ? cd.enc(x[J]) : kPad;
+        });
+      }
+      run_from<PR, 0>(x, lds, tid);  // its first regroup waits for the LDS
+      store_tile<PR, LAST>(x, keys.k + start, valid, cd, tid);
+      static_for<0, PR::R>([&](auto J) { x[J] = y[J]; });
+      start = nstart;
+      valid = nvalid;
+      u = nu;
     }
-    run_from<PR, 0>(x, lds, tid);  // its first regroup waits for the LDS
-    store_tile<PR, LAST>(x, keys.k + start, valid, cd, tid);
-    static_for<0, PR::R>([&](auto J) { x[J] = y[J]; });
-    start = nstart;
-    valid = nvalid;
-    u = nu;
   }
 }
 
@@ -463,9 +485,8 @@ void seg_run(ST keys, CD cd, const SegLaunch& l, const int64_t* offsets, const S
           keys, offsets, sc.meta, sc.big_ids, sc.big_tiles, l.cls, cd);
       break;
     case SegLaunch::kPhase:
-      if constexpr (std::is_same_v<ST, Keys32>)
-        seg_phase_kernel<<<l.grid, kSegPhaseThreads, 0, st>>>(keys, offsets, sc.meta, sc.big_ids,
-                                                              sc.big_keys, cd);
+      seg_phase_kernel<<<l.grid, seg_phase_threads<ST>(), 0, st>>>(keys, offsets, sc.meta,
+                                                                   sc.big_ids, sc.big_keys, cd);
       break;
     case SegLaunch::kPass: {
 #define BITONIC_SEG_PASS(F)                                                                     \

@@ -138,10 +138,9 @@ void launch_seg_tiles(bool merge, const SegData& d, const int64_t* offsets, cons
 // f fused steps on bits q+f-1 .. q of the big segments of class >= cls.
 void launch_seg_pass(int f, bool mirror, const SegData& d, const int64_t* offsets,
                      const SegScratch& sc, int cls, int q, int grid, hipStream_t st);
-// Phase kSegTileLog32 + 1 of the big segments of that class or above, 4-byte
-// keys only (seg_phase_supported): one launch instead of a one-step pass and
-// a tile merge.
-constexpr bool seg_phase_supported(const SegData& d) { return !d.keys64 && !d.values; }
+// Phase T + 1 of the big segments of that class or above (T the big
+// segments' tile log2): one launch instead of a one-step pass and a tile
+// merge.
 void launch_seg_phase(const SegData& d, const int64_t* offsets, const SegScratch& sc, int grid,
                       hipStream_t st);
 

@@ -294,10 +294,10 @@ def test_plan_shapes_segmented(lib, layout, unit):
     """The segmented planner, for a longest segment of 1..2^31 elements:
     prep, the small-segment kernel, and for segments past 2^13 elements the
     tile sort and per phase its passes (at most "seg_fuse" steps each) and
-    merge; for 4-byte keys phase 15 in one launch (a tile merge with the
-    mirror step, on 2^15-key units), with "phase_merge" on."""
+    merge; phase T + 1 in one launch (a tile merge with the mirror step, on
+    2^(T+1)-element units), with "phase_merge" on."""
     T = 14 if layout == "seg_keys32" else 13   # big-segment tile: 2^14 keys, 2^13 8-byte elements
-    phase = layout == "seg_keys32" and B.bitonic_get_tuning_value("phase_merge") == 1
+    phase = B.bitonic_get_tuning_value("phase_merge") == 1
     for k in range(0, 32):
         n = 2**k
         sh = B.bitonic_plan_shapes(n, layout)

@@ -335,6 +335,40 @@ def test_segmented_pairs_edge_lengths():
             assert np.array_equal(gk, wk) and np.array_equal(gv, wv), (asc, bound)
 
 
+def test_segmented_8_byte_phase_switch():
+    """Phase 14 of big 8-byte segments as one launch on 2^14-element units
+    (on, the default) and as a one-step pass and a merge (off): pairs and
+    int64 keys, segments whose last unit is full, one element long or only
+    padding, at an unaligned start, both directions."""
+    lens = [(1 << 13) + 1, (1 << 14) - 1, 1 << 14, (1 << 14) + 1, (1 << 15) + 1, (3 << 13) + 5,
+            (1 << 16) + 3, 9, 0]
+    off = np.concatenate([[5], 5 + np.cumsum(lens)]).astype(np.int64)
+    n = int(off[-1]) + 3
+    keys = (W.uniform_i32(W.SEED_BASE + 150, n).astype(np.int64) % 501 - 250).astype(np.int32)
+    values = W.uniform_i32(W.SEED_BASE + 151, n)
+    k64 = _i64(W.SEED_BASE + 152, n)
+    saved = B.bitonic_get_tuning_value("phase_merge")
+    try:
+        for on in (1, 0):
+            B.bitonic_set_tuning_value("phase_merge", on)
+            for asc in (True, False):
+                print(f"[case] segmented 8-byte phase_merge={on} asc={asc}", flush=True)
+                gk, gv = _seg_pairs_gpu(keys, values, off, asc)
+                wk, wv = _seg_pairs_oracle(keys, values, off, asc)
+                assert np.array_equal(gk, wk) and np.array_equal(gv, wv), (on, asc)
+                t = torch.from_numpy(k64.copy()).cuda()
+                o = torch.from_numpy(off).cuda()
+                B.bitonic_sort_segmented_keys(t, o, asc, "int64")
+                torch.cuda.synchronize()
+                want = k64.copy()
+                for a, b in zip(off[:-1], off[1:]):
+                    if b > a:
+                        want[a:b] = O.sort_keys64(k64[a:b], O.KEY_I64, asc)
+                assert np.array_equal(t.cpu().numpy(), want), (on, asc)
+    finally:
+        B.bitonic_set_tuning_value("phase_merge", saved)
+
+
 @pytest.mark.parametrize("seg_fuse", [3, 4, 5])
 def test_segmented_8_byte_fuse_depths(seg_fuse):
     """Big-segment passes of 3..5 fused steps on 8-byte elements (pairs and
