@@ -296,9 +296,11 @@ typedef struct bitonic_plan {
  * F64) sorts keys (bitonic_sort_keys64; values must be NULL), a 4-byte one
  * sorts pairs (bitonic_sort_pairs).  The plan's kind
  * must be BITONIC_PLAN_AUTO or BITONIC_PLAN_OPTIMIZED, its tile_log2 11..13
- * (elements per tile), its fuse 1..6; merge_blocks_per_cu is ignored (one
- * tile per workgroup).  Library choices (0): tile_log2 13, fuse 6 (tuning
- * values "wide_tile_log2" and "wide_fuse").
+ * (elements per tile), its fuse 1..8 (7 and 8 split each column over two
+ * or four lanes, for n a power of two and phases up to 29; otherwise at
+ * most 6 are used); merge_blocks_per_cu is ignored (one tile per
+ * workgroup).  Library choices (0): tile_log2 13, fuse 8 (tuning values
+ * "wide_tile_log2" and "wide_fuse").
  */
 int bitonic_sort_wide_plan(void* keys, int32_t* values, int64_t n, int key_type, int ascending,
                            const bitonic_plan* plan, void* stream);
@@ -455,7 +457,7 @@ int bitonic_sort_plan_launches_i32(int32_t* keys, int64_t n, int ascending,
  * 8: only nine and ten steps as lane passes, 2^8 keys per lane; 0: no lane
  * passes, so at most eight steps per pass),
  * "wide_tile_log2" (11..13) or
- * "wide_fuse" (1..6) (the 8-byte sorts' plan); bitonic_get_tuning_value
+ * "wide_fuse" (1..8) (the 8-byte sorts' plan); bitonic_get_tuning_value
  * reads one.
  * Size buckets: "tile_log2@k", "fuse@k" and "merge_blocks_per_cu@k" (k =
  * ceil(log2 n), 0..31) set the 4-byte sort's plan for that size only (0

@@ -193,7 +193,7 @@ def tune(buckets=(16, 18, 20, 22, 24, 26, 28), reps: int = 5, quick: bool = Fals
     k64 = torch.from_numpy(W.uniform_i64(W.SEED_BASE + 2, n)).cuda()
     buf = torch.empty_like(k64)
     wide = []
-    for t, f in itertools.product((13,) if quick else (11, 12, 13), (6,) if quick else (4, 5, 6)):
+    for t, f in itertools.product((13,) if quick else (11, 12, 13), (8,) if quick else (5, 6, 7, 8)):
         plan = ("optimized", t, f)
         ms = _median_ms(torch, lambda: buf.copy_(k64),
                         lambda: B.bitonic_sort_wide_plan(buf, None, True, "int64", plan), reps)

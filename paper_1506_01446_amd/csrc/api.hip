@@ -34,7 +34,7 @@ static std::atomic<int> g_tile_log2{0};  // 0: by n (default_tile_log2)
 static std::atomic<int> g_fuse{10};
 static std::atomic<int> g_merge_bpc{2};  // 0: one tile per workgroup
 static std::atomic<int> g_wide_tile_log2{13};  // 8-byte sorts
-static std::atomic<int> g_wide_fuse{6};
+static std::atomic<int> g_wide_fuse{8};
 static std::atomic<int> g_seg_bpc{4};    // small-segment workgroups per compute unit
 static std::atomic<int> g_seg_pass_bpc{8};  // big-segment pass workgroups per compute unit
 static std::atomic<int> g_seg_fuse{kSegFuseMax};  // steps per big-segment pass
@@ -546,13 +546,16 @@ static int64_t enqueue_wide(int64_t* k64, int32_t* k32, int32_t* vals, uint32_t 
            [&] { launch_wide_phase(p, k64, k32, vals, n, cd, cx, st); });
       continue;
     }
+    // more than kWideFuseMaxColumn steps split columns over lanes: whole
+    // blocks (n a power of two) and phases up to 29 (wide_lanes_fit)
+    const int Fp = (F > kWideFuseMaxColumn && ((n & (n - 1)) != 0 || p > 29)) ? kWideFuseMaxColumn : F;
     const int nb = p - L;
-    const int npass = (nb + F - 1) / F;
+    const int npass = (nb + Fp - 1) / Fp;
     int top = p - 1;
     for (int i = 0; i < npass; ++i) {  // widest pass first, as for 4-byte keys
       const int left = top - L + 1;
       const int passes_left = npass - i;
-      const int f = F < left - (passes_left - 1) ? F : left - (passes_left - 1);
+      const int f = Fp < left - (passes_left - 1) ? Fp : left - (passes_left - 1);
       const int q = top - f + 1;
       const bitonic_launch_shape sh{BITONIC_LAUNCH_GLOBAL_PASS, f, q, i == 0 ? 1 : 0, unit,
                                     column_pass_offset_bits((uint32_t)unit, f, q)};

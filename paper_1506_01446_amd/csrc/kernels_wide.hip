@@ -19,6 +19,9 @@
 //                                     twice the sort's tile)
 //  column_pass_kernel<F, MIRROR, B, ST>  F long-stride steps, one column of
 //                                        2^F elements per thread (column_pass.hpp)
+//  wide_lanes_pass_kernel<FR, G, MIRROR, ST>  F = FR + G = 7, 8 steps, each
+//                                        column split over 2^G lanes (as
+//                                        column_lanes_pass_kernel)
 //
 // ST is the storage: Keys64 (one array of 8-byte keys) or Pairs (an array of
 // 4-byte keys and an array of int32 values).  Indices >= n are absent
@@ -70,6 +73,76 @@ __global__ __launch_bounds__(1 << (L - kWideRegLog)) void wide_tile_kernel(ST st
       });
     }
   }
+}
+
+// An 8-byte element's value in lane (this lane XOR M): both words moved.
+template <uint32_t M>
+__device__ __forceinline__ int64_t lane_xor64(int64_t v) {
+  const uint64_t u = (uint64_t)v;
+  const uint32_t lo = (uint32_t)lane_xor<M>((int32_t)(uint32_t)u);
+  const uint32_t hi = (uint32_t)lane_xor<M>((int32_t)(uint32_t)(u >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// The element a lane keeps from the pair (a, b): the larger where `upper`.
+__device__ __forceinline__ int64_t keep_of_pair64(int64_t a, int64_t b, bool upper) {
+  return (a < b) == upper ? b : a;
+}
+
+// F = FR + G long-stride steps of an 8-byte sort with every column of a
+// 2^(q+F) block split over 2^G neighbouring lanes of 2^FR elements (the
+// layout of column_lanes_pass_kernel: lane s holds rows s 2^FR .. of column
+// c, or with MIRROR in the upper half of the lanes the mirrored rows of the
+// mirrored column, ascending).  Whole blocks only, lane byte offsets below
+// 2^(q+F) kUnit <= 2^32 (wide_lanes_fit).
+template <int FR, int G, bool MIRROR, class ST>
+__global__ __launch_bounds__(256) void wide_lanes_pass_kernel(ST st, int q) {
+  constexpr int F = FR + G;
+  constexpr int M = 1 << FR;
+  constexpr uint32_t SUBS = 1u << G;
+  constexpr uint32_t HALF = SUBS >> 1;
+  static_assert(G >= 1 && G <= 2, "one or two lane bits per column");
+  int64_t x[M];
+  const uint32_t gw = blockIdx.x * 256u;                        // uniform
+  const uint32_t bs = (gw >> (q + G)) << (q + F);               // uniform block start
+  const uint32_t t = (gw + threadIdx.x) & ((1u << (q + G)) - 1u);
+  const uint32_t s = t & (SUBS - 1u);
+  const uint32_t col = t >> G;
+  const bool upper = MIRROR && s >= HALF;
+  const uint32_t colx = upper ? ((1u << q) - 1u) - col : col;
+  const uint32_t row0 = upper ? (1u << F) - (s - HALF + 1u) * (uint32_t)M : s * (uint32_t)M;
+  const uint32_t off = ((row0 << q) + colx) * ST::kUnit;       // lane byte offset
+  static_for<0, M>([&](auto J) {
+    const uint32_t r0 = bs + ((uint32_t)J << q);                // uniform row start
+    x[J] = st.at(r0).getb(off);
+  });
+  __builtin_amdgcn_sched_barrier(0);
+  if constexpr (MIRROR) {
+    static_for<0, M / 2>([&](auto J) {
+      constexpr int j = J;
+      constexpr int jj = M - 1 - j;
+      const int64_t pa = lane_xor64<HALF>(x[jj]);
+      const int64_t pb = lane_xor64<HALF>(x[j]);
+      x[j] = keep_of_pair64(x[j], pa, upper);
+      x[jj] = keep_of_pair64(x[jj], pb, upper);
+    });
+  }
+  constexpr int NL = MIRROR ? G - 1 : G;
+  static_for<0, NL>([&](auto I) {
+    constexpr int b = NL - 1 - I;
+    const bool bit = ((s >> b) & 1u) != 0;
+    const bool keep_max = upper ? !bit : bit;
+    static_for<0, M>([&](auto J) {
+      x[J] = keep_of_pair64(x[J], lane_xor64<(1u << b)>(x[J]), keep_max);
+    });
+  });
+  pass_steps<FR, false, 1>(x);
+  __builtin_amdgcn_sched_barrier(0);
+  static_for<0, M>([&](auto J) {
+    const uint32_t r0 = bs + ((uint32_t)J << q);
+    st.at(r0).putb(off, x[J]);
+    __builtin_amdgcn_sched_barrier(0);
+  });
 }
 
 // ---------------------------------------------------------------------------
@@ -126,8 +199,23 @@ static void launch_wide_phase_st(int L, ST st, uint32_t n, Codec64 cd, int cx, h
   }
 }
 
+template <int G, class ST>
+static void launch_wide_lanes_G(bool mirror, ST st, uint32_t n, int q, hipStream_t s) {
+  constexpr int FR = kWideLaneRegLog;
+  const uint32_t blocks = n >> (FR + 8);  // n / 2^FR threads, 256 per workgroup
+  if (mirror)
+    wide_lanes_pass_kernel<FR, G, true, ST><<<blocks, 256, 0, s>>>(st, q);
+  else
+    wide_lanes_pass_kernel<FR, G, false, ST><<<blocks, 256, 0, s>>>(st, q);
+}
+
 template <class ST>
 static void launch_wide_pass_st(int f, bool mirror, ST st, uint32_t n, int q, hipStream_t s) {
+  if (f > kWideFuseMaxColumn) {  // the planner checked wide_lanes_fit
+    if (f == kWideLaneRegLog + 1) launch_wide_lanes_G<1>(mirror, st, n, q, s);
+    if (f == kWideLaneRegLog + 2) launch_wide_lanes_G<2>(mirror, st, n, q, s);
+    return;
+  }
   switch (f) {
     case 1: launch_column_pass_F<1>(mirror, st, n, q, s); break;
     case 2: launch_column_pass_F<2>(mirror, st, n, q, s); break;

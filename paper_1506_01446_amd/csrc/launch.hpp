@@ -69,7 +69,15 @@ void launch_step(int sb, bool mirror, int32_t* keys, uint32_t n, uint32_t N, Cod
 constexpr int kWideRegLog = 4;
 constexpr int kWideTileMinLog2 = 11;
 constexpr int kWideTileMaxLog2 = 13;
-constexpr int kWideFuseMax = 6;
+constexpr int kWideFuseMaxColumn = 6;  // steps one thread's registers hold
+constexpr int kWideFuseMax = 8;        // with a column split over lanes (lane passes)
+constexpr int kWideLaneRegLog = 6;     // elements per lane of a lane pass, log2
+
+// Lane passes of an 8-byte sort (f = 7, 8): whole 2^(q+f) blocks, and lane
+// byte offsets below 2^32 for 8-byte units (so for either storage).
+constexpr bool wide_lanes_fit(uint32_t n, int q, int f) {
+  return q + f <= 29 && q >= 8 && n != 0 && (n & ((uint32_t(1) << (q + f)) - 1u)) == 0;
+}
 
 // Tile sort (kind 0) or merge (kind 1) over the 2^L-element tiles of an
 // 8-byte sort: int64 keys at keys64 (values == nullptr), or pairs of 4-byte
@@ -85,7 +93,8 @@ void launch_wide_phase(int L, int64_t* keys64, int32_t* keys32, int32_t* values,
                        Codec64 cd, int cx, hipStream_t st);
 
 // f fused steps on bits q+f-1 .. q of an 8-byte sort, on mapped elements.
-// Requires q + f <= 31, 1 <= f <= kWideFuseMax.
+// Requires q + f <= 31, 1 <= f <= kWideFuseMax, and wide_lanes_fit for
+// f > kWideFuseMaxColumn.
 void launch_wide_pass(int f, bool mirror, int64_t* keys64, int32_t* keys32, int32_t* values,
                       uint32_t n, int q, hipStream_t st);
 

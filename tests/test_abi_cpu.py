@@ -77,7 +77,7 @@ def test_wide_argument_errors_are_synchronous(lib):
     assert lib.bitonic_sort_pairs(4, 6, 8, I32, 1, None) == -1        # values misaligned
     assert lib.bitonic_sort_pairs(2, 8, 8, I32, 1, None) == -1        # keys misaligned
     for bad in (B.bitonic_plan(1, 0, 0, 0), B.bitonic_plan(3, 14, 0, 0),
-                B.bitonic_plan(3, 10, 0, 0), B.bitonic_plan(3, 12, 7, 0)):
+                B.bitonic_plan(3, 10, 0, 0), B.bitonic_plan(3, 12, 9, 0)):
         assert lib.bitonic_sort_wide_plan(None, None, 0, I64, 1, ctypes.byref(bad), None) == -1
         assert lib.bitonic_wide_plan_passes(2**20, ctypes.byref(bad)) == -1
     assert lib.bitonic_sort_segmented_pairs(None, None, None, 0, 0, I32, 1, None) == 0
@@ -119,17 +119,30 @@ def test_optimized_pass_count(lib, t, f):
                 _closed_form_optimized(k, t, min(f, 7)), (k, t, f)
 
 
+def _closed_form_wide(k, t, f, phase, pow2=True):
+    """Launches of an 8-byte sort on n = 2^k (or a ragged n of that padded
+    size): as the 4-byte plan, with passes of more than six steps (lane
+    passes) only for powers of two and up to phase 29."""
+    if k <= 1:
+        return k
+    if k <= t:
+        return 1
+    return 1 + sum(-(-(p - t) // (f if f <= 6 or (pow2 and p <= 29) else 6)) + 1
+                   for p in range(t + 1, k + 1)) - (1 if phase else 0)
+
+
 @pytest.mark.parametrize("t", [11, 12, 13])
-@pytest.mark.parametrize("f", [1, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("f", [1, 2, 3, 4, 5, 6, 7, 8])
 def test_wide_pass_count(lib, t, f):
     """The 8-byte sorts run the optimized plan's schedule (section 4: one
     tile sort, then per phase beyond the tile its fused passes and a merge)."""
+    phase = B.bitonic_get_tuning_value("phase_merge") == 1
     for k in range(1, 32):
         got = B.bitonic_wide_plan_passes(2**k, ("optimized", t, f))
-        phase = B.bitonic_get_tuning_value("phase_merge") == 1
-        assert got == _closed_form_optimized(k, t, f, phase=phase), (k, t, f)
+        assert got == _closed_form_wide(k, t, f, phase), (k, t, f)
         if k >= 2:
-            assert B.bitonic_wide_plan_passes(2**k - 1, ("optimized", t, f)) == got
+            assert B.bitonic_wide_plan_passes(2**k - 1, ("optimized", t, f)) == \
+                _closed_form_wide(k, t, f, phase, pow2=False), (k, t, f)
 
 
 def test_basic_plan_is_one_launch_per_round(lib):
@@ -237,7 +250,7 @@ SHAPE_SIZES = sorted({2**k for k in range(1, 32)} | {2**k - 1 for k in range(2, 
                      | {2**30 + 2**20})
 
 
-def _check_shapes(shapes, n, elem_bytes):
+def _check_shapes(shapes, n, elem_bytes, wide=False):
     k = _ceil_log2(n)
     for s in shapes:
         assert s["elem_bytes"] == elem_bytes
@@ -246,6 +259,9 @@ def _check_shapes(shapes, n, elem_bytes):
         assert (1 << s["q"]) * s["elem_bytes"] <= 2 ** s["offset_bits"], (n, s)
         if s["kind"] in ("global_pass", "step"):
             assert 1 <= s["fuse"] and s["q"] + s["fuse"] <= k <= 31, (n, s)
+        if wide and s["kind"] == "global_pass" and s["fuse"] > 6:
+            # an 8-byte lane pass: whole blocks, lane offsets of 8-byte units
+            assert n == 1 << k and (1 << (s["q"] + s["fuse"])) * 8 <= 2 ** 32, (n, s)
         if s["kind"] == "global_pass" and s["fuse"] > 8:
             # a lane pass: whole blocks, its lane byte offsets span the block
             assert elem_bytes == 4 and n == 1 << k, (n, s)
@@ -269,18 +285,18 @@ def test_plan_shapes_4byte(lib, layout):
 
 @pytest.mark.parametrize("layout,unit", [("keys64", 8), ("pairs", 4)])
 def test_plan_shapes_8byte(lib, layout, unit):
-    """The 8-byte planner under every accepted plan (tiles 2^11..2^13, 1..6
-    fused steps) for n <= 2^31: every pass keeps its byte offsets within
-    their width.  One-step passes of phase 31 over 8-byte keys span 2^33
-    bytes per row, so they must take 64-bit offsets."""
+    """The 8-byte planner under every accepted plan (tiles 2^11..2^13, 1..8
+    fused steps, 7 and 8 as lane passes) for n <= 2^31: every pass keeps its
+    byte offsets within their width.  One-step passes of phase 31 over
+    8-byte keys span 2^33 bytes per row, so they must take 64-bit offsets."""
     wide_q30 = 0
     for t in (11, 12, 13):
-        for f in range(1, 7):
+        for f in range(1, 9):
             plan = ("optimized", t, f)
             for n in SHAPE_SIZES:
                 sh = B.bitonic_plan_shapes(n, layout, plan)
                 assert len(sh) == B.bitonic_wide_plan_passes(n, plan), (plan, n)
-                _check_shapes(sh, n, unit)
+                _check_shapes(sh, n, unit, wide=True)
                 wide_q30 += sum(1 for s in sh if s["kind"] == "global_pass" and s["q"] == 30)
     assert wide_q30 > 0   # the case that needs 64-bit offsets is reached
     sh = B.bitonic_plan_shapes(2**30 + 2**20, layout, ("optimized", 13, 1))

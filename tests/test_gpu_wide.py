@@ -58,6 +58,34 @@ def _sort_pairs(keys, values, asc, key_type="int32", plan=None):
 
 
 @pytest.mark.parametrize("t", [11, 12, 13])
+def test_wide_lane_passes(t):
+    """Passes of seven and eight steps with each column split over two or
+    four lanes (8-byte lane passes, mirror and plain): int64 keys and pairs,
+    power-of-two sizes whose last phases take them, both directions; a
+    ragged size keeps at most six steps per pass."""
+    for k in (t + 7, t + 8):
+        n = 1 << k
+        keys = _i64(W.SEED_BASE + 80 + k, n)
+        kp = W.uniform_i32(W.SEED_BASE + 81 + k, n) % 89
+        vals = W.uniform_i32(W.SEED_BASE + 82 + k, n)
+        w64 = {asc: O.sort_keys64(keys, O.KEY_I64, asc) for asc in (True, False)}
+        wpr = {asc: O.sort_pairs(kp, vals, O.KEY_I32, asc) for asc in (True, False)}
+        for f in (7, 8):
+            plan = ("optimized", t, f)
+            assert max(s["fuse"] for s in B.bitonic_plan_shapes(n, "keys64", plan)
+                       if s["kind"] == "global_pass") == min(f, k - t)
+            for asc in (True, False):
+                print(f"[case] wide lanes plan={plan} n=2^{k} asc={asc}", flush=True)
+                assert np.array_equal(_sort64(keys, asc, "int64", plan), w64[asc]), (plan, k, asc)
+                gk, gv = _sort_pairs(kp, vals, asc, "int32", plan)
+                assert np.array_equal(gk, wpr[asc][0]) and np.array_equal(gv, wpr[asc][1]), (plan, k)
+    n = (1 << (t + 8)) - 7
+    keys = _i64(W.SEED_BASE + 83, n)
+    assert np.array_equal(_sort64(keys, True, "int64", ("optimized", t, 8)),
+                          O.sort_keys64(keys, O.KEY_I64, True))
+
+
+@pytest.mark.parametrize("t", [11, 12, 13])
 def test_wide_phase_merge(t):
     """Phase t + 1 as one launch on 2^(t+1)-element tiles (on, the default)
     and as a one-step pass and a merge (off): int64 keys and pairs, the
