@@ -30,6 +30,7 @@ from __future__ import annotations
 import bisect
 import collections
 import dataclasses
+import gc
 import time
 
 import numpy as np
@@ -381,7 +382,15 @@ def run_gpu(duration_s: float = 60.0, rate: float = 2000.0, budget_bytes: int = 
     warm.run([Request(-1 - k, 0.0, 1 << 20, 7 + k) for k in range(slots * 2)])
     srv = Server(ex, budget, max_inflight=slots)
     ex.segmented_batches = 0
-    out = srv.run(reqs)
+    # The request list (all arrivals of the run) is built up front; move it
+    # out of the collector's reach, so that a full collection during the run
+    # does not walk it and stall the loop for milliseconds.
+    gc.collect()
+    gc.freeze()
+    try:
+        out = srv.run(reqs)
+    finally:
+        gc.unfreeze()
     out.update({"segmented_batches": ex.segmented_batches,
                 "duration_s": duration_s, "rate_per_s": rate, "budget_bytes": budget_bytes,
                 "streams": slots, "offered_gkeys_s":
