@@ -447,9 +447,11 @@ int bitonic_sort_plan_launches_i32(int32_t* keys, int64_t n, int ascending,
  * offsets validation, see bitonic_validation_error), "tile_lane_steps"
  * (1, the default: the tile sort runs its phases up to 9 as cross-lane
  * compare-exchanges inside each wave; 0: every phase through LDS regroups),
- * "phase_merge" (1, the default: phase t+1 of a sort with 2^t-key tiles,
- * t <= 14, 16-byte aligned keys, runs as one launch on 2^(t+1)-key tiles;
- * 0: a one-step pass and a tile merge), "phase_blocks_per_cu" (-1..16:
+ * "phase_merge" (1, the default: phase t+1 after the tile sort of 2^t-element
+ * tiles runs as one launch on 2^(t+1)-element tiles -- for single arrays of
+ * 4-byte keys on a 16-byte boundary with t <= 14, for the 8-byte sorts, and
+ * for the big segments of every segmented sort; 0: a one-step pass and a
+ * tile merge), "phase_blocks_per_cu" (-1..16:
  * tile-phase workgroups per compute unit, each looping over its tiles,
  * default 1; -1 one tile per workgroup; 0 as the tile merges),
  * "lane_pass" (7, the default: passes of eight and nine steps hold 2^7 keys
