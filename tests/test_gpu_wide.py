@@ -265,6 +265,36 @@ def test_int64_maximum_size():
     torch.cuda.empty_cache()
 
 
+def test_int64_lane_passes_at_2_30():
+    """int64 keys, n = 2^30 (8 GiB), 2^13-element tiles and eight steps per
+    pass: lane passes up to phase 29, whose lane byte offsets reach 2^32,
+    then six-step passes for phase 30.  Checked by order, two multiset
+    hashes, the extremes and sampled order statistics counted in the input."""
+    n = 1 << 30
+    plan = ("optimized", 13, 8)
+    shapes = B.bitonic_plan_shapes(n, "keys64", plan)
+    gp = [s for s in shapes if s["kind"] == "global_pass"]
+    assert any(s["fuse"] == 8 and s["q"] + s["fuse"] == 29 for s in gp)
+    assert all(s["fuse"] <= 6 for s in gp if s["q"] + s["fuse"] == 30)
+    print(f"[case] int64 lane passes n={n} plan={plan}", flush=True)
+    t = _i64_on_device(n, W.SEED_BASE + 95)
+    h0 = _hash64(t)
+    lo, hi = int(t.min().item()), int(t.max().item())
+    src = t.clone()
+    B.bitonic_sort_wide_plan(t, None, True, "int64", plan)
+    torch.cuda.synchronize()
+    assert _sorted64(t)
+    assert _hash64(t) == h0
+    assert int(t[0].item()) == lo and int(t[-1].item()) == hi
+    for i in (0, n // 5, n // 2, n - 1):
+        v = int(t[i].item())
+        below = int((src < v).sum().item())
+        upto = int((src <= v).sum().item())
+        assert below <= i < upto, i
+    del src, t
+    torch.cuda.empty_cache()
+
+
 def test_int64_one_step_passes_past_2_30():
     """int64 keys, n = 2^30 + 2^20, 2^13-element tiles and one step per pass:
     the mirror pass of phase 31 runs on its own at q = 30, where a row spans
