@@ -456,14 +456,17 @@ int bitonic_sort_plan_launches_i32(int32_t* keys, int64_t n, int ascending,
  * default 1; -1 one tile per workgroup; 0 as the tile merges),
  * "lane_pass" (7, the default: passes of eight and nine steps hold 2^7 keys
  * of a column per lane over two and four lanes, ten steps 2^8 over four;
- * 8: only nine and ten steps as lane passes, 2^8 keys per lane; 0: no lane
- * passes, so at most eight steps per pass),
+ * 8: only nine and ten steps as lane passes, 2^8 keys per lane; 9: eight
+ * steps as with 7, nine and ten with each column over the four waves of a
+ * workgroup, exchanging through LDS (longer memory runs: faster once the
+ * keys no longer fit the Infinity Cache); 0: no lane passes, so at most
+ * eight steps per pass),
  * "wide_tile_log2" (11..13) or
  * "wide_fuse" (1..8) (the 8-byte sorts' plan); bitonic_get_tuning_value
  * reads one.
- * Size buckets: "tile_log2@k", "fuse@k" and "merge_blocks_per_cu@k" (k =
- * ceil(log2 n), 0..31) set the 4-byte sort's plan for that size only (0
- * removes the entry); a bucket's entries take precedence over the global
+ * Size buckets: "tile_log2@k", "fuse@k", "merge_blocks_per_cu@k" and
+ * "lane_pass@k" (k = ceil(log2 n), 0..31) set the 4-byte sort's plan for
+ * that size only (0 removes the entry); a bucket's entries take precedence over the global
  * values, an explicit plan over both.
  * bitonic_load_tuning reads "<name> <value>" lines (the autotuner's output
  * file; '#' starts a comment).  A line "cus <count>" ties the file to

@@ -13,8 +13,10 @@ sections 4.1 and 4.2):
     merge_blocks_per_cu  tile-merge workgroups per compute unit (-1: one
                          tile each)
   lane_pass              how passes of eight to ten steps split columns
-                         over lanes (7 or 8), by the summed time of the
-                         tuned plans of the buckets from 2^22 up
+                         over lanes or waves (7, 8 or 9), by the summed time
+                         of the tuned plans of the buckets from 2^22 up, then
+                         per bucket ("lane_pass@k") where another mode is
+                         1 % faster
   phase_blocks_per_cu    workgroups of the tile phase (phase t+1 in one
                          launch) per compute unit, -1, 1, 2 or 4, by the
                          summed time of the tuned plans from 2^20 up
@@ -167,6 +169,26 @@ def tune(buckets=(16, 18, 20, 22, 24, 26, 28), reps: int = 5, quick: bool = Fals
     lanes.sort()
     B.bitonic_set_tuning_value("lane_pass", lanes[0][1])
     best["lane_pass"] = lanes[0][1]
+    # and per bucket from 2^22 up: a bucket entry where another mode beats
+    # the global one by 1 % or more
+    for k, e in best["buckets"].items():
+        if k < 22 or quick:
+            continue
+        src = torch.empty(1 << k, dtype=torch.int32, device="cuda")
+        B.bitonic_keygen_i32(src, W.SEED_BASE + k)
+        buf = torch.empty_like(src)
+        plan = ("optimized", e["tile_log2"], e["fuse"], e["merge_blocks_per_cu"])
+        times = {}
+        for mode in (7, 8, 9):
+            B.bitonic_set_tuning_value(f"lane_pass@{k}", mode)
+            times[mode] = _time_plain(torch, src, buf, plan, reps)
+            log(json.dumps({"bucket": k, "lane_pass": mode, "ms": round(times[mode], 4)}))
+        B.bitonic_set_tuning_value(f"lane_pass@{k}", 0)
+        mode = min(times, key=times.get)
+        if mode != best["lane_pass"] and times[mode] < 0.99 * times[best["lane_pass"]]:
+            e["lane_pass"] = mode
+            B.bitonic_set_tuning_value(f"lane_pass@{k}", mode)
+        del src, buf
     tables = _segment_tables(torch)
     seg = []
     for bpc in ((4,) if quick else (2, 3, 4, 6, 8)):
@@ -230,6 +252,8 @@ def write_tuning(path: str, best: dict, command: str = "") -> None:
             if e["ms"] < 0.99 * e["default_ms"]:   # a bucket entry only where it pays
                 for name in ("tile_log2", "fuse", "merge_blocks_per_cu"):
                     f.write(f"{name}@{k} {e[name]}\n")
+            if "lane_pass" in e:
+                f.write(f"lane_pass@{k} {e['lane_pass']}\n")
 
 
 def write_summary(path: str, rows: list, command: str) -> None:

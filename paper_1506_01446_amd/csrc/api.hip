@@ -95,12 +95,13 @@ static int ceil_log2(int64_t n) {
 }
 
 // Tuned plans by size bucket k = ceil(log2 n) (tuning keys "tile_log2@k",
-// "fuse@k", "merge_blocks_per_cu@k"; 0 = no entry).  A bucket's entries take
+// "fuse@k", "merge_blocks_per_cu@k", "lane_pass@k"; 0 = no entry).  A bucket's entries take
 // precedence over the global tuning values, an explicit plan over both.
 constexpr int kBuckets = 32;
 static std::atomic<int> g_bk_tile[kBuckets];
 static std::atomic<int> g_bk_fuse[kBuckets];
 static std::atomic<int> g_bk_merge[kBuckets];  // -1: one tile per workgroup
+static std::atomic<int> g_bk_lane[kBuckets];   // lane-pass mode (7, 8, 9)
 
 // The tuning file named by the environment variable BITONIC_TUNE_FILE, if
 // any, is loaded once, before the first plan is resolved.
@@ -120,11 +121,13 @@ static int resolve(const bitonic_plan* plan, int64_t n, Resolved* r) {
   r->merge_bpc = g_merge_bpc.load();
   r->merge_blocks = 0;
   r->sort_kind = g_tile_lane.load() ? 4 : 0;
+  r->lane_pass = g_lane_pass.load();
   {
     const int k = n > (int64_t(1) << 31) ? 31 : ceil_log2(n < 1 ? 1 : n);
     if (const int t = g_bk_tile[k].load()) r->tile = t;
     if (const int f = g_bk_fuse[k].load()) r->fuse = f;
     if (const int m = g_bk_merge[k].load()) r->merge_bpc = m > 0 ? m : 0;
+    if (const int lp = g_bk_lane[k].load()) r->lane_pass = lp;
   }
   if (plan) {
     if (plan->kind < BITONIC_PLAN_AUTO || plan->kind > BITONIC_PLAN_OPTIMIZED) return BITONIC_EINVAL;
@@ -142,7 +145,6 @@ static int resolve(const bitonic_plan* plan, int64_t n, Resolved* r) {
   if (r->kind == BITONIC_PLAN_OPTIMIZED && r->tile == 0) r->tile = default_tile_log2(n);
   if (r->kind == BITONIC_PLAN_OPTIMIZED && !tile_log2_supported(r->tile)) return BITONIC_EINVAL;
   if (r->fuse < 1 || r->fuse > kFuseMax) return BITONIC_EINVAL;
-  r->lane_pass = g_lane_pass.load();
   r->phase_merge = g_phase_merge.load() != 0;
   return BITONIC_OK;
 }
@@ -162,10 +164,13 @@ struct Observer {
 // Enqueue (or, with count_only, just count) the launches for phases 1..K of
 // the network over keys[0, n).
 // Keys per lane (log2) of an f-step lane pass under lane-pass mode `mode`
-// (g_lane_pass), or 0 for a register pass.
+// (g_lane_pass), or 0 for a register pass; negative: the column spread over
+// the four waves of a workgroup (column_waves_pass_kernel) with 2^-fr keys
+// per lane.
 static int lane_pass_regs(int mode, int f) {
   if (mode == 8) return f >= 9 ? 8 : 0;
   if (mode == 7) return f == 8 || f == 9 ? 7 : (f == 10 ? 8 : 0);
+  if (mode == 9) return f == 8 ? 7 : (f == 9 ? -7 : (f == 10 ? -8 : 0));
   return 0;
 }
 
@@ -962,6 +967,9 @@ static int set_bucket_value(const char* name, size_t len, int k, int value) {
   } else if (is("merge_blocks_per_cu")) {
     if (value < -1 || value > 16) return BITONIC_EINVAL;
     g_bk_merge[k].store(value);
+  } else if (is("lane_pass")) {
+    if (value != 0 && value != 7 && value != 8 && value != 9) return BITONIC_EINVAL;
+    g_bk_lane[k].store(value);
   } else {
     return BITONIC_EINVAL;
   }
@@ -1035,7 +1043,7 @@ int bitonic_set_tuning_value(const char* key, int value) {
     return BITONIC_OK;
   }
   if (!std::strcmp(key, "lane_pass")) {
-    if (value != 0 && value != 7 && value != 8) return BITONIC_EINVAL;
+    if (value != 0 && value != 7 && value != 8 && value != 9) return BITONIC_EINVAL;
     g_lane_pass.store(value);
     return BITONIC_OK;
   }
@@ -1063,6 +1071,7 @@ int bitonic_get_tuning_value(const char* key, int* value) {
       if (is("tile_log2")) *value = g_bk_tile[k].load();
       else if (is("fuse")) *value = g_bk_fuse[k].load();
       else if (is("merge_blocks_per_cu")) *value = g_bk_merge[k].load();
+      else if (is("lane_pass")) *value = g_bk_lane[k].load();
       else return BITONIC_EINVAL;
       return BITONIC_OK;
     }

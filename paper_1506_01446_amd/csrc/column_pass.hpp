@@ -256,6 +256,91 @@ __global__ __launch_bounds__(256) void column_lanes_pass_kernel(int32_t* __restr
   });
 }
 
+// F = FR + 2 steps on index bits q+F-1 .. q of 4-byte keys with every
+// column of a 2^(q+F) block spread over the four waves of a workgroup: wave
+// w holds rows w 2^FR .. (w+1) 2^FR - 1 of 64 consecutive columns, one key
+// per lane and row, so a wave's access to a row is one 256-byte run (the
+// lane passes, whose lanes split a column, touch two or four shorter runs).
+// With MIRROR the upper two waves hold the mirrored rows of the mirrored
+// columns (rows R_w .. R_w + 2^FR - 1 of column 2^q-1-c, R_w = 2^F -
+// (w - 1) 2^FR) in descending order, so that register j of the four waves
+// holds the four rows one compare-exchange group of the top two row bits
+// needs.  Those two steps go through LDS in chunks of C registers (two
+// buffers, two barriers per chunk): every wave writes its registers of the
+// chunk, takes a quarter of the slots, performs both steps on the four keys
+// of each, writes them back, and reads its own again.  The other FR steps
+// run in registers; the mirrored waves, whose rows descend, hold their keys
+// complemented meanwhile (~ reverses the signed order), so the same
+// ascending steps serve every wave.  Whole blocks only, as the lane passes.
+template <int FR, bool MIRROR>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, FR >= 8 ? 1 : 2)))
+void column_waves_pass_kernel(int32_t* __restrict__ keys, int q) {
+  constexpr int F = FR + 2;
+  constexpr int M = 1 << FR;
+  constexpr int C = 32;  // registers per chunk
+  static_assert(M % C == 0 && C % 4 == 0, "whole chunks, quarters of a chunk");
+  __shared__ int32_t xch[2][4][C][64];
+  int32_t x[M];
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
+  const uint32_t g = blockIdx.x;  // one workgroup per 64 columns of a block
+  const uint32_t bs = (g >> (q - 6)) << (q + F);  // uniform block start
+  const uint32_t c = ((g & ((1u << (q - 6)) - 1u)) << 6) + lane;
+  const bool upper = MIRROR && w >= 2u;
+  const uint32_t colx = upper ? ((1u << q) - 1u) - c : c;
+  // row of register j: row0 + j, or (mirrored waves) row0 - j
+  const uint32_t row0 = upper ? (1u << F) - (w - 1u) * (uint32_t)M + (uint32_t)(M - 1)
+                              : w * (uint32_t)M;
+  const uint32_t off = colx * 4u;  // lane byte offset inside a row
+  auto row_of = [&](uint32_t j) { return upper ? row0 - j : row0 + j; };  // wave-uniform
+  const int32_t flip = upper ? -1 : 0;  // complement of the mirrored waves' keys
+  static_for<0, M>([&](auto J) {
+    const uint32_t r0 = bs + (row_of(J) << q);
+    x[J] = Keys32{keys}.at(r0).getb(off);
+  });
+  static_for<0, M / C>([&](auto K) {
+    constexpr int b = K & 1;
+    static_for<0, C>([&](auto J) { xch[b][w][J][lane] = x[K * C + J]; });
+    __syncthreads();
+    static_for<0, C / 4>([&](auto I) {
+      const uint32_t j = w * (C / 4) + I;
+      int32_t a0 = xch[b][0][j][lane], a1 = xch[b][1][j][lane];
+      int32_t a2 = xch[b][2][j][lane], a3 = xch[b][3][j][lane];
+      cmpx(a0, a2);  // the mirror step, or the step on the top row bit
+      cmpx(a1, a3);
+      cmpx(a0, a1);
+      if constexpr (MIRROR)
+        cmpx(a3, a2);  // wave 3 holds the lower rows of the mirrored half
+      else
+        cmpx(a2, a3);
+      xch[b][0][j][lane] = a0;
+      xch[b][1][j][lane] = a1;
+      xch[b][2][j][lane] = a2;
+      xch[b][3][j][lane] = a3;
+    });
+    __syncthreads();
+    static_for<0, C>([&](auto J) { x[K * C + J] = xch[b][w][J][lane] ^ flip; });
+  });
+  pass_steps<FR, false, 1>(x);
+  __builtin_amdgcn_sched_barrier(0);
+  uint32_t bs_st = bs;
+  asm volatile("" : "+s"(bs_st));
+  static_for<0, M>([&](auto J) {
+    const uint32_t r0 = bs_st + (row_of(J) << q);
+    Keys32{keys}.at(r0).putb(off, x[J] ^ flip);
+    __builtin_amdgcn_sched_barrier(0);
+  });
+}
+
+template <int FR>
+static void launch_column_waves_F(bool mirror, int32_t* keys, uint32_t n, int q, hipStream_t st) {
+  const uint32_t blocks = n >> (FR + 8);  // one workgroup per 64 columns x 2^(FR+2) rows
+  if (mirror)
+    column_waves_pass_kernel<FR, true><<<blocks, 256, 0, st>>>(keys, q);
+  else
+    column_waves_pass_kernel<FR, false><<<blocks, 256, 0, st>>>(keys, q);
+}
+
 template <int FR, int G>
 static void launch_column_lanes_FG(bool mirror, int32_t* keys, uint32_t n, int q, hipStream_t st) {
   const uint32_t blocks = n >> (FR + 8);  // n / 2^FR threads, 256 per workgroup

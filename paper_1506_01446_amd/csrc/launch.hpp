@@ -46,7 +46,9 @@ void launch_global_pass(int f, bool mirror, int32_t* keys, uint32_t n, int q, hi
 void launch_column_pass_i32(int f, bool mirror, int32_t* keys, uint32_t n, int q, hipStream_t st);
 
 // Lane passes (column_lanes_pass_kernel): f = fr + g steps, each column split
-// over 2^g lanes of 2^fr keys; (fr, g) in {7, 8} x {1, 2}.  Needs n a
+// over 2^g lanes of 2^fr keys; (fr, g) in {7, 8} x {1, 2}; fr = -7, -8: the
+// column over the four waves of a workgroup instead (column_waves_pass_kernel,
+// f = 9, 10).  Needs n a
 // multiple of 2^(q+f) and q + f <= 30 (lane_pass_fits); false (nothing
 // launched) for any other shape.
 constexpr bool lane_pass_fits(uint32_t n, int q, int f) {

@@ -367,6 +367,11 @@ def test_bucket_tuning(lib, tmp_path):
         assert B.bitonic_plan_tile_log2(2**(k + 1)) == 14          # other buckets untouched
         assert B.bitonic_plan_passes(2**k) == _closed_form_optimized(k, 13, 5)
         assert B.bitonic_plan_passes(2**k, ("optimized", 14, 8)) == _closed_form_optimized(k, 14, 8)
+        B.bitonic_set_tuning_value(f"lane_pass@{k}", 9)
+        assert B.bitonic_get_tuning_value(f"lane_pass@{k}") == 9
+        with pytest.raises(B.BitonicError):
+            B.bitonic_set_tuning_value(f"lane_pass@{k}", 5)
+        B.bitonic_set_tuning_value(f"lane_pass@{k}", 0)
         for bad in ("tile_log2@32", "fuse@-1", "nonsense@3", "tile_log2@x"):
             with pytest.raises(B.BitonicError):
                 B.bitonic_set_tuning_value(bad, 13)
@@ -424,10 +429,10 @@ def test_lane_pass_modes(lib):
     a pass takes at most eight steps (seven for other sizes)."""
     saved = B.bitonic_get_tuning_value("lane_pass")
     try:
-        for bad in (1, 6, 9, -1):
+        for bad in (1, 6, 10, -1):
             with pytest.raises(B.BitonicError):
                 B.bitonic_set_tuning_value("lane_pass", bad)
-        for mode in (7, 8):
+        for mode in (7, 8, 9):
             B.bitonic_set_tuning_value("lane_pass", mode)
             assert B.bitonic_get_tuning_value("lane_pass") == mode
             for f in (9, 10):

@@ -136,11 +136,12 @@ def test_per_phase_states(plan):
         assert np.array_equal(t.cpu().numpy(), states[p]), (plan, p)
 
 
-@pytest.mark.parametrize("mode", [8, 7])
+@pytest.mark.parametrize("mode", [8, 7, 9])
 def test_lane_passes(mode):
     """Passes of eight to ten steps with each column split over two or four
     lanes (lane passes; with mode 7 eight- and nine-step passes take 2^7
-    keys per lane): every tile size, both directions, at power-of-two sizes
+    keys per lane; with mode 9 nine and ten steps spread each column over
+    the four waves of a workgroup): every tile size, both directions, at power-of-two sizes
     whose last phases have nine and ten long-stride steps, so that mirror
     and plain lane passes of every width run."""
     saved = B.bitonic_get_tuning_value("lane_pass")
@@ -165,9 +166,10 @@ def test_lane_passes(mode):
         B.bitonic_set_tuning_value("lane_pass", saved)
 
 
+@pytest.mark.parametrize("mode", [7, 9])
 @pytest.mark.parametrize("plan", [("optimized", 11, 10), ("optimized", 11, 9)],
                          ids=lambda p: "-".join(map(str, p)))
-def test_per_phase_states_lane_passes(plan):
+def test_per_phase_states_lane_passes(plan, mode):
     """Per-phase states through the lane passes: n = 2^21 with 2^11 tiles,
     whose phases 20 and 21 take nine- and ten-step passes."""
     n = 1 << 21
@@ -175,12 +177,17 @@ def test_per_phase_states_lane_passes(plan):
     states = {}
     O.bitonic_i32(keys, True, O.FLIP_VIRTUAL,
                   hook=lambda p, s, x: states.__setitem__(p, x) if s == p else None)
-    for p in range(12, 22):
-        print(f"[case] per-phase lane passes plan={plan} p={p}", flush=True)
-        t = torch.from_numpy(keys.copy()).cuda()
-        B.bitonic_network_phases_i32(t, p, True, plan)
-        torch.cuda.synchronize()
-        assert np.array_equal(t.cpu().numpy(), states[p]), (plan, p)
+    saved = B.bitonic_get_tuning_value("lane_pass")
+    try:
+        B.bitonic_set_tuning_value("lane_pass", mode)
+        for p in range(12, 22):
+            print(f"[case] per-phase lane passes plan={plan} mode={mode} p={p}", flush=True)
+            t = torch.from_numpy(keys.copy()).cuda()
+            B.bitonic_network_phases_i32(t, p, True, plan)
+            torch.cuda.synchronize()
+            assert np.array_equal(t.cpu().numpy(), states[p]), (plan, p)
+    finally:
+        B.bitonic_set_tuning_value("lane_pass", saved)
 
 
 @pytest.mark.parametrize("t", [11, 12, 13, 14])
