@@ -572,6 +572,41 @@ def _hashes(t, chunk=1 << 26):
     return int(s1.item()), int(s2.item())
 
 
+def test_wave_passes_at_2_30():
+    """n = 2^30 with 2^15-key tiles, ten fused steps and lane mode 9: the
+    nine- and ten-step passes of phases 25..30 spread each column over the
+    four waves of a workgroup (the plan the tuning table picks beyond the
+    Infinity Cache).  Checked by order, two multiset hashes, the extremes
+    and sampled order statistics counted in the input."""
+    n = 1 << 30
+    plan = ("optimized", 15, 10)
+    saved = B.bitonic_get_tuning_value("lane_pass")
+    try:
+        B.bitonic_set_tuning_value("lane_pass", 9)
+        shapes = B.bitonic_plan_shapes(n, "keys32", plan)
+        assert sum(1 for s in shapes if s["kind"] == "global_pass" and s["fuse"] == 10) >= 4
+        print(f"[case] wave passes n={n} plan={plan}", flush=True)
+        t = torch.empty(n, dtype=torch.int32, device="cuda")
+        B.bitonic_keygen_i32(t, W.SEED_BASE + 98)
+        h0 = _hashes(t)
+        lo, hi = int(t.min().item()), int(t.max().item())
+        src = t.clone()
+        B.bitonic_sort_plan_i32(t, True, plan)
+        torch.cuda.synchronize()
+        assert bool((t[1:] >= t[:-1]).all().item())
+        assert _hashes(t) == h0
+        assert int(t[0].item()) == lo and int(t[-1].item()) == hi
+        for i in (0, n // 7, n // 2, n - 1):
+            v = int(t[i].item())
+            below = int((src < v).sum().item())
+            upto = int((src <= v).sum().item())
+            assert below <= i < upto, i
+        del src, t
+        torch.cuda.empty_cache()
+    finally:
+        B.bitonic_set_tuning_value("lane_pass", saved)
+
+
 @pytest.mark.parametrize("n", [1 << 31, (1 << 31) - 1])
 def test_maximum_size(n):
     """The largest supported n: sorted order, the multiset (two hashes), the
