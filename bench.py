@@ -182,8 +182,8 @@ def kernel_source_hash() -> str:
 
 def kernel_class(name: str):
     """Kernel class of a (demangled, shortened) kernel name: tile_sort,
-    tile_merge, tile_phase, global_pass_f<F> for the unbounded pass kernels,
-    else None."""
+    tile_merge, tile_phase, global_pass_f<F> for the unbounded pass kernels
+    (F steps: four-column, one-column, lane and wave passes), else None."""
     for pre in ("tile_kernel<", "tile_loop_kernel<"):
         if name.startswith(pre):
             args = name[len(pre):name.index(">")].split(", ")
@@ -197,6 +197,9 @@ def kernel_class(name: str):
     if name.startswith("column_lanes_pass_kernel<"):
         fr, g = name[len("column_lanes_pass_kernel<"):name.index(">")].split(", ")[:2]
         return f"global_pass_f{int(fr) + int(g)}"
+    if name.startswith("column_waves_pass_kernel<"):
+        fr = name[len("column_waves_pass_kernel<"):name.index(">")].split(", ")[0]
+        return f"global_pass_f{int(fr) + 2}"
     return None
 
 

@@ -240,6 +240,23 @@ def test_bench_traffic_lookup(monkeypatch):
     assert bench.committed_traffic("tile_merge", 12345) is None
 
 
+def test_bench_kernel_classes():
+    import bench
+    cases = {
+        "tile_kernel<14, 5, 4, 0>": "tile_sort",
+        "tile_loop_kernel<14, 5, 1, 0>": "tile_merge",
+        "tile_loop_kernel<15, 5, 5, 0>": "tile_phase",
+        "global_pass_kernel<3, true, false>": "global_pass_f3",
+        "global_pass_kernel<3, true, true>": None,
+        "column_pass_kernel<7, true, false, Keys32, false>": "global_pass_f7",
+        "column_lanes_pass_kernel<8, 2, true>": "global_pass_f10",
+        "column_waves_pass_kernel<7, true>": "global_pass_f9",
+        "keygen_kernel": None,
+    }
+    for name, cls in cases.items():
+        assert bench.kernel_class(name) == cls, name
+
+
 def _ceil_log2(n):
     return max(0, (n - 1).bit_length())
 
