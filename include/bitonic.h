@@ -461,13 +461,20 @@ int bitonic_sort_plan_launches_i32(int32_t* keys, int64_t n, int ascending,
  * workgroup, exchanging through LDS (longer memory runs: faster once the
  * keys no longer fit the Infinity Cache); 0: no lane passes, so at most
  * eight steps per pass),
+ * "sort_tile_log2" (0, the default, or 11..15: when larger than the
+ * optimized plan's tile 2^t, the tile sort takes 2^s-key tiles, phases
+ * 1..s in one launch, and every later phase passes down to stride 2^t and
+ * merges 2^t-key tiles -- one launch fewer than tiles of 2^t with the tile
+ * phase, for a longer tile sort; applies to explicit optimized plans too,
+ * not to arrays off a 16-byte boundary),
  * "wide_tile_log2" (11..13) or
  * "wide_fuse" (1..8) (the 8-byte sorts' plan); bitonic_get_tuning_value
  * reads one.
- * Size buckets: "tile_log2@k", "fuse@k", "merge_blocks_per_cu@k" and
- * "lane_pass@k" (k = ceil(log2 n), 0..31) set the 4-byte sort's plan for
- * that size only (0 removes the entry); a bucket's entries take precedence over the global
- * values, an explicit plan over both.
+ * Size buckets: "tile_log2@k", "fuse@k", "merge_blocks_per_cu@k",
+ * "lane_pass@k" and "sort_tile_log2@k" (k = ceil(log2 n), 0..31) set the
+ * 4-byte sort's plan for that size only (0 removes the entry); a bucket's
+ * entries take precedence over the global values, an explicit plan's tile,
+ * fuse and merge grid over both.
  * bitonic_load_tuning reads "<name> <value>" lines (the autotuner's output
  * file; '#' starts a comment).  A line "cus <count>" ties the file to
  * devices with that many compute units: on the current device with another

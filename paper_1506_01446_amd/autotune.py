@@ -12,6 +12,9 @@ sections 4.1 and 4.2):
     fuse                 long-stride steps fused per HBM pass (6 .. 10)
     merge_blocks_per_cu  tile-merge workgroups per compute unit (-1: one
                          tile each)
+  sort_tile_log2@k       a tile sort of larger tiles than the merges' (one
+                         launch fewer, a longer tile sort), per bucket from
+                         2^20 up where it is 0.3 % faster
   lane_pass              how passes of eight to ten steps split columns
                          over lanes or waves (7, 8 or 9), by the summed time
                          of the tuned plans of the buckets from 2^22 up, then
@@ -189,6 +192,27 @@ def tune(buckets=(16, 18, 20, 22, 24, 26, 28), reps: int = 5, quick: bool = Fals
             e["lane_pass"] = mode
             B.bitonic_set_tuning_value(f"lane_pass@{k}", mode)
         del src, buf
+    # and per bucket from 2^20 up: a tile sort of larger tiles than the
+    # merges' ("sort_tile_log2@k"), which saves a launch for a longer tile
+    # sort, where it beats the bucket's plan by 0.3 % or more (medians of
+    # four times as many sorts: the difference is a fraction of a percent)
+    for k, e in best["buckets"].items():
+        if k < 20 or quick or e["tile_log2"] >= 15:
+            continue
+        src = torch.empty(1 << k, dtype=torch.int32, device="cuda")
+        B.bitonic_keygen_i32(src, W.SEED_BASE + k)
+        buf = torch.empty_like(src)
+        plan = ("optimized", e["tile_log2"], e["fuse"], e["merge_blocks_per_cu"])
+        times = {}
+        for st in (0,) + tuple(range(e["tile_log2"] + 1, 16)):
+            B.bitonic_set_tuning_value(f"sort_tile_log2@{k}", st)
+            times[st] = _time_plain(torch, src, buf, plan, 4 * reps)
+            log(json.dumps({"bucket": k, "sort_tile_log2": st, "ms": round(times[st], 4)}))
+        st = min(times, key=times.get)
+        if st and times[st] < 0.997 * times[0]:
+            e["sort_tile_log2"] = st
+        B.bitonic_set_tuning_value(f"sort_tile_log2@{k}", e.get("sort_tile_log2", 0))
+        del src, buf
     tables = _segment_tables(torch)
     seg = []
     for bpc in ((4,) if quick else (2, 3, 4, 6, 8)):
@@ -254,6 +278,8 @@ def write_tuning(path: str, best: dict, command: str = "") -> None:
                     f.write(f"{name}@{k} {e[name]}\n")
             if "lane_pass" in e:
                 f.write(f"lane_pass@{k} {e['lane_pass']}\n")
+            if "sort_tile_log2" in e:
+                f.write(f"sort_tile_log2@{k} {e['sort_tile_log2']}\n")
 
 
 def write_summary(path: str, rows: list, command: str) -> None:
@@ -269,6 +295,7 @@ def write_summary(path: str, rows: list, command: str) -> None:
         out.append(f"## n = 2^{k}: {len(cand)} plans timed, slowest {cand[-1]['ms']} ms"
                    if cand else f"## n = 2^{k}")
         out += [json.dumps(r) for r in cand[:5]]
+        out += [json.dumps(r) for r in cand[5:] if "sort_tile_log2" in r]
         out += [json.dumps(r) for r in rows if r.get("bucket") == k and "best" in r]
     out.append("## segmented and 8-byte knobs")
     out += [json.dumps(r) for r in rows if "bucket" not in r]

@@ -50,6 +50,10 @@ static std::atomic<int> g_phase_merge{1};
 // Tile-phase workgroups per compute unit, each looping over its tiles
 // (-1: one tile per workgroup; 0: as the tile merges).
 static std::atomic<int> g_phase_bpc{1};
+// Tile-sort tile (log2 keys) of the optimized plan when larger than the
+// merge tile: phases 1..s sort in one launch, later phases pass down to the
+// merge tile's bit and merge 2^t-key tiles (0: the merge tile).
+static std::atomic<int> g_sort_tile{0};
 static std::atomic<int> g_validate{-1};  // check segment tables on the device; -1: not yet read
 
 // Offsets validation of the segmented sorts: the tuning value "validate", or
@@ -69,6 +73,7 @@ static bool validate_enabled() {
 struct Resolved {
   int kind;
   int tile;
+  int sort_tile = 0;      // tile sort's tile (log2), >= tile (optimized plan)
   int fuse;
   int sort_kind = 0;      // tile-sort program: 0, or 4 with cross-lane steps
   int merge_bpc;          // tile-merge workgroups per compute unit
@@ -102,6 +107,7 @@ static std::atomic<int> g_bk_tile[kBuckets];
 static std::atomic<int> g_bk_fuse[kBuckets];
 static std::atomic<int> g_bk_merge[kBuckets];  // -1: one tile per workgroup
 static std::atomic<int> g_bk_lane[kBuckets];   // lane-pass mode (7, 8, 9)
+static std::atomic<int> g_bk_sort_tile[kBuckets];  // tile-sort tile (log2)
 
 // The tuning file named by the environment variable BITONIC_TUNE_FILE, if
 // any, is loaded once, before the first plan is resolved.
@@ -122,12 +128,14 @@ static int resolve(const bitonic_plan* plan, int64_t n, Resolved* r) {
   r->merge_blocks = 0;
   r->sort_kind = g_tile_lane.load() ? 4 : 0;
   r->lane_pass = g_lane_pass.load();
+  int sort_tile = g_sort_tile.load();
   {
     const int k = n > (int64_t(1) << 31) ? 31 : ceil_log2(n < 1 ? 1 : n);
     if (const int t = g_bk_tile[k].load()) r->tile = t;
     if (const int f = g_bk_fuse[k].load()) r->fuse = f;
     if (const int m = g_bk_merge[k].load()) r->merge_bpc = m > 0 ? m : 0;
     if (const int lp = g_bk_lane[k].load()) r->lane_pass = lp;
+    if (const int s = g_bk_sort_tile[k].load()) sort_tile = s;
   }
   if (plan) {
     if (plan->kind < BITONIC_PLAN_AUTO || plan->kind > BITONIC_PLAN_OPTIMIZED) return BITONIC_EINVAL;
@@ -144,6 +152,7 @@ static int resolve(const bitonic_plan* plan, int64_t n, Resolved* r) {
   }
   if (r->kind == BITONIC_PLAN_OPTIMIZED && r->tile == 0) r->tile = default_tile_log2(n);
   if (r->kind == BITONIC_PLAN_OPTIMIZED && !tile_log2_supported(r->tile)) return BITONIC_EINVAL;
+  r->sort_tile = r->kind == BITONIC_PLAN_OPTIMIZED && sort_tile > r->tile ? sort_tile : r->tile;
   if (r->fuse < 1 || r->fuse > kFuseMax) return BITONIC_EINVAL;
   r->phase_merge = g_phase_merge.load() != 0;
   return BITONIC_OK;
@@ -230,7 +239,7 @@ static int64_t enqueue_plain(int32_t* keys, uint32_t n, int K, Codec flip, const
   }
 
   // optimized
-  if (K <= r.tile) {
+  if (K <= r.sort_tile) {
     // Phases 1..K.  The scalar-access tile sorts 2^13-key tiles, which is
     // phases 1..K only when one tile holds all n keys (K == k); fewer phases
     // of a longer array run in the LDS network.
@@ -246,8 +255,11 @@ static int64_t enqueue_plain(int32_t* keys, uint32_t n, int K, Codec flip, const
     return launches;
   }
   // The tile sort encodes the keys and the last merge decodes them; the
-  // passes and merges in between work on encoded keys.
+  // passes and merges in between work on encoded keys.  The tile sort takes
+  // phases 1..Ls; each later phase passes down to bit L and merges 2^L-key
+  // tiles (Ls >= L).
   const int L = r.tile;
+  const int Ls = r.sort_tile;
   // Eight fused steps only when n is a power of two: otherwise the block of
   // a pass that straddles n takes the bounds-checked eight-step kernel, which
   // runs out of registers, so such sorts use at most seven.
@@ -256,14 +268,14 @@ static int64_t enqueue_plain(int32_t* keys, uint32_t n, int K, Codec flip, const
   // they need whole blocks and lane byte offsets below 2^32 (lane_pass_fits):
   // aligned power-of-two arrays, phases up to 30.
   const bool lanes_ok = r.lane_pass != 0 && !r.scalar_io && (n & (n - 1)) == 0;
-  emit(tile_shape(BITONIC_LAUNCH_TILE_SORT, L), [&] {
+  emit(tile_shape(BITONIC_LAUNCH_TILE_SORT, Ls), [&] {
     if (r.scalar_io)
       launch_tile_scalar(0, keys, n, flip, CX_ENC, st);
     else
-      launch_tile(L, r.sort_kind, keys, n, flip, CX_ENC, 0, st);
+      launch_tile(Ls, r.sort_kind, keys, n, flip, CX_ENC, 0, st);
   });
-  for (int p = L + 1; p <= K; ++p) {
-    if (p == L + 1 && r.phase_merge && !r.scalar_io && p <= kTileMaxLog2) {
+  for (int p = Ls + 1; p <= K; ++p) {
+    if (p == Ls + 1 && r.phase_merge && !r.scalar_io && p <= kTileMaxLog2) {
       // the whole phase on 2^p-key tiles (mirror step included)
       const int cx = p == K ? CX_DEC : CX_NONE;
       emit(bitonic_launch_shape{BITONIC_LAUNCH_TILE_MERGE, 0, p, 1, 4, 64},
@@ -318,6 +330,7 @@ static void fit_alignment(const int32_t* keys, Resolved* r) {
   if (r->kind == BITONIC_PLAN_OPTIMIZED && (reinterpret_cast<uintptr_t>(keys) & 15u) != 0) {
     r->scalar_io = true;
     r->tile = kScalarTileLog2;
+    r->sort_tile = kScalarTileLog2;
   }
 }
 
@@ -970,6 +983,9 @@ static int set_bucket_value(const char* name, size_t len, int k, int value) {
   } else if (is("lane_pass")) {
     if (value != 0 && value != 7 && value != 8 && value != 9) return BITONIC_EINVAL;
     g_bk_lane[k].store(value);
+  } else if (is("sort_tile_log2")) {
+    if (value && !tile_log2_supported(value)) return BITONIC_EINVAL;
+    g_bk_sort_tile[k].store(value);
   } else {
     return BITONIC_EINVAL;
   }
@@ -1047,6 +1063,11 @@ int bitonic_set_tuning_value(const char* key, int value) {
     g_lane_pass.store(value);
     return BITONIC_OK;
   }
+  if (!std::strcmp(key, "sort_tile_log2")) {
+    if (value && !tile_log2_supported(value)) return BITONIC_EINVAL;
+    g_sort_tile.store(value);
+    return BITONIC_OK;
+  }
   if (!std::strcmp(key, "wide_tile_log2")) {
     if (value < kWideTileMinLog2 || value > kWideTileMaxLog2) return BITONIC_EINVAL;
     g_wide_tile_log2.store(value);
@@ -1072,6 +1093,7 @@ int bitonic_get_tuning_value(const char* key, int* value) {
       else if (is("fuse")) *value = g_bk_fuse[k].load();
       else if (is("merge_blocks_per_cu")) *value = g_bk_merge[k].load();
       else if (is("lane_pass")) *value = g_bk_lane[k].load();
+      else if (is("sort_tile_log2")) *value = g_bk_sort_tile[k].load();
       else return BITONIC_EINVAL;
       return BITONIC_OK;
     }
@@ -1084,6 +1106,7 @@ int bitonic_get_tuning_value(const char* key, int* value) {
   else if (!std::strcmp(key, "seg_fuse")) *value = g_seg_fuse.load();
   else if (!std::strcmp(key, "tile_lane_steps")) *value = g_tile_lane.load();
   else if (!std::strcmp(key, "lane_pass")) *value = g_lane_pass.load();
+  else if (!std::strcmp(key, "sort_tile_log2")) *value = g_sort_tile.load();
   else if (!std::strcmp(key, "phase_merge")) *value = g_phase_merge.load();
   else if (!std::strcmp(key, "phase_blocks_per_cu")) *value = g_phase_bpc.load();
   else if (!std::strcmp(key, "validate")) *value = validate_enabled() ? 1 : 0;

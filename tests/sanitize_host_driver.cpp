@@ -82,6 +82,16 @@ int main() {
       CHECK(bitonic_plan_shapes(n, BITONIC_LAYOUT_KEYS32, &plan, shapes.data(), 4096) ==
             bitonic_plan_passes(n, &plan));
   }
+  // tile-sort tiles larger than the merge tile
+  for (int s : {0, 13, 15}) {
+    CHECK(bitonic_set_tuning_value("sort_tile_log2", s) == BITONIC_OK);
+    bitonic_plan plan{BITONIC_PLAN_OPTIMIZED, 12, 10, 0};
+    for (int64_t n : sizes)
+      CHECK(bitonic_plan_shapes(n, BITONIC_LAYOUT_KEYS32, &plan, shapes.data(), 4096) ==
+            bitonic_plan_passes(n, &plan));
+  }
+  CHECK(bitonic_set_tuning_value("sort_tile_log2", 16) == BITONIC_EINVAL);
+  CHECK(bitonic_set_tuning_value("sort_tile_log2", 0) == BITONIC_OK);
   CHECK(bitonic_set_tuning_value("lane_pass", 7) == BITONIC_OK);
   CHECK(bitonic_plan_shapes(-1, 0, nullptr, nullptr, 0) == -1);
   CHECK(bitonic_plan_shapes(5, 99, nullptr, nullptr, 0) == -1);

@@ -423,7 +423,7 @@ def test_validation_switch(lib):
     assert lib.bitonic_validation_error(None) == -1
 
 
-def test_autotune_summary(tmp_path):
+def test_autotune_summary(lib, tmp_path):
     """The autotuner's summary keeps the five fastest plans per bucket, the
     winner, and every segmented and 8-byte timing."""
     import json
@@ -431,13 +431,27 @@ def test_autotune_summary(tmp_path):
     rows = [{"bucket": 20, "tile_log2": t, "fuse": 8, "merge_blocks_per_cu": -1, "ms": 1.0 + t}
             for t in range(12, 19)]
     rows.append({"bucket": 20, "best": {"tile_log2": 12, "ms": 13.0, "default_ms": 14.0}})
+    rows.append({"bucket": 20, "sort_tile_log2": 15, "ms": 30.0})
     rows.append({"seg_blocks_per_cu": 4, "ms": 0.5})
     p = tmp_path / "summary.txt"
     autotune.write_summary(str(p), rows, "cmd")
     body = [json.loads(ln) for ln in p.read_text().splitlines() if ln.startswith("{")]
     assert [r["tile_log2"] for r in body if "tile_log2" in r][:5] == [12, 13, 14, 15, 16]
     assert any("best" in r for r in body) and body[-1] == {"seg_blocks_per_cu": 4, "ms": 0.5}
-    assert "slowest 19.0 ms" in p.read_text()
+    assert {"bucket": 20, "sort_tile_log2": 15, "ms": 30.0} in body   # kept though slow
+    assert "slowest 30.0 ms" in p.read_text()
+    # a bucket's sort-tile entry goes into the table and loads back
+    t = tmp_path / "table.txt"
+    autotune.write_tuning(str(t), {"buckets": {24: {"tile_log2": 14, "fuse": 10,
+                                                    "merge_blocks_per_cu": 2, "ms": 1.0,
+                                                    "default_ms": 1.0, "sort_tile_log2": 15}}})
+    assert "sort_tile_log2@24 15" in t.read_text().splitlines()
+    saved = B.bitonic_get_tuning_value("sort_tile_log2@24")
+    try:
+        B.bitonic_load_tuning(str(t))
+        assert B.bitonic_get_tuning_value("sort_tile_log2@24") == 15
+    finally:
+        B.bitonic_set_tuning_value("sort_tile_log2@24", saved)
 
 
 def test_lane_pass_modes(lib):
@@ -468,6 +482,83 @@ def test_lane_pass_modes(lib):
             _closed_form_optimized(24, 14, 8)
     finally:
         B.bitonic_set_tuning_value("lane_pass", saved)
+
+
+def _closed_form_sort_tile(k, t, f, s, phase=True):
+    """Launches of the optimized plan on n = 2^k whose tile sort takes 2^s-key
+    tiles (s >= t): phases 1..s in one launch, then per phase p > s its
+    ceil((p - t) / f) passes down to bit t and a merge of 2^t-key tiles;
+    phase s + 1 in one launch when s <= 14."""
+    if k <= 1:
+        return k
+    if k <= s:
+        return 1
+    per = [-(-(p - t) // (f if f <= 8 or p <= 30 else 8)) + 1 for p in range(s + 1, k + 1)]
+    if phase and s <= 14:
+        per[0] = 1
+    return 1 + sum(per)
+
+
+def test_sort_tile(lib):
+    """A tile-sort tile larger than the merge tile ("sort_tile_log2"): the
+    tile sort takes phases 1..s, every later phase's passes cover its strides
+    from 2^(p-1) down to the merge tile 2^t, each once, and its merge the
+    rest; an array off a 16-byte boundary keeps its scalar-access plan."""
+    saved = B.bitonic_get_tuning_value("sort_tile_log2")
+    saved24 = B.bitonic_get_tuning_value("sort_tile_log2@24")
+    try:
+        for bad in (-1, 1, 10, 16):
+            with pytest.raises(B.BitonicError):
+                B.bitonic_set_tuning_value("sort_tile_log2", bad)
+            with pytest.raises(B.BitonicError):
+                B.bitonic_set_tuning_value("sort_tile_log2@24", bad)
+        for s in (12, 13, 14, 15):
+            B.bitonic_set_tuning_value("sort_tile_log2", s)
+            assert B.bitonic_get_tuning_value("sort_tile_log2") == s
+            for t in (11, 12, 13, 14, 15):
+                for f in (2, 7, 10):
+                    plan = ("optimized", t, f)
+                    for k in range(1, 32):
+                        assert B.bitonic_plan_passes(2**k, plan) == \
+                            _closed_form_sort_tile(k, t, f, max(s, t)), (s, t, f, k)
+                    for n in (2**24, 2**24 - 1, 10**7, 2**s + 5, 2**31):
+                        sh = B.bitonic_plan_shapes(n, "keys32", plan)
+                        k = _ceil_log2(n)
+                        ls = max(s, t)
+                        assert sh[0]["kind"] == "tile_sort" and sh[0]["q"] == min(ls, k)
+                        i, p = 1, ls + 1
+                        while i < len(sh):   # one phase: passes, then its merge
+                            if p == ls + 1 and ls <= 14:
+                                assert sh[i]["kind"] == "tile_merge" and sh[i]["q"] == p
+                                i, p = i + 1, p + 1
+                                continue
+                            top = p - 1
+                            while sh[i]["kind"] == "global_pass":
+                                assert sh[i]["q"] + sh[i]["fuse"] - 1 == top
+                                assert sh[i]["mirror"] == (1 if top == p - 1 else 0)
+                                top = sh[i]["q"] - 1
+                                i += 1
+                            assert top == t - 1, (s, t, f, n, p)
+                            assert sh[i]["kind"] == "tile_merge" and sh[i]["q"] == t
+                            i, p = i + 1, p + 1
+                        assert p == max(k, ls) + 1, (s, t, f, n)
+                        _check_shapes(sh, n, 4)
+                    un = B.bitonic_plan_shapes(2**24, "keys32_unaligned", plan)
+                    assert un[0]["q"] == 13 and all(x["q"] == 13 for x in un
+                                                    if x["kind"] == "tile_merge")
+        B.bitonic_set_tuning_value("sort_tile_log2", 0)
+        assert B.bitonic_plan_passes(2**24, ("optimized", 14, 10)) == \
+            _closed_form_optimized(24, 14, 10)
+        # a size-bucket entry applies to its bucket only
+        B.bitonic_set_tuning_value("sort_tile_log2@24", 15)
+        assert B.bitonic_get_tuning_value("sort_tile_log2@24") == 15
+        assert B.bitonic_plan_passes(2**24, ("optimized", 14, 10)) == \
+            _closed_form_sort_tile(24, 14, 10, 15)
+        assert B.bitonic_plan_passes(2**23, ("optimized", 14, 10)) == \
+            _closed_form_optimized(23, 14, 10)
+    finally:
+        B.bitonic_set_tuning_value("sort_tile_log2", saved)
+        B.bitonic_set_tuning_value("sort_tile_log2@24", saved24)
 
 
 def test_phase_merge_switch(lib):

@@ -190,6 +190,81 @@ def test_per_phase_states_lane_passes(plan, mode):
         B.bitonic_set_tuning_value("lane_pass", saved)
 
 
+@pytest.mark.parametrize("s", [12, 13, 14, 15])
+def test_sort_tile(s):
+    """A tile sort of 2^s-key tiles ahead of 2^t-key merges (t < s, tuning
+    value "sort_tile_log2"): every such pair, short and ten-step passes,
+    with the tile phase on and off, as the whole sort (n <= 2^s), at powers
+    of two and with ragged tails, looping and one-tile merge workgroups,
+    both directions, bit-exact against the oracle."""
+    saved = B.bitonic_get_tuning_value("sort_tile_log2")
+    saved_pm = B.bitonic_get_tuning_value("phase_merge")
+    want = {}
+    try:
+        B.bitonic_set_tuning_value("sort_tile_log2", s)
+        for pm in (1, 0):
+            B.bitonic_set_tuning_value("phase_merge", pm)
+            for t in range(11, s):
+                for n in ((1 << s) - 7, 1 << (s + 1), (1 << (s + 2)) + 4099, 1 << (s + 4)):
+                    if n not in want:
+                        keys = W.uniform_i32(W.SEED_BASE + 91 * s + n, n)
+                        want[n] = (keys, O.sort_i32(keys, True))
+                    keys, w = want[n]
+                    for plan in (("optimized", t, 2, -1), ("optimized", t, 10, 2)):
+                        assert B.bitonic_plan_shapes(n, "keys32", plan)[0]["q"] == \
+                            min(s, max(1, (n - 1).bit_length()))
+                        for asc in (True, False):
+                            print(f"[case] sort_tile={s} phase_merge={pm} plan={plan} n={n} "
+                                  f"asc={asc}", flush=True)
+                            got = gpu_sort(keys, asc, plan)
+                            assert np.array_equal(got, w if asc else w[::-1]), (s, pm, plan, n, asc)
+    finally:
+        B.bitonic_set_tuning_value("sort_tile_log2", saved)
+        B.bitonic_set_tuning_value("phase_merge", saved_pm)
+
+
+def test_sort_tile_per_phase_states():
+    """Per-phase states with 2^15-key tile sorts ahead of 2^11-key merges
+    (n = 2^19): the state after every phase from the tile sort's last on
+    equals the oracle network's."""
+    n = 1 << 19
+    keys = W.uniform_i32(83, n)
+    states = {}
+    O.bitonic_i32(keys, True, O.FLIP_VIRTUAL,
+                  hook=lambda p, s, x: states.__setitem__(p, x) if s == p else None)
+    saved = B.bitonic_get_tuning_value("sort_tile_log2")
+    try:
+        B.bitonic_set_tuning_value("sort_tile_log2", 15)
+        for plan in (("optimized", 11, 3), ("optimized", 14, 10)):
+            for p in range(15, 20):
+                print(f"[case] per-phase sort_tile=15 plan={plan} p={p}", flush=True)
+                t = torch.from_numpy(keys.copy()).cuda()
+                B.bitonic_network_phases_i32(t, p, True, plan)
+                torch.cuda.synchronize()
+                assert np.array_equal(t.cpu().numpy(), states[p]), (plan, p)
+    finally:
+        B.bitonic_set_tuning_value("sort_tile_log2", saved)
+
+
+def test_sort_tile_full_size():
+    """The 2^24-key bucket with 2^15-key tile sorts (as the plan table may
+    choose): n = 2^24 and n = 10,000,000 (virtual padding), both
+    directions, bit-exact against the oracle."""
+    saved = B.bitonic_get_tuning_value("sort_tile_log2@24")
+    try:
+        B.bitonic_set_tuning_value("sort_tile_log2@24", 15)
+        for n in (1 << 24, 10_000_000):
+            keys = W.uniform_i32(W.SEED_BASE + 2 + n, n)
+            w = O.sort_i32(keys, True)
+            assert B.bitonic_plan_shapes(n, "keys32", None)[0]["q"] == 15
+            for asc in (True, False):
+                print(f"[case] sort_tile@24=15 n={n} asc={asc}", flush=True)
+                got = gpu_sort(keys, asc)
+                assert np.array_equal(got, w if asc else w[::-1]), (n, asc)
+    finally:
+        B.bitonic_set_tuning_value("sort_tile_log2@24", saved)
+
+
 @pytest.mark.parametrize("t", [11, 12, 13, 14])
 def test_phase_merge(t):
     """Phase t + 1 as one launch on 2^(t+1)-key tiles (the tile phase), on
