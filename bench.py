@@ -597,6 +597,7 @@ def main():
         log(f"[bench] counters run done: copy of {4 * n} bytes, 3 sorts of n={n}")
         return
     passes = B.bitonic_plan_passes(n, plan)
+    shapes = B.bitonic_plan_shapes(n, "keys32", plan)
     log(f"[bench] n={n} passes={passes}; timing {args.steps} steps after {args.warmup} warm-up")
     ms, wall, ok = time_sorts(torch, B, src, args.steps, args.warmup, plan)
     gkeys = n / (ms * 1e-3) / 1e9
@@ -676,8 +677,10 @@ def main():
                                    "(seeded SplitMix64), ascending, device-resident; "
                                    "plus n=10,000,000 in extra",
                        "n": n, "plan": {"kind": "optimized",
+                                        "sort_tile_log2": shapes[0]["q"],
                                         "tile_log2": B.bitonic_plan_tile_log2(n, plan),
-                                        "fuse": args.fuse or B.bitonic_get_tuning_value("fuse")},
+                                        "fuse": max((x["fuse"] for x in shapes
+                                                     if x["kind"] == "global_pass"), default=0)},
                        "passes": passes, "parallelism": "single GPU",
                        "tuning": tuning},
             "roofline": roofline, "cpu_baseline": cpu, "extra": extra}

@@ -16,19 +16,20 @@ sections 4.1 and 4.2):
                          launch fewer, a longer tile sort), per bucket from
                          2^20 up where it is 0.3 % faster
   lane_pass              how passes of eight to ten steps split columns
-                         over lanes or waves (7, 8 or 9), by the summed time
-                         of the tuned plans of the buckets from 2^22 up, then
-                         per bucket ("lane_pass@k") where another mode is
-                         1 % faster
+                         over lanes or waves (7, 8 or 9), by the tuned plans
+                         of the buckets from 2^22 up (their times relative to
+                         each bucket's best mode, averaged), then per bucket
+                         ("lane_pass@k") where another mode is 1 % faster
   phase_blocks_per_cu    workgroups of the tile phase (phase t+1 in one
                          launch) per compute unit, -1, 1, 2 or 4, by the
-                         summed time of the tuned plans from 2^20 up
+                         tuned plans from 2^20 up (relative times, averaged)
   segmented sort (the 8192-segment batched workload, and a table of 64
   segments of the serving workload's lengths, 2^8 .. 2^22 keys)
     seg_blocks_per_cu       small-segment kernel workgroups per compute unit
     seg_pass_blocks_per_cu  big-segment pass workgroups per compute unit
     seg_fuse                steps per big-segment pass (3 .. 5)
-  8-byte sorts (int64 keys at n = 2^24)
+  8-byte sorts (int64 keys and int32 (key, value) pairs at n = 2^24, by
+  their summed time)
     wide_tile_log2, wide_fuse
 Every candidate is timed with HIP events over fresh copies of the same seeded
 input (median of `reps` runs) and its output checked sorted.  The winners are
@@ -141,37 +142,39 @@ def tune(buckets=(16, 18, 20, 22, 24, 26, 28), reps: int = 5, quick: bool = Fals
                               "ms": round(ms, 4), "default_ms": round(default_ms, 4)}
         log(json.dumps({"bucket": k, "best": best["buckets"][k]}))
         del src, buf
-    def bucket_total(lo):
-        total = 0.0
+    def bucket_times(lo):
+        times = {}
         for k, e in best["buckets"].items():
             if k < lo:
                 continue
             src = torch.empty(1 << k, dtype=torch.int32, device="cuda")
             B.bitonic_keygen_i32(src, W.SEED_BASE + k)
             buf = torch.empty_like(src)
-            total += _time_plain(torch, src, buf, ("optimized", e["tile_log2"], e["fuse"],
-                                                   e["merge_blocks_per_cu"]), reps)
+            times[k] = _time_plain(torch, src, buf, ("optimized", e["tile_log2"], e["fuse"],
+                                                     e["merge_blocks_per_cu"]), reps)
             del src, buf
-        return total
+        return times
 
-    phases = []
-    for pb in ((1,) if quick else (-1, 1, 2, 4)):
-        B.bitonic_set_tuning_value("phase_blocks_per_cu", pb)
-        total = bucket_total(20)
-        phases.append((total, pb))
-        log(json.dumps({"phase_blocks_per_cu": pb, "ms_buckets_20_up": round(total, 4)}))
-    phases.sort()
-    B.bitonic_set_tuning_value("phase_blocks_per_cu", phases[0][1])
-    best["phase_blocks_per_cu"] = phases[0][1]
-    lanes = []
-    for mode in (7, 8):
-        B.bitonic_set_tuning_value("lane_pass", mode)
-        total = bucket_total(22)
-        lanes.append((total, mode))
-        log(json.dumps({"lane_pass": mode, "ms_buckets_22_up": round(total, 4)}))
-    lanes.sort()
-    B.bitonic_set_tuning_value("lane_pass", lanes[0][1])
-    best["lane_pass"] = lanes[0][1]
+    def pick_global(name, values, lo):
+        """The value of a global knob whose tuned plans of the buckets from
+        2^lo up are fastest on average relative to each bucket's best value
+        (every bucket weighs the same, not the largest's milliseconds)."""
+        times = {}
+        for v in values:
+            B.bitonic_set_tuning_value(name, v)
+            times[v] = bucket_times(lo)
+        rel = {v: statistics.mean(times[v][k] / min(times[u][k] for u in values)
+                                  for k in times[v]) for v in values}
+        for v in values:
+            log(json.dumps({name: v, f"ms_buckets_{lo}_up": round(sum(times[v].values()), 4),
+                            "mean_over_best": round(rel[v], 5)}))
+        v = min(values, key=rel.get)
+        B.bitonic_set_tuning_value(name, v)
+        return v
+
+    best["phase_blocks_per_cu"] = pick_global("phase_blocks_per_cu",
+                                              (1,) if quick else (-1, 1, 2, 4), 20)
+    best["lane_pass"] = pick_global("lane_pass", (7, 8), 22)
     # and per bucket from 2^22 up: a bucket entry where another mode beats
     # the global one by 1 % or more
     for k, e in best["buckets"].items():
@@ -238,6 +241,14 @@ def tune(buckets=(16, 18, 20, 22, 24, 26, 28), reps: int = 5, quick: bool = Fals
     n = 1 << 24
     k64 = torch.from_numpy(W.uniform_i64(W.SEED_BASE + 2, n)).cuda()
     buf = torch.empty_like(k64)
+    k32 = torch.from_numpy(W.uniform_i32(W.SEED_BASE + 2, n)).cuda()
+    v32 = torch.arange(n, dtype=torch.int32, device="cuda")
+    kbuf, vbuf = torch.empty_like(k32), torch.empty_like(v32)
+
+    def reset_pairs():
+        kbuf.copy_(k32)
+        vbuf.copy_(v32)
+
     wide = []
     for t, f in itertools.product((13,) if quick else (11, 12, 13), (8,) if quick else (5, 6, 7, 8)):
         plan = ("optimized", t, f)
@@ -245,8 +256,15 @@ def tune(buckets=(16, 18, 20, 22, 24, 26, 28), reps: int = 5, quick: bool = Fals
                         lambda: B.bitonic_sort_wide_plan(buf, None, True, "int64", plan), reps)
         if not bool((buf[1:] >= buf[:-1]).all().item()):
             raise RuntimeError(f"8-byte plan {plan} produced unsorted output")
-        wide.append((ms, t, f))
-        log(json.dumps({"wide_tile_log2": t, "wide_fuse": f, "ms": round(ms, 4)}))
+        ms_pairs = _median_ms(torch, reset_pairs,
+                              lambda: B.bitonic_sort_wide_plan(kbuf, vbuf, True, "int32", plan),
+                              reps)
+        if not bool((kbuf[1:] >= kbuf[:-1]).all().item()):
+            raise RuntimeError(f"8-byte plan {plan} produced unsorted pairs")
+        # int64 keys and (key, value) pairs weigh the same
+        wide.append((ms + ms_pairs, t, f))
+        log(json.dumps({"wide_tile_log2": t, "wide_fuse": f, "ms": round(ms, 4),
+                        "ms_pairs": round(ms_pairs, 4)}))
     wide.sort()
     best.update({"wide_tile_log2": wide[0][1], "wide_fuse": wide[0][2],
                  "wide_ms": round(wide[0][0], 4)})
