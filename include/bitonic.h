@@ -465,8 +465,8 @@ int bitonic_sort_plan_launches_i32(int32_t* keys, int64_t n, int ascending,
  * optimized plan's tile 2^t, the tile sort takes 2^s-key tiles, phases
  * 1..s in one launch, and every later phase passes down to stride 2^t and
  * merges 2^t-key tiles -- one launch fewer than tiles of 2^t with the tile
- * phase, for a longer tile sort; applies to explicit optimized plans too,
- * not to arrays off a 16-byte boundary),
+ * phase, for a longer tile sort; for n a power of two on a 16-byte
+ * boundary, with explicit optimized plans too),
  * "wide_tile_log2" (11..13) or
  * "wide_fuse" (1..8) (the 8-byte sorts' plan); bitonic_get_tuning_value
  * reads one.

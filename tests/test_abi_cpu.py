@@ -500,10 +500,11 @@ def _closed_form_sort_tile(k, t, f, s, phase=True):
 
 
 def test_sort_tile(lib):
-    """A tile-sort tile larger than the merge tile ("sort_tile_log2"): the
-    tile sort takes phases 1..s, every later phase's passes cover its strides
-    from 2^(p-1) down to the merge tile 2^t, each once, and its merge the
-    rest; an array off a 16-byte boundary keeps its scalar-access plan."""
+    """A tile-sort tile larger than the merge tile ("sort_tile_log2"): for
+    n a power of two the tile sort takes phases 1..s, every later phase's
+    passes cover its strides from 2^(p-1) down to the merge tile 2^t, each
+    once, and its merge the rest; other sizes, and arrays off a 16-byte
+    boundary, keep the plan's tile."""
     saved = B.bitonic_get_tuning_value("sort_tile_log2")
     saved24 = B.bitonic_get_tuning_value("sort_tile_log2@24")
     try:
@@ -521,10 +522,11 @@ def test_sort_tile(lib):
                     for k in range(1, 32):
                         assert B.bitonic_plan_passes(2**k, plan) == \
                             _closed_form_sort_tile(k, t, f, max(s, t)), (s, t, f, k)
-                    for n in (2**24, 2**24 - 1, 10**7, 2**s + 5, 2**31):
+                    for n in (2**24, 2**24 - 1, 10**7, 2**s + 5, 2**31, 2**(s - 1)):
                         sh = B.bitonic_plan_shapes(n, "keys32", plan)
                         k = _ceil_log2(n)
-                        ls = max(s, t)
+                        # a larger tile sort only for powers of two
+                        ls = max(s, t) if n & (n - 1) == 0 else t
                         assert sh[0]["kind"] == "tile_sort" and sh[0]["q"] == min(ls, k)
                         i, p = 1, ls + 1
                         while i < len(sh):   # one phase: passes, then its merge

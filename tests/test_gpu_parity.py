@@ -193,10 +193,11 @@ def test_per_phase_states_lane_passes(plan, mode):
 @pytest.mark.parametrize("s", [12, 13, 14, 15])
 def test_sort_tile(s):
     """A tile sort of 2^s-key tiles ahead of 2^t-key merges (t < s, tuning
-    value "sort_tile_log2"): every such pair, short and ten-step passes,
-    with the tile phase on and off, as the whole sort (n <= 2^s), at powers
-    of two and with ragged tails, looping and one-tile merge workgroups,
-    both directions, bit-exact against the oracle."""
+    value "sort_tile_log2", powers of two): every such pair, short and
+    ten-step passes, with the tile phase on and off, at powers of two (the
+    larger tile sort) and with ragged tails (the plan's tile), looping and
+    one-tile merge workgroups, both directions, bit-exact against the
+    oracle."""
     saved = B.bitonic_get_tuning_value("sort_tile_log2")
     saved_pm = B.bitonic_get_tuning_value("phase_merge")
     want = {}
@@ -205,14 +206,16 @@ def test_sort_tile(s):
         for pm in (1, 0):
             B.bitonic_set_tuning_value("phase_merge", pm)
             for t in range(11, s):
-                for n in ((1 << s) - 7, 1 << (s + 1), (1 << (s + 2)) + 4099, 1 << (s + 4)):
+                for n in ((1 << s) - 7, 1 << s, 1 << (s + 1), (1 << (s + 2)) + 4099,
+                          1 << (s + 4)):
                     if n not in want:
                         keys = W.uniform_i32(W.SEED_BASE + 91 * s + n, n)
                         want[n] = (keys, O.sort_i32(keys, True))
                     keys, w = want[n]
                     for plan in (("optimized", t, 2, -1), ("optimized", t, 10, 2)):
+                        pow2 = n & (n - 1) == 0
                         assert B.bitonic_plan_shapes(n, "keys32", plan)[0]["q"] == \
-                            min(s, max(1, (n - 1).bit_length()))
+                            min(s if pow2 else t, max(1, (n - 1).bit_length()))
                         for asc in (True, False):
                             print(f"[case] sort_tile={s} phase_merge={pm} plan={plan} n={n} "
                                   f"asc={asc}", flush=True)
@@ -248,15 +251,17 @@ def test_sort_tile_per_phase_states():
 
 def test_sort_tile_full_size():
     """The 2^24-key bucket with 2^15-key tile sorts (as the plan table may
-    choose): n = 2^24 and n = 10,000,000 (virtual padding), both
-    directions, bit-exact against the oracle."""
+    choose): n = 2^24, and n = 10,000,000 (virtual padding), which keeps
+    the plan's 2^14-key tile sort, both directions, bit-exact against the
+    oracle."""
     saved = B.bitonic_get_tuning_value("sort_tile_log2@24")
     try:
         B.bitonic_set_tuning_value("sort_tile_log2@24", 15)
         for n in (1 << 24, 10_000_000):
             keys = W.uniform_i32(W.SEED_BASE + 2 + n, n)
             w = O.sort_i32(keys, True)
-            assert B.bitonic_plan_shapes(n, "keys32", None)[0]["q"] == 15
+            assert B.bitonic_plan_shapes(n, "keys32", None)[0]["q"] == \
+                (15 if n == 1 << 24 else B.bitonic_plan_tile_log2(n))
             for asc in (True, False):
                 print(f"[case] sort_tile@24=15 n={n} asc={asc}", flush=True)
                 got = gpu_sort(keys, asc)
