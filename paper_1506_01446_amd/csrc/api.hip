@@ -175,8 +175,6 @@ struct Observer {
   int64_t count = INT64_MAX;
 };
 
-// Enqueue (or, with count_only, just count) the launches for phases 1..K of
-// the network over keys[0, n).
 // Keys per lane (log2) of an f-step lane pass under lane-pass mode `mode`
 // (g_lane_pass), or 0 for a register pass; negative: the column spread over
 // the four waves of a workgroup (column_waves_pass_kernel) with 2^-fr keys
@@ -188,6 +186,8 @@ static int lane_pass_regs(int mode, int f) {
   return 0;
 }
 
+// Enqueue (or, with count_only, just count) the launches for phases 1..K of
+// the network over keys[0, n).
 static int64_t enqueue_plain(int32_t* keys, uint32_t n, int K, Codec flip, const Resolved& r,
                              hipStream_t st, bool count_only, Observer* obs = nullptr) {
   const int k = ceil_log2(n);
