@@ -291,7 +291,9 @@ def write_tuning(path: str, best: dict, command: str = "") -> None:
                 f.write(f"{name} {best[name]}\n")
         for k, e in sorted(best.get("buckets", {}).items()):
             f.write(f"# n = 2^{k}: {e['ms']} ms tuned, {e['default_ms']} ms with the built-in plan\n")
-            if e["ms"] < 0.99 * e["default_ms"]:   # a bucket entry only where it pays
+            # a bucket's plan entries only where they pay, or where a lane
+            # mode or tile-sort tile was timed with that plan for the bucket
+            if e["ms"] < 0.99 * e["default_ms"] or "lane_pass" in e or "sort_tile_log2" in e:
                 for name in ("tile_log2", "fuse", "merge_blocks_per_cu"):
                     f.write(f"{name}@{k} {e[name]}\n")
             if "lane_pass" in e:
