@@ -265,14 +265,17 @@ static int64_t enqueue_plain(int32_t* keys, uint32_t n, int K, Codec flip, const
   // tiles (Ls >= L).
   const int L = r.tile;
   const int Ls = r.sort_tile;
-  // Eight fused steps only when n is a power of two: otherwise the block of
-  // a pass that straddles n takes the bounds-checked eight-step kernel, which
-  // runs out of registers, so such sorts use at most seven.
-  const int fuse = (r.fuse > kFuseMaxRagged && (n & (n - 1)) != 0) ? kFuseMaxRagged : r.fuse;
-  // Passes of more than kFuseMaxColumn steps split each column over lanes;
-  // they need whole blocks and lane byte offsets below 2^32 (lane_pass_fits):
-  // aligned power-of-two arrays, phases up to 30.
-  const bool lanes_ok = r.lane_pass != 0 && !r.scalar_io && (n & (n - 1)) == 0;
+  // Passes of more than kFuseMaxColumn steps split each column over lanes
+  // (or waves); they need lane byte offsets below 2^32 (lane_pass_fits):
+  // arrays on a 16-byte boundary, phases up to 30.  When n is not a power of
+  // two the block of a pass that straddles n is bounds-checked: the lane
+  // passes (lane mode 7's mapping, since the wave passes need whole blocks)
+  // take eight to ten steps, while the one-column pass would take eight
+  // only with more registers than it has, so without lane passes such sorts
+  // use at most seven.
+  const bool ragged = (n & (n - 1)) != 0;
+  const bool lanes_ok = r.lane_pass != 0 && !r.scalar_io;
+  const int lane_mode = ragged ? 7 : r.lane_pass;
   emit(tile_shape(BITONIC_LAUNCH_TILE_SORT, Ls), [&] {
     if (r.scalar_io)
       launch_tile_scalar(0, keys, n, flip, CX_ENC, st);
@@ -288,7 +291,8 @@ static int64_t enqueue_plain(int32_t* keys, uint32_t n, int K, Codec flip, const
       continue;
     }
     const bool lanes = lanes_ok && p <= 30;
-    const int fz = lanes || fuse < kFuseMaxColumn ? fuse : kFuseMaxColumn;
+    const int cap = lanes ? kFuseMax : (ragged ? kFuseMaxRagged : kFuseMaxColumn);
+    const int fz = r.fuse < cap ? r.fuse : cap;
     const int nb = p - L;                          // long-stride steps
     const int npass = (nb + fz - 1) / fz;          // fused HBM passes
     int top = p - 1;
@@ -300,7 +304,7 @@ static int64_t enqueue_plain(int32_t* keys, uint32_t n, int K, Codec flip, const
       const int left = top - L + 1;                // bits still to do
       const int passes_left = npass - i;
       const int f = fz < left - (passes_left - 1) ? fz : left - (passes_left - 1);
-      const int fr = lanes ? lane_pass_regs(r.lane_pass, f) : 0;
+      const int fr = lanes ? lane_pass_regs(lane_mode, f) : 0;
       const int q = top - f + 1;
       // the four-column passes (f <= 5, aligned) form 32-bit byte offsets
       // below 2^(q+2); the one-column passes follow column_pass_offset_bits

@@ -196,11 +196,15 @@ namespace bitonic {
 // R_s = 2^F - (s - 2^(G-1) + 1) 2^FR, again ascending, so the mirror step
 // pairs register j of lane s with register 2^FR-1-j of lane s XOR 2^(G-1),
 // and in every later step the lower register of a pair holds the lower
-// index.  Whole blocks only (n a multiple of 2^(q+F)), lane byte offsets
-// below 2^(q+F+2) <= 2^32.  A wave's access to one register row is two (G
-// = 1) or four (G = 2) runs of consecutive keys.
+// index.  Lane byte offsets below 2^(q+F+2) <= 2^32.  The last block may
+// end past n (virtual padding): its workgroups load the keys at indices
+// n and up as the sentinel and do not store them (exec-masked accesses), so
+// every block start is below n and every index below 2^31.  A wave's access
+// to one register row is two (G = 1) or four (G = 2) runs of consecutive
+// keys.
 template <int FR, int G, bool MIRROR>
-__global__ __launch_bounds__(256) void column_lanes_pass_kernel(int32_t* __restrict__ keys, int q) {
+__global__ __launch_bounds__(256) void column_lanes_pass_kernel(int32_t* __restrict__ keys, int q,
+                                                                uint32_t n) {
   constexpr int F = FR + G;
   constexpr int M = 1 << FR;
   constexpr uint32_t SUBS = 1u << G;
@@ -216,10 +220,18 @@ __global__ __launch_bounds__(256) void column_lanes_pass_kernel(int32_t* __restr
   const uint32_t colx = upper ? ((1u << q) - 1u) - col : col;
   const uint32_t row0 = upper ? (1u << F) - (s - HALF + 1u) * (uint32_t)M : s * (uint32_t)M;
   const uint32_t off = ((row0 << q) + colx) * 4u;               // lane byte offset
-  static_for<0, M>([&](auto J) {
-    const uint32_t r0 = bs + ((uint32_t)J << q);                // uniform row start
-    x[J] = Keys32{keys}.at(r0).getb(off);
-  });
+  const bool whole = bs + (1u << (q + F)) <= n;                 // uniform
+  if (whole) {
+    static_for<0, M>([&](auto J) {
+      const uint32_t r0 = bs + ((uint32_t)J << q);              // uniform row start
+      x[J] = Keys32{keys}.at(r0).getb(off);
+    });
+  } else {
+    static_for<0, M>([&](auto J) {
+      const uint32_t r0 = bs + ((uint32_t)J << q);
+      x[J] = r0 + (off >> 2) < n ? Keys32{keys}.at(r0).getb(off) : kPad;
+    });
+  }
   __builtin_amdgcn_sched_barrier(0);
   if constexpr (MIRROR) {
     // the lower half of the column's lanes keeps the minimum of each pair
@@ -249,11 +261,18 @@ __global__ __launch_bounds__(256) void column_lanes_pass_kernel(int32_t* __restr
   // column_pass_kernel)
   uint32_t bs_st = bs;
   asm volatile("" : "+s"(bs_st));
-  static_for<0, M>([&](auto J) {
-    const uint32_t r0 = bs_st + ((uint32_t)J << q);
-    Keys32{keys}.at(r0).putb(off, x[J]);
-    __builtin_amdgcn_sched_barrier(0);
-  });
+  if (whole) {
+    static_for<0, M>([&](auto J) {
+      const uint32_t r0 = bs_st + ((uint32_t)J << q);
+      Keys32{keys}.at(r0).putb(off, x[J]);
+      __builtin_amdgcn_sched_barrier(0);
+    });
+  } else {
+    static_for<0, M>([&](auto J) {
+      const uint32_t r0 = bs_st + ((uint32_t)J << q);
+      if (r0 + (off >> 2) < n) Keys32{keys}.at(r0).putb(off, x[J]);
+    });
+  }
 }
 
 // F = FR + 2 steps on index bits q+F-1 .. q of 4-byte keys with every
@@ -271,7 +290,7 @@ __global__ __launch_bounds__(256) void column_lanes_pass_kernel(int32_t* __restr
 // of each, writes them back, and reads its own again.  The other FR steps
 // run in registers; the mirrored waves, whose rows descend, hold their keys
 // complemented meanwhile (~ reverses the signed order), so the same
-// ascending steps serve every wave.  Whole blocks only, as the lane passes.
+// ascending steps serve every wave.  Whole blocks only (wave_pass_fits).
 template <int FR, bool MIRROR>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, FR >= 8 ? 1 : 2)))
 void column_waves_pass_kernel(int32_t* __restrict__ keys, int q) {
@@ -343,11 +362,15 @@ static void launch_column_waves_F(bool mirror, int32_t* keys, uint32_t n, int q,
 
 template <int FR, int G>
 static void launch_column_lanes_FG(bool mirror, int32_t* keys, uint32_t n, int q, hipStream_t st) {
-  const uint32_t blocks = n >> (FR + 8);  // n / 2^FR threads, 256 per workgroup
+  // the 2^(q+F)-key blocks that start below n, 2^(q+G) threads each, 256
+  // per workgroup
+  constexpr int F = FR + G;
+  const uint32_t nblocks = (uint32_t)(((uint64_t)n + (1u << (q + F)) - 1u) >> (q + F));
+  const uint32_t blocks = nblocks << (q + G - 8);
   if (mirror)
-    column_lanes_pass_kernel<FR, G, true><<<blocks, 256, 0, st>>>(keys, q);
+    column_lanes_pass_kernel<FR, G, true><<<blocks, 256, 0, st>>>(keys, q, n);
   else
-    column_lanes_pass_kernel<FR, G, false><<<blocks, 256, 0, st>>>(keys, q);
+    column_lanes_pass_kernel<FR, G, false><<<blocks, 256, 0, st>>>(keys, q, n);
 }
 
 }  // namespace bitonic

@@ -11,6 +11,7 @@ bool launch_column_lanes_pass8(int f, bool waves, bool mirror, int32_t* keys, ui
 bool launch_column_lanes_pass(int f, int fr, bool mirror, int32_t* keys, uint32_t n, int q,
                               hipStream_t st) {
   if (!lane_pass_fits(n, q, f)) return false;
+  if (fr < 0 && !wave_pass_fits(n, q, f)) return false;
   if (fr == 8 || fr == -8) return launch_column_lanes_pass8(f, fr < 0, mirror, keys, n, q, st);
   if (fr == -7) {  // four waves per column (f = 9)
     if (f != 9) return false;

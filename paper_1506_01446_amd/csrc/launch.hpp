@@ -46,13 +46,16 @@ void launch_global_pass(int f, bool mirror, int32_t* keys, uint32_t n, int q, hi
 void launch_column_pass_i32(int f, bool mirror, int32_t* keys, uint32_t n, int q, hipStream_t st);
 
 // Lane passes (column_lanes_pass_kernel): f = fr + g steps, each column split
-// over 2^g lanes of 2^fr keys; (fr, g) in {7, 8} x {1, 2}; fr = -7, -8: the
-// column over the four waves of a workgroup instead (column_waves_pass_kernel,
-// f = 9, 10).  Needs n a
-// multiple of 2^(q+f) and q + f <= 30 (lane_pass_fits); false (nothing
-// launched) for any other shape.
+// over 2^g lanes of 2^fr keys; (fr, g) in {7, 8} x {1, 2}; any n, the last
+// block padded virtually (lane_pass_fits).  fr = -7, -8: the column over the
+// four waves of a workgroup instead (column_waves_pass_kernel, f = 9, 10),
+// whole blocks only: n a multiple of 2^(q+f) (wave_pass_fits).  Both need
+// q + f <= 30.  False (nothing launched) for any other shape.
 constexpr bool lane_pass_fits(uint32_t n, int q, int f) {
-  return q + f <= 30 && q >= 8 && n != 0 && (n & ((uint32_t(1) << (q + f)) - 1u)) == 0;
+  return q + f <= 30 && q >= 8 && n != 0;
+}
+constexpr bool wave_pass_fits(uint32_t n, int q, int f) {
+  return lane_pass_fits(n, q, f) && (n & ((uint32_t(1) << (q + f)) - 1u)) == 0;
 }
 bool launch_column_lanes_pass(int f, int fr, bool mirror, int32_t* keys, uint32_t n, int q,
                               hipStream_t st);

@@ -92,16 +92,19 @@ def test_wide_argument_errors_are_synchronous(lib):
     assert lib.bitonic_set_tuning_value(b"wide_fuse", 0) == -1
 
 
-def _closed_form_optimized(k, t, f, phase=True):
-    """Launches of the optimized plan on n = 2^k: the tile sort, then per
-    phase p > t its ceil((p - t) / f) passes and one merge; passes of more
-    than eight steps (columns split over lanes) only up to phase 30; with
-    `phase` (16-byte aligned keys, t <= 14) phase t + 1 is one launch."""
+def _closed_form_optimized(k, t, f, phase=True, ragged=False):
+    """Launches of the optimized plan on n = 2^k (or, `ragged`, a size that
+    pads to 2^k): the tile sort, then per phase p > t its ceil((p - t) / f)
+    passes and one merge; passes of more than eight steps (columns split
+    over lanes) only up to phase 30, above it at most eight steps (seven
+    for a ragged size); with `phase` (16-byte aligned keys, t <= 14) phase
+    t + 1 is one launch."""
     if k <= 1:
         return k
     if k <= t:
         return 1
-    return 1 + sum(-(-(p - t) // (f if f <= 8 or p <= 30 else 8)) + 1
+    cap = 7 if ragged else 8
+    return 1 + sum(-(-(p - t) // (f if f <= cap or p <= 30 else cap)) + 1
                    for p in range(t + 1, k + 1)) - (1 if phase and t <= 14 else 0)
 
 
@@ -112,11 +115,11 @@ def test_optimized_pass_count(lib, t, f):
         n = 2**k
         got = B.bitonic_plan_passes(n, ("optimized", t, f))
         assert got == _closed_form_optimized(k, t, f), (k, t, f)
-        # a non-power-of-two n makes the launches of its padded size, with at
-        # most seven fused steps
+        # a non-power-of-two n makes the launches of its padded size, its
+        # passes of eight to ten steps as lane passes up to phase 30
         if k >= 2:
             assert B.bitonic_plan_passes(n - 1, ("optimized", t, f)) == \
-                _closed_form_optimized(k, t, min(f, 7)), (k, t, f)
+                _closed_form_optimized(k, t, f, ragged=True), (k, t, f)
 
 
 def _closed_form_wide(k, t, f, phase, pow2=True):
@@ -280,9 +283,13 @@ def _check_shapes(shapes, n, elem_bytes, wide=False):
             # an 8-byte lane pass: whole blocks, lane offsets of 8-byte units
             assert n == 1 << k and (1 << (s["q"] + s["fuse"])) * 8 <= 2 ** 32, (n, s)
         if s["kind"] == "global_pass" and s["fuse"] > 8:
-            # a lane pass: whole blocks, its lane byte offsets span the block
-            assert elem_bytes == 4 and n == 1 << k, (n, s)
+            # a lane pass: its lane byte offsets span the block (the last
+            # block of a ragged size padded virtually)
+            assert elem_bytes == 4 and s["q"] + s["fuse"] <= 30, (n, s)
             assert (1 << (s["q"] + s["fuse"])) * 4 <= 2 ** s["offset_bits"], (n, s)
+        if s["kind"] == "global_pass" and s["fuse"] > 7 and n != 1 << k:
+            # a ragged size's eight-step passes are lane passes too
+            assert s["q"] + s["fuse"] <= 30, (n, s)
 
 
 @pytest.mark.parametrize("layout", ["keys32", "keys32_unaligned"])
@@ -459,8 +466,9 @@ def test_autotune_summary(lib, tmp_path):
 
 def test_lane_pass_modes(lib):
     """Passes of nine and ten steps exist only with lane passes on, for
-    power-of-two arrays on a 16-byte boundary; off, or for other arrays,
-    a pass takes at most eight steps (seven for other sizes)."""
+    arrays on a 16-byte boundary (a ragged size's lane passes are all
+    column-over-lanes ones, whatever the mode); off, or for other arrays, a
+    pass takes at most eight steps (seven for ragged sizes)."""
     saved = B.bitonic_get_tuning_value("lane_pass")
     try:
         for bad in (1, 6, 10, -1):
@@ -479,8 +487,12 @@ def test_lane_pass_modes(lib):
                     2**24, "keys32_unaligned", ("optimized", 14, f))
                     if s["kind"] == "global_pass") == 8
                 assert B.bitonic_plan_passes(2**24 - 1, ("optimized", 14, f)) == \
-                    _closed_form_optimized(24, 14, 7)
+                    _closed_form_optimized(24, 14, f, ragged=True)
+                assert max(s["fuse"] for s in B.bitonic_plan_shapes(
+                    10**7, "keys32", ("optimized", 14, f)) if s["kind"] == "global_pass") == f
         B.bitonic_set_tuning_value("lane_pass", 0)
+        assert B.bitonic_plan_passes(2**24 - 1, ("optimized", 14, 10)) == \
+            _closed_form_optimized(24, 14, 7, ragged=True)
         assert B.bitonic_plan_passes(2**24, ("optimized", 14, 10)) == \
             _closed_form_optimized(24, 14, 8)
     finally:

@@ -167,6 +167,55 @@ def test_lane_passes(mode):
 
 
 @pytest.mark.parametrize("mode", [7, 9])
+def test_lane_passes_ragged(mode):
+    """Lane passes over sizes that are not powers of two (the last block of
+    each pass padded virtually: keys past n read as the sentinel, never
+    stored): eight- to ten-step passes at every tile size, sizes just under
+    a power of two, just over one, and in between, both directions."""
+    saved = B.bitonic_get_tuning_value("lane_pass")
+    want = {}
+    try:
+        B.bitonic_set_tuning_value("lane_pass", mode)
+        for t in (11, 13, 14):
+            for n in ((1 << (t + 10)) - 3, (1 << (t + 9)) + 12345, 3 * (1 << (t + 8)) + 7):
+                if n > 1 << 24:
+                    continue
+                if n not in want:
+                    keys = W.uniform_i32(W.SEED_BASE + 500 + n % 997, n)
+                    want[n] = (keys, O.sort_i32(keys, True))
+                keys, w = want[n]
+                for f in (8, 9, 10):
+                    plan = ("optimized", t, f)
+                    sh = B.bitonic_plan_shapes(n, "keys32", plan)
+                    assert max(s["fuse"] for s in sh if s["kind"] == "global_pass") == \
+                        min(f, (n - 1).bit_length() - t)
+                    for asc in (True, False):
+                        print(f"[case] ragged lane_pass={mode} plan={plan} n={n} asc={asc}",
+                              flush=True)
+                        got = gpu_sort(keys, asc, plan)
+                        assert np.array_equal(got, w if asc else w[::-1]), (mode, plan, n, asc)
+    finally:
+        B.bitonic_set_tuning_value("lane_pass", saved)
+
+
+def test_per_phase_states_ragged_lane_passes():
+    """Per-phase states through lane passes over a ragged size: n = 2^21 -
+    4099 with 2^11 tiles (phases 19..21 take eight- to ten-step passes whose
+    last block straddles n) equals the oracle's virtually padded network."""
+    n = (1 << 21) - 4099
+    keys = W.uniform_i32(81, n)
+    states = {}
+    O.bitonic_i32(keys, True, O.FLIP_VIRTUAL,
+                  hook=lambda p, s, x: states.__setitem__(p, x) if s == p else None)
+    for p in range(12, 22):
+        print(f"[case] per-phase ragged lane passes p={p}", flush=True)
+        t = torch.from_numpy(keys.copy()).cuda()
+        B.bitonic_network_phases_i32(t, p, True, ("optimized", 11, 10))
+        torch.cuda.synchronize()
+        assert np.array_equal(t.cpu().numpy(), states[p]), p
+
+
+@pytest.mark.parametrize("mode", [7, 9])
 @pytest.mark.parametrize("plan", [("optimized", 11, 10), ("optimized", 11, 9)],
                          ids=lambda p: "-".join(map(str, p)))
 def test_per_phase_states_lane_passes(plan, mode):
