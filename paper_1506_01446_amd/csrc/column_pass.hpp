@@ -93,8 +93,9 @@ struct Pairs {
 // row's address is a workgroup-uniform row start plus the lane's column (or
 // its mirror image) as a byte offset (32-bit wherever it fits), which keeps few vector
 // registers live.  BOUNDED == false: the whole block lies below n and nothing
-// is checked.  BOUNDED == true: indices >= n read as sentinels and are not
-// stored.  OFF64: the lane byte offsets are formed in 64 bits, for rows of
+// is checked.  BOUNDED == true: the workgroups of blocks wholly below n run
+// as unchecked, those of the block that straddles n read indices >= n as
+// sentinels and do not store them, so one launch covers any n.  OFF64: the lane byte offsets are formed in 64 bits, for rows of
 // 2^q elements of kUnit bytes that span more than 2^32 bytes (8-byte
 // elements at q = 30; see column_pass_offset_bits).
 template <int F, bool MIRROR, bool BOUNDED, class ST, bool OFF64 = false>
@@ -108,22 +109,30 @@ __global__ __launch_bounds__(256) void column_pass_kernel(ST st, uint32_t n, int
   const uint32_t bs = (gw >> q) << (q + F);                   // uniform block start
   const uint32_t col = (gw + threadIdx.x) & ((1u << q) - 1u);
   const uint32_t mcol = ((1u << q) - 1u) - col;
+  // uniform: the block lies wholly below n (always, unless BOUNDED)
+  const bool whole = !BOUNDED || (uint64_t)bs + (1ull << (q + F)) <= (uint64_t)n;
   // the thread's lowest index is bs + col; its mirrored rows lie higher
-  if (BOUNDED && bs + col >= n) return;
+  if (BOUNDED && !whole && bs + col >= n) return;
   const Off off = (Off)col * ST::kUnit;                       // byte offsets, < 2^q kUnit
   const Off moff = (Off)mcol * ST::kUnit;
   auto row_of = [&](int rho) -> uint32_t {                    // uniform row
     return (MIRROR && (rho & TOP)) ? (uint32_t)(ROWS - 1 - (rho & (TOP - 1))) : (uint32_t)rho;
   };
-  static_for<0, ROWS>([&](auto RHO) {
-    constexpr bool mir = MIRROR && (RHO & TOP);
-    const uint32_t r0 = bs + (row_of(RHO) << q);              // uniform
-    if constexpr (BOUNDED) {
-      x[RHO] = r0 + (mir ? mcol : col) < n ? st.at(r0).getb(mir ? moff : off) : ST::kPadE;
-    } else {
-      x[RHO] = st.at(r0).getb(mir ? moff : off);
-    }
-  });
+  auto load_rows = [&](auto CHECK) {
+    static_for<0, ROWS>([&](auto RHO) {
+      constexpr bool mir = MIRROR && (RHO & TOP);
+      const uint32_t r0 = bs + (row_of(RHO) << q);            // uniform
+      if constexpr (decltype(CHECK)::value) {
+        x[RHO] = r0 + (mir ? mcol : col) < n ? st.at(r0).getb(mir ? moff : off) : ST::kPadE;
+      } else {
+        x[RHO] = st.at(r0).getb(mir ? moff : off);
+      }
+    });
+  };
+  if (whole)
+    load_rows(std::false_type{});
+  else if constexpr (BOUNDED)
+    load_rows(std::true_type{});
   __builtin_amdgcn_sched_barrier(0);
   pass_steps<F, MIRROR, 1>(x);
   __builtin_amdgcn_sched_barrier(0);
@@ -135,27 +144,35 @@ __global__ __launch_bounds__(256) void column_pass_kernel(ST st, uint32_t n, int
   // this way (more vector registers at the same occupancy) and keep theirs.
   uint32_t bs_st = bs;
   if constexpr (sizeof(E) == 4) asm volatile("" : "+s"(bs_st));
-  static_for<0, ROWS>([&](auto RHO) {
-    constexpr bool mir = MIRROR && (RHO & TOP);
-    const uint32_t r0 = bs_st + (row_of(RHO) << q);
-    if (!BOUNDED || r0 + (mir ? mcol : col) < n) st.at(r0).putb(mir ? moff : off, x[RHO]);
-    __builtin_amdgcn_sched_barrier(0);
-  });
+  auto store_rows = [&](auto CHECK) {
+    static_for<0, ROWS>([&](auto RHO) {
+      constexpr bool mir = MIRROR && (RHO & TOP);
+      const uint32_t r0 = bs_st + (row_of(RHO) << q);
+      if (!decltype(CHECK)::value || r0 + (mir ? mcol : col) < n)
+        st.at(r0).putb(mir ? moff : off, x[RHO]);
+      __builtin_amdgcn_sched_barrier(0);
+    });
+  };
+  if (whole)
+    store_rows(std::false_type{});
+  else if constexpr (BOUNDED)
+    store_rows(std::true_type{});
 }
 
 template <int F, bool MIRROR, class ST, bool OFF64>
 static void launch_column_pass_FMO(ST st, uint32_t n, int q, hipStream_t s) {
-  // 2^q threads per 2^(q+F) block: blocks wholly below n take the unchecked
-  // kernel, the block that straddles n (if any) the checked one
-  const uint64_t full = ((uint64_t)n >> (q + F)) << q;   // a multiple of 256 (q >= 8)
+  // 2^q threads per 2^(q+F) block (a multiple of 256, q >= 8): when every
+  // block lies below n the unchecked kernel, else one launch of the checked
+  // one, whose workgroups of whole blocks run unchecked
+  const uint64_t full = ((uint64_t)n >> (q + F)) << q;
   const uint64_t blocks = ((uint64_t)n + (1ull << (q + F)) - 1) >> (q + F);
   const uint64_t total = blocks << q;
-  if (full > 0)
+  if (total == full)
     column_pass_kernel<F, MIRROR, false, ST, OFF64><<<(uint32_t)(full / 256), 256, 0, s>>>(
         st, n, q, 0u);
-  if (total > full)
-    column_pass_kernel<F, MIRROR, true, ST, OFF64>
-        <<<(uint32_t)((total - full + 255) / 256), 256, 0, s>>>(st, n, q, (uint32_t)full);
+  else
+    column_pass_kernel<F, MIRROR, true, ST, OFF64><<<(uint32_t)(total / 256), 256, 0, s>>>(
+        st, n, q, 0u);
 }
 
 template <int F, bool MIRROR, class ST>

@@ -72,8 +72,10 @@ __device__ __forceinline__ void pass_store_row(const int32_t* x, int32_t* __rest
 // (block start + row offset, kept in scalar registers) plus one of two
 // per-lane 32-bit byte offsets (the column, or its mirror image), which keeps
 // the kernel to few vector registers.
-// BOUNDED == true: rows wholly below n move as vectors, a row that straddles
-// n goes key by key, rows at or past n are sentinels.
+// BOUNDED == true: the workgroups of blocks wholly below n run as above; in
+// the block that straddles n rows wholly below n move as vectors, a row that
+// straddles n goes key by key, rows at or past n are sentinels -- one launch
+// for any n.
 // A pass is never the first or last kernel of a sort, so keys are in the
 // sorting domain on both sides and no codec is applied.
 template <int F, bool MIRROR, bool BOUNDED>
@@ -81,8 +83,13 @@ __global__ __launch_bounds__(256) void global_pass_kernel(int32_t* __restrict__ 
                                                           int q, uint32_t g0) {
   constexpr int ROWS = 1 << F;
   constexpr int TOP = ROWS >> 1;
-  int32_t x[4 * ROWS];
-  if constexpr (!BOUNDED) {
+  bool whole = true;  // uniform: the workgroup's block lies wholly below n
+  if constexpr (BOUNDED)
+    whole = ((uint64_t)(((g0 + blockIdx.x * 256u) >> (q - 2)) + 1u) << (q + F)) <= (uint64_t)n;
+  // each path has its own key array: the checked path's may live in
+  // scratch memory, which must not pull the unchecked path's there too
+  if (whole) {
+    int32_t x[4 * ROWS];
     const uint32_t gw = g0 + blockIdx.x * 256u;            // uniform
     const uint32_t blk = gw >> (q - 2);                    // uniform block index
     int32_t* bp = keys + ((size_t)blk << (q + F));         // uniform block start
@@ -114,7 +121,8 @@ __global__ __launch_bounds__(256) void global_pass_kernel(int32_t* __restrict__ 
                                 x[4 * RHO + (rev ? 1 : 2)], x[4 * RHO + (rev ? 0 : 3)]);
       __builtin_amdgcn_sched_barrier(0);
     });
-  } else {
+  } else if constexpr (BOUNDED) {
+    int32_t x[4 * ROWS];
     const uint32_t g = g0 + blockIdx.x * 256u + threadIdx.x;
     const uint32_t lowmask = (1u << (q - 2)) - 1u;
     const uint32_t base = ((g & lowmask) << 2) | ((g >> (q - 2)) << (q + F));
@@ -157,11 +165,10 @@ template <int F, bool MIRROR>
 static void launch_global_FM(int32_t* keys, uint32_t n, int q, hipStream_t st) {
   uint32_t full = 0, total = 0;
   global_pass_threads(n, q, F, &full, &total);
-  if (full > 0)  // full is a multiple of 2^(q-2) >= 256
+  if (total == full)  // full is a multiple of 2^(q-2) >= 256
     global_pass_kernel<F, MIRROR, false><<<full / 256, 256, 0, st>>>(keys, n, q, 0u);
-  if (total > full)
-    global_pass_kernel<F, MIRROR, true><<<(total - full + 255) / 256, 256, 0, st>>>(keys, n, q,
-                                                                                  full);
+  else  // one launch: whole blocks unchecked, the straddling block checked
+    global_pass_kernel<F, MIRROR, true><<<(total + 255) / 256, 256, 0, st>>>(keys, n, q, 0u);
 }
 
 template <int F>
