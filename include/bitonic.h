@@ -281,10 +281,10 @@ typedef struct bitonic_plan {
                               choice: by n for the optimized plan, see
                               bitonic_plan_tile_log2; 12 for semi) */
   int fuse;                /* max long-stride steps per HBM pass, 1..10
-                              (0 = library choice, 10); at most 7 are used
-                              when n is not a power of two, at most 8 for
-                              an array off a 16-byte boundary, in phases
-                              above 30, or with lane passes off */
+                              (0 = library choice, 10); at most 8 are used
+                              for an array off a 16-byte boundary, in
+                              phases above 30, or with lane passes off --
+                              at most 7 then when n is not a power of two */
   int merge_blocks_per_cu; /* tile-merge workgroups per compute unit, 1..16,
                               each looping over its tiles with the next
                               tile's loads in flight; -1 = one tile per
